@@ -1,0 +1,175 @@
+/*
+ * wc.h -- C ABI of the MI355X (gfx950) Wilson-clover quark-solver library.
+ *
+ * The library solves D x = b for the O(a)-improved Wilson ("clover") quark
+ * operator of Boku, Ishikawa, Kuramashi and Meadows, arXiv:1709.08785:
+ *
+ *   D(n,m) = F(n) delta(n,m) - kappa H(n,m)                  (Sec. II-A, eq. 3)
+ *   H psi(n) = sum_mu (1 - g_mu) U_mu(n) psi(n+mu)
+ *            + (1 + g_mu) U_mu(n-mu)^dagger psi(n-mu)         (Sec. II-A, eq. 4)
+ *
+ * on a periodic 4-d lattice, through the even-odd (Schur) preconditioned
+ * system D-hat_ee x_e = b-hat_e of Sec. II-B (eqs. 5-9) and the nested
+ * (flexible) BiCGStab of Algorithms 1 and 2: an FP64 outer iteration whose
+ * preconditioner is a low-precision (FP32, or FP16 storage with FP32
+ * arithmetic) inner BiCGStab.
+ *
+ * Conventions (fixed by this library where the paper is silent):
+ *   - gamma matrices in the Dirac representation:
+ *       g_k = [[0, -i s_k], [i s_k, 0]] (k = x, y, z), g_t = diag(1, 1, -1, -1);
+ *   - F(n) = 1 - kappa c_SW sum_{mu<nu} g_mu g_nu (x) Fhat_{mu nu}(n),
+ *     Fhat = (Q - Q^dagger)/8 with Q the sum of the four counter-clockwise
+ *     plaquettes at n (Sheikholeslami-Wohlert clover, no trace subtraction);
+ *   - parity of site (x, y, z, t) is (x + y + z + t) mod 2, even = 0.
+ *
+ * Canonical layouts (device memory, complex128 = two doubles, C order), with
+ * dims = {Lx, Ly, Lz, Lt}:
+ *   links    U[mu][t][z][y][x][i][j], mu = x, y, z, t = 0..3; U_mu(n) is the
+ *            3x3 matrix on the link n -> n + mu-hat;
+ *   spinors  psi[t][z][y][x][alpha][a], spin alpha = 0..3, colour a = 0..2.
+ *
+ * Internal even-odd ("EO") layout: one parity of a spinor field holds V/2
+ * sites, site n = x + Lx (y + Ly (z + Lz t)) stored at index n >> 1 of its
+ * parity, structure-of-arrays.  wc_spinor_bytes() gives the size of one
+ * parity in a given precision; a two-parity EO field stores the even half
+ * first, then the odd half.
+ *
+ * Ownership: every pointer passed in is owned by the caller.  Field pointers
+ * are device pointers unless stated otherwise.  wc_load_links copies the
+ * links into library-owned buffers, so the caller may free U afterwards.
+ * All internal buffers are released by wc_destroy_lattice.
+ *
+ * Streams: every kernel runs on the stream given to wc_create_lattice (0 is
+ * the null stream).  wc_apply_* calls are asynchronous on that stream.
+ * wc_solve and wc_solve_batch return after the solve has finished.
+ *
+ * Errors: every int-returning call returns WC_OK (0) or a negative wc_status.
+ * Arguments are checked on the host before any GPU work (WC_EINVAL).  The
+ * text of the last error of the calling thread is wc_last_error().  A
+ * lattice handle must not be used from two threads at once.
+ */
+#ifndef WC_H
+#define WC_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct wc_lattice wc_lattice;
+
+enum wc_prec { WC_FP64 = 0, WC_FP32 = 1, WC_FP16 = 2 };
+
+enum wc_status {
+    WC_OK = 0,
+    WC_EINVAL = -1,       /* bad argument (odd or zero extent, null pointer, bad enum) */
+    WC_ENOMEM = -2,       /* device allocation failed */
+    WC_EHIP = -3,         /* a HIP runtime call failed; see wc_last_error() */
+    WC_ENOTREADY = -4,    /* no links loaded, or no clover term built */
+    WC_ENOCONV = -5,      /* iteration cap reached before the tolerance */
+    WC_EBREAKDOWN = -6    /* BiCGStab breakdown (zero or non-finite scalar) after restarts */
+};
+
+/* Solver parameters.  wc_solve_params_default() fills the defaults. */
+typedef struct {
+    int inner_prec;       /* WC_FP32 (default) or WC_FP16: storage precision of the inner
+                             BiCGStab of Algorithm 2; WC_FP64 runs one plain FP64 BiCGStab
+                             on D-hat_ee (no inner/outer nesting) */
+    double inner_tol;     /* inner relative residual target (default 1e-6 FP32, 1e-3 FP16) */
+    int inner_maxit;      /* inner iteration cap (default 5000; the iteration cap of WC_FP64) */
+    int outer_maxit;      /* outer iteration cap (default 100) */
+    int fixed_work;       /* >0: run exactly this many inner iterations per inner call, no
+                             convergence test (the fixed-count timing mode of Sec. IV) */
+    int check_every;      /* inner iterations queued between host convergence reads (default 8) */
+} wc_solve_params;
+
+/* What a solve did.  Iteration counts follow Algorithms 1 and 2. */
+typedef struct {
+    int outer_iters;          /* outer (Algorithm 1) iterations, summed over restarts */
+    int inner_iters_total;    /* inner (Algorithm 2) iterations summed over all inner calls */
+    int inner_calls;          /* calls of the inner solver */
+    int restarts;             /* outer restarts from the true residual */
+    long dslash_count;        /* MULT applications (one D-hat_ee = 2 MULTs), any precision */
+    int status;               /* same value as returned */
+    double eo_rel_residual;   /* last recursive ||r_e|| / ||b-hat_e|| of the outer loop */
+    double true_rel_residual; /* ||b - D x|| / ||b|| in FP64 on the full lattice */
+    double seconds;           /* wall time of the solve (host clock, after the final sync) */
+} wc_solve_info;
+
+void wc_solve_params_default(wc_solve_params *p);
+
+/* Create a lattice of extents dims = {Lx, Ly, Lz, Lt}; every extent even and >= 2
+   (the even-odd split of Sec. II-B with periodic wrap needs even extents).
+   stream is a hipStream_t (NULL = null stream).  *out receives the handle. */
+int wc_create_lattice(const int dims[4], void *stream, wc_lattice **out);
+void wc_destroy_lattice(wc_lattice *lat);
+/* Rebind the stream used for all later work on this lattice. */
+int wc_set_stream(wc_lattice *lat, void *stream);
+
+/* Copy gauge links (canonical complex128 layout, device pointer) into the internal
+   FP64, FP32 and FP16 copies.  FP32 and FP16 keep the first two columns of each
+   matrix and rebuild the third as conj(col0 x col1) (SU(3) reconstruction,
+   Sec. III-A); this is exact only for special-unitary links.  Invalidates the
+   clover term. */
+int wc_load_links(wc_lattice *lat, const void *U_dev);
+
+/* Build the clover term F (Sec. II-A) from the loaded links in FP64, split into
+   its two 6x6 Hermitian chiral blocks (Sec. III-A), invert them in FP64, and keep
+   FP64, FP32 and FP16 copies of F and F^-1.  WC_ENOTREADY before wc_load_links. */
+int wc_build_clover(wc_lattice *lat, double kappa, double csw);
+
+/* Bytes of one parity of a spinor field in the internal EO layout of precision prec. */
+size_t wc_spinor_bytes(const wc_lattice *lat, int prec);
+
+/* Canonical complex128 spinor -> two-parity EO field of precision prec (FP16 stores
+   one FP32 scale per site, the largest magnitude of its 24 reals), and back. */
+int wc_pack_spinor(wc_lattice *lat, void *eo_out, const void *canon_in, int prec);
+int wc_unpack_spinor(wc_lattice *lat, void *canon_out, const void *eo_in, int prec);
+
+/* out = D in on the whole lattice (eq. 3); canonical complex128 in and out.  The
+   operator is applied in precision prec (WC_FP64 or WC_FP32) on internal copies. */
+int wc_apply_D(wc_lattice *lat, void *out_dev, const void *in_dev, int prec);
+
+/* MULT of Sec. II-B: out_p = H-tilde_{p,1-p} in_{1-p} = F_pp^-1 H_{p,1-p} in_{1-p}
+   (eq. 9).  in and out are single-parity EO fields of precision prec; out_parity
+   is 0 (even, H-tilde_eo) or 1 (odd, H-tilde_oe). */
+int wc_apply_mult(wc_lattice *lat, void *out, const void *in, int out_parity, int prec);
+
+/* The even-odd preconditioned operator D-hat_ee = 1 - kappa^2 H-tilde_eo H-tilde_oe
+   (eq. 8, read with H-tilde_oe as the second factor) on single-parity EO fields
+   of precision prec: out_e = D-hat_ee in_e.  Uses the kappa of the built clover. */
+int wc_apply_Dee_oo(wc_lattice *lat, void *out_e, const void *in_e, int prec);
+
+/* Site-diagonal clover: out_p = F_pp in_p (inverse = 0) or F_pp^-1 in_p (inverse = 1)
+   on single-parity EO fields of precision prec. */
+int wc_apply_clover(wc_lattice *lat, void *out, const void *in, int parity, int inverse, int prec);
+
+/* Solve D x = b (eq. 1) for canonical complex128 b, x (device pointers) with the
+   nested BiCGStab of Algorithms 1 and 2 on the even-odd system (eqs. 5-9), until
+   the true relative residual ||b - D x|| / ||b|| (FP64, full lattice) is below tol.
+   Rebuilds the clover when (kappa, csw) differ from the built pair.  p may be NULL
+   (defaults).  x is also the initial guess when x0_is_guess != 0 (else ignored).
+   info may be NULL.  Returns WC_ENOCONV with the best iterate in x when the caps
+   are reached. */
+int wc_solve(wc_lattice *lat, const void *b_dev, double kappa, double csw, double tol,
+             const wc_solve_params *p, void *x_dev, int x0_is_guess, wc_solve_info *info);
+
+/* Per-kernel timing with HIP events on the lattice's stream.  While enabled, every
+   launch of the hot kernels is bracketed by an event pair; wc_kernel_stats()
+   synchronises and reports, for kernel slot k (0 <= k < wc_kernel_slots()), its
+   name, launch count, total milliseconds and total algorithmic bytes. */
+int wc_set_timing(wc_lattice *lat, int enable);
+int wc_kernel_slots(void);
+int wc_kernel_stats(wc_lattice *lat, int slot, const char **name, long *launches,
+                    double *total_ms, double *total_bytes);
+int wc_reset_kernel_stats(wc_lattice *lat);
+
+/* Text of the last error on the calling thread ("" if none). */
+const char *wc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WC_H */

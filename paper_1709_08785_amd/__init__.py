@@ -1,0 +1,250 @@
+"""Python binding of the gfx950 Wilson-clover quark-solver library (libwc.so).
+
+Argument marshalling only: every step of the operator and the solvers runs in
+the library's HIP kernels.  torch supplies device memory and the stream.  The
+binding refuses to work when the built library is missing; there is no CPU
+path.
+
+Fields are torch tensors on the GPU in the canonical layouts of ``include/wc.h``:
+links ``complex128 (4, Lt, Lz, Ly, Lx, 3, 3)``, spinors
+``complex128 (Lt, Lz, Ly, Lx, 4, 3)``.  Even-odd (EO) fields are opaque byte
+tensors (``uint8``) in the library's structure-of-arrays layout.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+__all__ = ["Lattice", "SolveParams", "FP64", "FP32", "FP16", "WCError", "library_path", "load_library"]
+
+FP64, FP32, FP16 = 0, 1, 2
+_PREC_NAMES = {"fp64": FP64, "fp32": FP32, "fp16": FP16}
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIBPATH = os.path.join(_HERE, "libwc.so")
+_lib = None
+
+STATUS = {0: "WC_OK", -1: "WC_EINVAL", -2: "WC_ENOMEM", -3: "WC_EHIP", -4: "WC_ENOTREADY",
+          -5: "WC_ENOCONV", -6: "WC_EBREAKDOWN"}
+
+
+class WCError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (STATUS.get(code, "?"), code, msg))
+        self.code = code
+
+
+class SolveParams(ctypes.Structure):
+    _fields_ = [("inner_prec", ctypes.c_int), ("inner_tol", ctypes.c_double), ("inner_maxit", ctypes.c_int),
+                ("outer_maxit", ctypes.c_int), ("fixed_work", ctypes.c_int), ("check_every", ctypes.c_int)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("outer_iters", ctypes.c_int), ("inner_iters_total", ctypes.c_int), ("inner_calls", ctypes.c_int),
+                ("restarts", ctypes.c_int), ("dslash_count", ctypes.c_long), ("status", ctypes.c_int),
+                ("eo_rel_residual", ctypes.c_double), ("true_rel_residual", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def library_path() -> str:
+    return _LIBPATH
+
+
+def load_library():
+    """Load libwc.so (built by paper_1709_08785_amd/build.py); raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIBPATH):
+        raise ImportError("libwc.so is not built: run `python paper_1709_08785_amd/build.py` "
+                          "(or __graft_entry__.build()) first")
+    lib = ctypes.CDLL(_LIBPATH)
+    P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    sig = {
+        "wc_solve_params_default": (None, [ctypes.POINTER(SolveParams)]),
+        "wc_create_lattice": (I, [ctypes.POINTER(ctypes.c_int), P, ctypes.POINTER(P)]),
+        "wc_destroy_lattice": (None, [P]),
+        "wc_set_stream": (I, [P, P]),
+        "wc_load_links": (I, [P, P]),
+        "wc_build_clover": (I, [P, D, D]),
+        "wc_spinor_bytes": (ctypes.c_size_t, [P, I]),
+        "wc_pack_spinor": (I, [P, P, P, I]),
+        "wc_unpack_spinor": (I, [P, P, P, I]),
+        "wc_apply_D": (I, [P, P, P, I]),
+        "wc_apply_mult": (I, [P, P, P, I, I]),
+        "wc_apply_Dee_oo": (I, [P, P, P, I]),
+        "wc_apply_clover": (I, [P, P, P, I, I, I]),
+        "wc_solve": (I, [P, P, D, D, D, ctypes.POINTER(SolveParams), P, I, ctypes.POINTER(SolveInfo)]),
+        "wc_set_timing": (I, [P, I]),
+        "wc_kernel_slots": (I, []),
+        "wc_kernel_stats": (I, [P, I, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_long),
+                                ctypes.POINTER(D), ctypes.POINTER(D)]),
+        "wc_reset_kernel_stats": (I, [P]),
+        "wc_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise WCError(rc, _lib.wc_last_error().decode())
+
+
+def _prec(p):
+    if isinstance(p, str):
+        return _PREC_NAMES[p.lower()]
+    return int(p)
+
+
+def _ptr(t: torch.Tensor):
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Lattice:
+    """A lattice of extents dims = (Lx, Ly, Lz, Lt) with its links and clover term on the GPU."""
+
+    def __init__(self, dims, device=None):
+        self.lib = load_library()
+        self.dims = tuple(int(d) for d in dims)
+        self.device = torch.device("cuda") if device is None else torch.device(device)
+        arr = (ctypes.c_int * 4)(*self.dims)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(self.lib.wc_create_lattice(arr, self._stream(), ctypes.byref(h)))
+        self.h = h
+        lx, ly, lz, lt = self.dims
+        self.volume = lx * ly * lz * lt
+        self.spinor_shape = (lt, lz, ly, lx, 4, 3)
+        self.link_shape = (4, lt, lz, ly, lx, 3, 3)
+
+    def _stream(self):
+        return ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def _sync_stream(self):
+        _check(self.lib.wc_set_stream(self.h, self._stream()))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.wc_destroy_lattice(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- set-up -------------------------------------------------------------
+    def load_links(self, U: torch.Tensor):
+        assert U.dtype == torch.complex128 and tuple(U.shape) == self.link_shape
+        self._sync_stream()
+        _check(self.lib.wc_load_links(self.h, _ptr(U)))
+
+    def build_clover(self, kappa: float, csw: float):
+        self._sync_stream()
+        _check(self.lib.wc_build_clover(self.h, float(kappa), float(csw)))
+
+    # ---- EO fields -----------------------------------------------------------
+    def spinor_bytes(self, prec) -> int:
+        return int(self.lib.wc_spinor_bytes(self.h, _prec(prec)))
+
+    def new_eo(self, prec, parities: int = 1) -> torch.Tensor:
+        return torch.zeros(parities * self.spinor_bytes(prec), dtype=torch.uint8, device=self.device)
+
+    def pack(self, psi: torch.Tensor, prec) -> torch.Tensor:
+        assert psi.dtype == torch.complex128 and tuple(psi.shape) == self.spinor_shape
+        out = self.new_eo(prec, 2)
+        self._sync_stream()
+        _check(self.lib.wc_pack_spinor(self.h, _ptr(out), _ptr(psi), _prec(prec)))
+        return out
+
+    def unpack(self, eo: torch.Tensor, prec) -> torch.Tensor:
+        assert eo.numel() == 2 * self.spinor_bytes(prec)
+        out = torch.empty(self.spinor_shape, dtype=torch.complex128, device=self.device)
+        self._sync_stream()
+        _check(self.lib.wc_unpack_spinor(self.h, _ptr(out), _ptr(eo), _prec(prec)))
+        return out
+
+    def parity_view(self, eo: torch.Tensor, parity: int, prec) -> torch.Tensor:
+        sb = self.spinor_bytes(prec)
+        return eo[parity * sb:(parity + 1) * sb]
+
+    # ---- operators -------------------------------------------------------------
+    def apply_D(self, psi: torch.Tensor, prec=FP64) -> torch.Tensor:
+        assert psi.dtype == torch.complex128 and tuple(psi.shape) == self.spinor_shape
+        out = torch.empty_like(psi)
+        self._sync_stream()
+        _check(self.lib.wc_apply_D(self.h, _ptr(out), _ptr(psi), _prec(prec)))
+        return out
+
+    def apply_mult(self, out: torch.Tensor, inp: torch.Tensor, out_parity: int, prec):
+        self._sync_stream()
+        _check(self.lib.wc_apply_mult(self.h, _ptr(out), _ptr(inp), int(out_parity), _prec(prec)))
+
+    def apply_Dee_oo(self, out_e: torch.Tensor, in_e: torch.Tensor, prec):
+        self._sync_stream()
+        _check(self.lib.wc_apply_Dee_oo(self.h, _ptr(out_e), _ptr(in_e), _prec(prec)))
+
+    def apply_clover(self, out: torch.Tensor, inp: torch.Tensor, parity: int, inverse: bool, prec):
+        self._sync_stream()
+        _check(self.lib.wc_apply_clover(self.h, _ptr(out), _ptr(inp), int(parity), int(bool(inverse)),
+                                        _prec(prec)))
+
+    # ---- solve -------------------------------------------------------------------
+    @staticmethod
+    def default_params(**kw) -> SolveParams:
+        p = SolveParams()
+        load_library().wc_solve_params_default(ctypes.byref(p))
+        for k, v in kw.items():
+            if k == "inner_prec":
+                v = _prec(v)
+            setattr(p, k, v)
+        return p
+
+    def solve(self, b: torch.Tensor, kappa: float, csw: float, tol: float, x0: torch.Tensor = None,
+              raise_on_error: bool = True, **params):
+        """x = D^-1 b; returns (x, info dict).  params go into wc_solve_params."""
+        assert b.dtype == torch.complex128 and tuple(b.shape) == self.spinor_shape
+        p = self.default_params(**params)
+        info = SolveInfo()
+        x = torch.empty_like(b) if x0 is None else x0.clone()
+        self._sync_stream()
+        rc = self.lib.wc_solve(self.h, _ptr(b), float(kappa), float(csw), float(tol), ctypes.byref(p), _ptr(x),
+                               0 if x0 is None else 1, ctypes.byref(info))
+        if rc != 0 and raise_on_error:
+            _check(rc)
+        d = info.as_dict()
+        d["rc"] = rc
+        return x, d
+
+    # ---- timing --------------------------------------------------------------------
+    def set_timing(self, on: bool):
+        _check(self.lib.wc_set_timing(self.h, int(bool(on))))
+
+    def reset_kernel_stats(self):
+        _check(self.lib.wc_reset_kernel_stats(self.h))
+
+    def kernel_stats(self):
+        out = {}
+        for s in range(self.lib.wc_kernel_slots()):
+            name = ctypes.c_char_p()
+            n = ctypes.c_long()
+            ms = ctypes.c_double()
+            by = ctypes.c_double()
+            _check(self.lib.wc_kernel_stats(self.h, s, ctypes.byref(name), ctypes.byref(n), ctypes.byref(ms),
+                                            ctypes.byref(by)))
+            out[name.value.decode()] = {"launches": n.value, "ms": ms.value, "bytes": by.value}
+        return out

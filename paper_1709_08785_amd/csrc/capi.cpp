@@ -1,0 +1,367 @@
+// The C ABI of include/wc.h: argument checks, lattice lifetime, operator
+// applications and the per-kernel event timing.  Solvers live in solver.cpp.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <string>
+
+#include "internal.hpp"
+#include "work.hpp"
+
+static thread_local std::string g_last_error;
+
+int wc_fail(int code, const std::string &msg) {
+    g_last_error = msg;
+    return code;
+}
+
+extern "C" const char *wc_last_error(void) { return g_last_error.c_str(); }
+
+// ---------------------------------------------------------------------------
+// work buffers
+// ---------------------------------------------------------------------------
+int work_get(wc_lattice *lat, int id, size_t bytes, void **out) {
+    if (lat->work[id] && lat->work_bytes[id] >= bytes) {
+        *out = lat->work[id];
+        return WC_OK;
+    }
+    if (lat->work[id]) {
+        WC_HIP(hipStreamSynchronize(lat->stream));
+        WC_HIP(hipFree(lat->work[id]));
+        lat->work[id] = nullptr;
+        lat->work_bytes[id] = 0;
+    }
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return wc_fail(WC_ENOMEM, "work buffer allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+    lat->work[id] = p;
+    lat->work_bytes[id] = bytes;
+    *out = p;
+    return WC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// timing
+// ---------------------------------------------------------------------------
+static hipEvent_t take_event(wc_lattice *lat) {
+    if (!lat->event_pool.empty()) {
+        hipEvent_t e = lat->event_pool.back();
+        lat->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+void timing_begin(wc_lattice *lat, int slot, double bytes, TimedLaunch &t) {
+    t.slot = slot;
+    t.bytes = bytes;
+    t.a = take_event(lat);
+    t.b = take_event(lat);
+    if (t.a) (void)hipEventRecord(t.a, lat->stream);
+}
+
+void timing_end(wc_lattice *lat, TimedLaunch &t) {
+    if (t.b) (void)hipEventRecord(t.b, lat->stream);
+    if (t.a && t.b) lat->launches.push_back(t);
+}
+
+static const char *kSlotNames[KS_COUNT] = {
+    "mult_hopinv_fp64", "mult_hopinv_fp32", "mult_hopinv_fp16", "mult_dhat_fp64",
+    "mult_dhat_fp32",   "mult_dhat_fp16",   "mult_other",       "blas",
+};
+
+struct SlotStats {
+    long n = 0;
+    double ms = 0, bytes = 0;
+};
+
+static int collect_stats(wc_lattice *lat, SlotStats *st) {
+    WC_HIP(hipStreamSynchronize(lat->stream));
+    for (auto &t : lat->launches) {
+        float ms = 0.f;
+        WC_HIP(hipEventElapsedTime(&ms, t.a, t.b));
+        st[t.slot].n++;
+        st[t.slot].ms += ms;
+        st[t.slot].bytes += t.bytes;
+    }
+    return WC_OK;
+}
+
+extern "C" int wc_set_timing(wc_lattice *lat, int enable) {
+    if (!lat) return wc_fail(WC_EINVAL, "null lattice");
+    lat->timing = enable != 0;
+    return WC_OK;
+}
+
+extern "C" int wc_kernel_slots(void) { return KS_COUNT; }
+
+extern "C" int wc_kernel_stats(wc_lattice *lat, int slot, const char **name, long *launches, double *total_ms,
+                               double *total_bytes) {
+    if (!lat || slot < 0 || slot >= KS_COUNT) return wc_fail(WC_EINVAL, "bad lattice or slot");
+    SlotStats st[KS_COUNT];
+    int rc = collect_stats(lat, st);
+    if (rc) return rc;
+    if (name) *name = kSlotNames[slot];
+    if (launches) *launches = st[slot].n;
+    if (total_ms) *total_ms = st[slot].ms;
+    if (total_bytes) *total_bytes = st[slot].bytes;
+    return WC_OK;
+}
+
+extern "C" int wc_reset_kernel_stats(wc_lattice *lat) {
+    if (!lat) return wc_fail(WC_EINVAL, "null lattice");
+    WC_HIP(hipStreamSynchronize(lat->stream));
+    for (auto &t : lat->launches) {
+        lat->event_pool.push_back(t.a);
+        lat->event_pool.push_back(t.b);
+    }
+    lat->launches.clear();
+    return WC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// lattice lifetime
+// ---------------------------------------------------------------------------
+static void free_all(wc_lattice *lat) {
+    for (int p = 0; p < 3; p++) {
+        if (lat->links[p]) (void)hipFree(lat->links[p]);
+        if (lat->clov[p]) (void)hipFree(lat->clov[p]);
+        if (lat->clovinv[p]) (void)hipFree(lat->clovinv[p]);
+    }
+    for (int k = 0; k < 32; k++)
+        if (lat->work[k]) (void)hipFree(lat->work[k]);
+    if (lat->partials) (void)hipFree(lat->partials);
+    if (lat->counter) (void)hipFree(lat->counter);
+    if (lat->scalars) (void)hipFree(lat->scalars);
+    if (lat->flags) (void)hipFree(lat->flags);
+    if (lat->host_scalars) (void)hipHostFree(lat->host_scalars);
+    if (lat->host_flags) (void)hipHostFree(lat->host_flags);
+    for (auto &t : lat->launches) {
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    for (auto e : lat->event_pool) (void)hipEventDestroy(e);
+}
+
+static int dev_alloc(void **p, size_t bytes) {
+    if (hipMalloc(p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return wc_fail(WC_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+    return WC_OK;
+}
+
+extern "C" int wc_create_lattice(const int dims[4], void *stream, wc_lattice **out) {
+    if (!dims || !out) return wc_fail(WC_EINVAL, "null dims or out pointer");
+    *out = nullptr;
+    long V = 1;
+    for (int d = 0; d < 4; d++) {
+        if (dims[d] < 2 || (dims[d] & 1))
+            return wc_fail(WC_EINVAL, "every lattice extent must be even and >= 2 (got " + std::to_string(dims[d]) +
+                                          " in direction " + std::to_string(d) + ")");
+        V *= dims[d];
+    }
+    if (V / 2 > (1L << 30)) return wc_fail(WC_EINVAL, "lattice too large (V/2 must fit in 30 bits)");
+    wc_lattice *lat = new wc_lattice();
+    for (int d = 0; d < 4; d++) {
+        lat->dims[d] = dims[d];
+        lat->g.L[d] = dims[d];
+    }
+    lat->V = V;
+    lat->Vh = (int)(V / 2);
+    lat->g.Lxh = dims[0] / 2;
+    lat->g.Vh = lat->Vh;
+    lat->stream = (hipStream_t)stream;
+    lat->max_blocks = (lat->Vh + 255) / 256;
+    int rc = WC_OK;
+    if ((rc = dev_alloc((void **)&lat->partials, sizeof(double) * 8 * (size_t)lat->max_blocks)) ||
+        (rc = dev_alloc((void **)&lat->counter, 256)) ||
+        (rc = dev_alloc((void **)&lat->scalars, sizeof(double) * NUM_LEVELS * S_COUNT)) ||
+        (rc = dev_alloc((void **)&lat->flags, sizeof(int) * NUM_LEVELS * F_COUNT))) {
+        free_all(lat);
+        delete lat;
+        return rc;
+    }
+    if (hipHostMalloc((void **)&lat->host_scalars, sizeof(double) * NUM_LEVELS * S_COUNT, hipHostMallocDefault) !=
+            hipSuccess ||
+        hipHostMalloc((void **)&lat->host_flags, sizeof(int) * NUM_LEVELS * F_COUNT, hipHostMallocDefault) !=
+            hipSuccess) {
+        (void)hipGetLastError();
+        free_all(lat);
+        delete lat;
+        return wc_fail(WC_ENOMEM, "pinned host allocation failed");
+    }
+    if (hipMemsetAsync(lat->counter, 0, 256, lat->stream) != hipSuccess ||
+        hipMemsetAsync(lat->scalars, 0, sizeof(double) * NUM_LEVELS * S_COUNT, lat->stream) != hipSuccess ||
+        hipMemsetAsync(lat->flags, 0, sizeof(int) * NUM_LEVELS * F_COUNT, lat->stream) != hipSuccess ||
+        hipStreamSynchronize(lat->stream) != hipSuccess) {
+        std::string m = hipGetErrorString(hipGetLastError());
+        free_all(lat);
+        delete lat;
+        return wc_fail(WC_EHIP, "initialising lattice scratch: " + m);
+    }
+    *out = lat;
+    return WC_OK;
+}
+
+extern "C" void wc_destroy_lattice(wc_lattice *lat) {
+    if (!lat) return;
+    (void)hipStreamSynchronize(lat->stream);
+    free_all(lat);
+    delete lat;
+}
+
+extern "C" int wc_set_stream(wc_lattice *lat, void *stream) {
+    if (!lat) return wc_fail(WC_EINVAL, "null lattice");
+    lat->stream = (hipStream_t)stream;
+    return WC_OK;
+}
+
+extern "C" void wc_solve_params_default(wc_solve_params *p) {
+    if (!p) return;
+    p->inner_prec = WC_FP32;
+    p->inner_tol = 0.0;  // 0 = default of the precision
+    p->inner_maxit = 5000;
+    p->outer_maxit = 100;
+    p->fixed_work = 0;
+    p->check_every = 8;
+}
+
+extern "C" size_t wc_spinor_bytes(const wc_lattice *lat, int prec) {
+    if (!lat || prec < 0 || prec > 2) return 0;
+    return spinor_bytes(prec, lat->Vh);
+}
+
+extern "C" int wc_load_links(wc_lattice *lat, const void *U_dev) {
+    if (!lat || !U_dev) return wc_fail(WC_EINVAL, "null lattice or link pointer");
+    for (int p = 0; p < 3; p++) {
+        if (!lat->links[p]) {
+            int rc = dev_alloc(&lat->links[p], 8 * link_slab_bytes(p, lat->Vh));
+            if (rc) return rc;
+        }
+    }
+    int rc = launch_load_links(lat, U_dev);
+    if (rc) return rc;
+    lat->have_links = true;
+    lat->have_clover = false;
+    return WC_OK;
+}
+
+extern "C" int wc_build_clover(wc_lattice *lat, double kappa, double csw) {
+    if (!lat) return wc_fail(WC_EINVAL, "null lattice");
+    if (!lat->have_links) return wc_fail(WC_ENOTREADY, "wc_build_clover before wc_load_links");
+    if (!(kappa >= 0.0) || !(csw >= 0.0) || kappa * csw * 6.0 >= 1.0)
+        return wc_fail(WC_EINVAL, "need kappa >= 0, csw >= 0 and 6 kappa csw < 1 (F positive definite)");
+    for (int p = 0; p < 3; p++) {
+        if (!lat->clov[p]) {
+            int rc = dev_alloc(&lat->clov[p], 2 * clover_slab_bytes(p, lat->Vh));
+            if (rc) return rc;
+        }
+        if (!lat->clovinv[p]) {
+            int rc = dev_alloc(&lat->clovinv[p], 2 * clover_slab_bytes(p, lat->Vh));
+            if (rc) return rc;
+        }
+    }
+    int rc = launch_build_clover(lat, kappa, csw);
+    if (rc) return rc;
+    lat->kappa = kappa;
+    lat->csw = csw;
+    lat->have_clover = true;
+    return WC_OK;
+}
+
+static int check_prec(int prec) {
+    if (prec < 0 || prec > 2) return wc_fail(WC_EINVAL, "precision must be WC_FP64, WC_FP32 or WC_FP16");
+    return WC_OK;
+}
+
+static int check_ready(const wc_lattice *lat) {
+    if (!lat->have_links) return wc_fail(WC_ENOTREADY, "no links loaded");
+    if (!lat->have_clover) return wc_fail(WC_ENOTREADY, "no clover term built");
+    return WC_OK;
+}
+
+extern "C" int wc_pack_spinor(wc_lattice *lat, void *eo_out, const void *canon_in, int prec) {
+    if (!lat || !eo_out || !canon_in) return wc_fail(WC_EINVAL, "null argument");
+    if (int rc = check_prec(prec)) return rc;
+    return launch_pack_spinor(lat, prec, eo_out, canon_in);
+}
+
+extern "C" int wc_unpack_spinor(wc_lattice *lat, void *canon_out, const void *eo_in, int prec) {
+    if (!lat || !canon_out || !eo_in) return wc_fail(WC_EINVAL, "null argument");
+    if (int rc = check_prec(prec)) return rc;
+    return launch_unpack_spinor(lat, prec, canon_out, eo_in);
+}
+
+static MultCall mult_call(int prec, int mode, int out_par, void *out, const void *in, const void *center,
+                          double coef) {
+    MultCall c;
+    std::memset(&c, 0, sizeof(c));
+    c.prec = prec;
+    c.mode = mode;
+    c.red = R_NONE;
+    c.out_par = out_par;
+    c.out = out;
+    c.in = in;
+    c.center = center;
+    c.aux = nullptr;
+    c.coef = coef;
+    c.inverse = false;
+    c.done = nullptr;
+    return c;
+}
+
+extern "C" int wc_apply_D(wc_lattice *lat, void *out_dev, const void *in_dev, int prec) {
+    if (!lat || !out_dev || !in_dev) return wc_fail(WC_EINVAL, "null argument");
+    if (int rc = check_prec(prec)) return rc;
+    if (prec == WC_FP16) return wc_fail(WC_EINVAL, "wc_apply_D supports WC_FP64 and WC_FP32");
+    if (int rc = check_ready(lat)) return rc;
+    const size_t sb = spinor_bytes(prec, lat->Vh);
+    void *in2, *out2;
+    if (int rc = work_get(lat, W_APPLY_IN, 2 * sb, &in2)) return rc;
+    if (int rc = work_get(lat, W_APPLY_OUT, 2 * sb, &out2)) return rc;
+    if (int rc = launch_pack_spinor(lat, prec, in2, in_dev)) return rc;
+    for (int par = 0; par < 2; par++) {
+        MultCall c = mult_call(prec, M_DFULL, par, (char *)out2 + par * sb, (const char *)in2 + (1 - par) * sb,
+                               (const char *)in2 + par * sb, -lat->kappa);
+        if (int rc = launch_mult(lat, c)) return rc;
+    }
+    return launch_unpack_spinor(lat, prec, out_dev, out2);
+}
+
+extern "C" int wc_apply_mult(wc_lattice *lat, void *out, const void *in, int out_parity, int prec) {
+    if (!lat || !out || !in) return wc_fail(WC_EINVAL, "null argument");
+    if (int rc = check_prec(prec)) return rc;
+    if (out_parity != 0 && out_parity != 1) return wc_fail(WC_EINVAL, "out_parity must be 0 or 1");
+    if (int rc = check_ready(lat)) return rc;
+    MultCall c = mult_call(prec, M_HOPINV, out_parity, out, in, nullptr, 0.0);
+    return launch_mult(lat, c);
+}
+
+extern "C" int wc_apply_Dee_oo(wc_lattice *lat, void *out_e, const void *in_e, int prec) {
+    if (!lat || !out_e || !in_e) return wc_fail(WC_EINVAL, "null argument");
+    if (int rc = check_prec(prec)) return rc;
+    if (out_e == in_e) return wc_fail(WC_EINVAL, "wc_apply_Dee_oo cannot work in place");
+    if (int rc = check_ready(lat)) return rc;
+    void *tmp;
+    if (int rc = work_get(lat, W_APPLY_TMP, spinor_bytes(prec, lat->Vh), &tmp)) return rc;
+    MultCall c1 = mult_call(prec, M_HOPINV, 1, tmp, in_e, nullptr, 0.0);
+    if (int rc = launch_mult(lat, c1)) return rc;
+    MultCall c2 = mult_call(prec, M_DHAT, 0, out_e, tmp, in_e, -lat->kappa * lat->kappa);
+    return launch_mult(lat, c2);
+}
+
+extern "C" int wc_apply_clover(wc_lattice *lat, void *out, const void *in, int parity, int inverse, int prec) {
+    if (!lat || !out || !in) return wc_fail(WC_EINVAL, "null argument");
+    if (int rc = check_prec(prec)) return rc;
+    if (parity != 0 && parity != 1) return wc_fail(WC_EINVAL, "parity must be 0 or 1");
+    if (int rc = check_ready(lat)) return rc;
+    MultCall c = mult_call(prec, M_CLOV, parity, out, nullptr, in, 0.0);
+    c.inverse = inverse != 0;
+    return launch_mult(lat, c);
+}

@@ -1,0 +1,459 @@
+// Device-side building blocks shared by the gfx950 kernels: complex arithmetic,
+// even-odd geometry, and the structure-of-arrays accessors of each storage
+// precision.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+#define WC_HD __host__ __device__ __forceinline__
+
+// ---------------------------------------------------------------------------
+// complex numbers
+// ---------------------------------------------------------------------------
+template <class R> struct cx {
+    R re, im;
+};
+
+template <class R> WC_HD cx<R> mk(R a, R b) { return cx<R>{a, b}; }
+template <class R> WC_HD cx<R> operator+(cx<R> a, cx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <class R> WC_HD cx<R> operator-(cx<R> a, cx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <class R> WC_HD cx<R> operator-(cx<R> a) { return {-a.re, -a.im}; }
+template <class R> WC_HD cx<R> operator*(cx<R> a, cx<R> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <class R> WC_HD cx<R> operator*(R s, cx<R> a) { return {s * a.re, s * a.im}; }
+template <class R> WC_HD cx<R> conjx(cx<R> a) { return {a.re, -a.im}; }
+// conj(a) * b
+template <class R> WC_HD cx<R> cmulc(cx<R> a, cx<R> b) {
+    return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+// i * a, -i * a
+template <class R> WC_HD cx<R> mul_i(cx<R> a) { return {-a.im, a.re}; }
+template <class R> WC_HD cx<R> mul_mi(cx<R> a) { return {a.im, -a.re}; }
+// acc += a * b
+template <class R> WC_HD void cmac(cx<R> &acc, cx<R> a, cx<R> b) {
+    acc.re += a.re * b.re - a.im * b.im;
+    acc.im += a.re * b.im + a.im * b.re;
+}
+// acc += conj(a) * b
+template <class R> WC_HD void cmacc(cx<R> &acc, cx<R> a, cx<R> b) {
+    acc.re += a.re * b.re + a.im * b.im;
+    acc.im += a.re * b.im - a.im * b.re;
+}
+template <class R> WC_HD R norm2(cx<R> a) { return a.re * a.re + a.im * a.im; }
+
+// ---------------------------------------------------------------------------
+// even-odd geometry
+//   site n = x + Lx (y + Ly (z + Lz t)), parity (x+y+z+t)&1, EO index n >> 1.
+//   All extents are even, so each x-row holds Lx/2 sites of each parity and
+//   EO index i of parity p decodes as xh = i % (Lx/2), row = i / (Lx/2).
+// ---------------------------------------------------------------------------
+struct Geom {
+    int L[4];      // Lx, Ly, Lz, Lt
+    int Lxh;       // Lx / 2
+    int Vh;        // sites per parity
+};
+
+struct SiteCoord {
+    int x, y, z, t, row;  // row = y + Ly (z + Lz t)
+};
+
+WC_HD SiteCoord eo_coords(const Geom &g, int i, int parity) {
+    SiteCoord c;
+    int xh = i % g.Lxh;
+    c.row = i / g.Lxh;
+    c.y = c.row % g.L[1];
+    int r2 = c.row / g.L[1];
+    c.z = r2 % g.L[2];
+    c.t = r2 / g.L[2];
+    c.x = 2 * xh + ((parity + c.y + c.z + c.t) & 1);
+    return c;
+}
+
+// EO index (within the opposite parity) of the neighbour n + s mu-hat, s = +-1
+WC_HD int eo_neighbour(const Geom &g, const SiteCoord &c, int mu, int s) {
+    if (mu == 0) {
+        int x = c.x + s;
+        x = (x == g.L[0]) ? 0 : (x < 0 ? g.L[0] - 1 : x);
+        return (x >> 1) + g.Lxh * c.row;
+    }
+    int row;
+    if (mu == 1) {
+        int y = c.y + s;
+        y = (y == g.L[1]) ? 0 : (y < 0 ? g.L[1] - 1 : y);
+        row = c.row + (y - c.y);
+    } else if (mu == 2) {
+        int z = c.z + s;
+        z = (z == g.L[2]) ? 0 : (z < 0 ? g.L[2] - 1 : z);
+        row = c.row + (z - c.z) * g.L[1];
+    } else {
+        int t = c.t + s;
+        t = (t == g.L[3]) ? 0 : (t < 0 ? g.L[3] - 1 : t);
+        row = c.row + (t - c.t) * g.L[1] * g.L[2];
+    }
+    return (c.x >> 1) + g.Lxh * row;
+}
+
+// ---------------------------------------------------------------------------
+// storage precisions
+//   spinor  (12 complex per site)
+//     FP64: 12 planes of double2
+//     FP32:  6 planes of float4 (two complex per plane)
+//     FP16:  3 planes of uint4 (eight halves = four complex per plane) plus a
+//            float scale per site; value = scale * half
+//   links (one (mu, parity) slab = Vh matrices)
+//     FP64: 9 planes of double2, row-major U[i][j]
+//     FP32: 3 planes of float4: columns 0 and 1 (U00 U10 | U20 U01 | U11 U21);
+//           column 2 = conj(col0 x col1)
+//     FP16: the same six complex as halves: 1 uint4 + 1 uint2 plane
+//   clover (two Hermitian 6x6 blocks per site, each 6 real diagonal entries
+//           then the 15 complex entries above the diagonal, row by row)
+//     FP64: 36 planes of double2
+//     FP32: 18 planes of float4
+//     FP16:  9 planes of uint4 plus a float scale per site
+// ---------------------------------------------------------------------------
+enum { P64 = 0, P32 = 1, P16 = 2 };
+
+template <int P> struct Real;
+template <> struct Real<P64> { using T = double; };
+template <> struct Real<P32> { using T = float; };
+template <> struct Real<P16> { using T = float; };
+
+// bytes of one parity-slab of each field kind
+WC_HD size_t spinor_bytes(int prec, int Vh) {
+    return prec == P64 ? (size_t)Vh * 192 : prec == P32 ? (size_t)Vh * 96 : (size_t)Vh * 52;
+}
+WC_HD size_t link_slab_bytes(int prec, int Vh) {
+    return prec == P64 ? (size_t)Vh * 144 : prec == P32 ? (size_t)Vh * 48 : (size_t)Vh * 24;
+}
+WC_HD size_t clover_slab_bytes(int prec, int Vh) {
+    return prec == P64 ? (size_t)Vh * 576 : prec == P32 ? (size_t)Vh * 288 : (size_t)Vh * 148;
+}
+
+template <class R> struct Spinor {
+    cx<R> c[12];  // index 3*alpha + colour
+};
+
+// ---- non-temporal loads: streamed operands that are read exactly once ----
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+typedef unsigned int nt_u4 __attribute__((ext_vector_type(4)));
+typedef unsigned int nt_u2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float4 ld_stream(const float4 *p) {
+    nt_f4 v = __builtin_nontemporal_load((const nt_f4 *)p);
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ double2 ld_stream(const double2 *p) {
+    nt_d2 v = __builtin_nontemporal_load((const nt_d2 *)p);
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ uint4 ld_stream(const uint4 *p) {
+    nt_u4 v = __builtin_nontemporal_load((const nt_u4 *)p);
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ uint2 ld_stream(const uint2 *p) {
+    nt_u2 v = __builtin_nontemporal_load((const nt_u2 *)p);
+    return make_uint2(v.x, v.y);
+}
+
+// ---- half <-> float ----
+__device__ __forceinline__ float2 h2f(uint32_t u) {
+    __half2 h = *reinterpret_cast<__half2 *>(&u);
+    return __half22float2(h);
+}
+__device__ __forceinline__ uint32_t f2h(float a, float b) {
+    __half2 h = __floats2half2_rn(a, b);
+    return *reinterpret_cast<uint32_t *>(&h);
+}
+
+// ---------------------------------------------------------------------------
+// spinor load / store (one parity slab: base pointer, stride Vh)
+// ---------------------------------------------------------------------------
+template <int P> struct SpinorIO;
+
+template <> struct SpinorIO<P64> {
+    using R = double;
+    __device__ static Spinor<R> load(const void *base, int Vh, int i) {
+        const double2 *p = (const double2 *)base;
+        Spinor<R> s;
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            double2 v = p[(size_t)k * Vh + i];
+            s.c[k] = {v.x, v.y};
+        }
+        return s;
+    }
+    __device__ static void store(void *base, int Vh, int i, const Spinor<R> &s) {
+        double2 *p = (double2 *)base;
+#pragma unroll
+        for (int k = 0; k < 12; k++) p[(size_t)k * Vh + i] = make_double2(s.c[k].re, s.c[k].im);
+    }
+};
+
+template <> struct SpinorIO<P32> {
+    using R = float;
+    __device__ static Spinor<R> load(const void *base, int Vh, int i) {
+        const float4 *p = (const float4 *)base;
+        Spinor<R> s;
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            float4 v = p[(size_t)k * Vh + i];
+            s.c[2 * k] = {v.x, v.y};
+            s.c[2 * k + 1] = {v.z, v.w};
+        }
+        return s;
+    }
+    __device__ static void store(void *base, int Vh, int i, const Spinor<R> &s) {
+        float4 *p = (float4 *)base;
+#pragma unroll
+        for (int k = 0; k < 6; k++)
+            p[(size_t)k * Vh + i] = make_float4(s.c[2 * k].re, s.c[2 * k].im, s.c[2 * k + 1].re, s.c[2 * k + 1].im);
+    }
+};
+
+// FP16 storage: planes of uint4 (3 * 16 B) followed by a float scale plane
+template <> struct SpinorIO<P16> {
+    using R = float;
+    __device__ static Spinor<R> load(const void *base, int Vh, int i) {
+        const uint4 *p = (const uint4 *)base;
+        const float *sc = (const float *)((const char *)base + (size_t)Vh * 48);
+        float s = sc[i];
+        Spinor<R> out;
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            uint4 v = p[(size_t)k * Vh + i];
+            float2 a = h2f(v.x), b = h2f(v.y), c = h2f(v.z), d = h2f(v.w);
+            out.c[4 * k + 0] = {s * a.x, s * a.y};
+            out.c[4 * k + 1] = {s * b.x, s * b.y};
+            out.c[4 * k + 2] = {s * c.x, s * c.y};
+            out.c[4 * k + 3] = {s * d.x, s * d.y};
+        }
+        return out;
+    }
+    __device__ static void store(void *base, int Vh, int i, const Spinor<R> &v) {
+        uint4 *p = (uint4 *)base;
+        float *sc = (float *)((char *)base + (size_t)Vh * 48);
+        float m = 0.f;
+#pragma unroll
+        for (int k = 0; k < 12; k++) m = fmaxf(m, fmaxf(fabsf(v.c[k].re), fabsf(v.c[k].im)));
+        float inv = m > 0.f ? 1.0f / m : 0.f;
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            uint4 u;
+            u.x = f2h(v.c[4 * k + 0].re * inv, v.c[4 * k + 0].im * inv);
+            u.y = f2h(v.c[4 * k + 1].re * inv, v.c[4 * k + 1].im * inv);
+            u.z = f2h(v.c[4 * k + 2].re * inv, v.c[4 * k + 2].im * inv);
+            u.w = f2h(v.c[4 * k + 3].re * inv, v.c[4 * k + 3].im * inv);
+            p[(size_t)k * Vh + i] = u;
+        }
+        sc[i] = m;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// links: full 3x3 matrices in registers
+// ---------------------------------------------------------------------------
+template <class R> struct Mat3 {
+    cx<R> m[9];  // row-major
+};
+
+template <class R> WC_HD void recon_col2(Mat3<R> &u) {
+    // column 2 = conj(col0 x col1)
+    cx<R> a0 = u.m[0], a1 = u.m[3], a2 = u.m[6];
+    cx<R> b0 = u.m[1], b1 = u.m[4], b2 = u.m[7];
+    u.m[2] = conjx(a1 * b2 - a2 * b1);
+    u.m[5] = conjx(a2 * b0 - a0 * b2);
+    u.m[8] = conjx(a0 * b1 - a1 * b0);
+}
+
+template <int P> struct LinkIO;
+
+template <> struct LinkIO<P64> {
+    using R = double;
+    __device__ static Mat3<R> load(const void *slab, int Vh, int i) {
+        const double2 *p = (const double2 *)slab;
+        Mat3<R> u;
+#pragma unroll
+        for (int k = 0; k < 9; k++) {
+            double2 v = ld_stream(p + (size_t)k * Vh + i);
+            u.m[k] = {v.x, v.y};
+        }
+        return u;
+    }
+};
+
+template <> struct LinkIO<P32> {
+    using R = float;
+    __device__ static Mat3<R> load(const void *slab, int Vh, int i) {
+        const float4 *p = (const float4 *)slab;
+        float4 a = ld_stream(p + i);
+        float4 b = ld_stream(p + (size_t)Vh + i);
+        float4 c = ld_stream(p + 2 * (size_t)Vh + i);
+        Mat3<R> u;
+        u.m[0] = {a.x, a.y};
+        u.m[3] = {a.z, a.w};
+        u.m[6] = {b.x, b.y};
+        u.m[1] = {b.z, b.w};
+        u.m[4] = {c.x, c.y};
+        u.m[7] = {c.z, c.w};
+        recon_col2(u);
+        return u;
+    }
+};
+
+template <> struct LinkIO<P16> {
+    using R = float;
+    __device__ static Mat3<R> load(const void *slab, int Vh, int i) {
+        const uint4 *p = (const uint4 *)slab;
+        const uint2 *q = (const uint2 *)((const char *)slab + (size_t)Vh * 16);
+        uint4 a = ld_stream(p + i);
+        uint2 b = ld_stream(q + i);
+        float2 v0 = h2f(a.x), v1 = h2f(a.y), v2 = h2f(a.z), v3 = h2f(a.w), v4 = h2f(b.x), v5 = h2f(b.y);
+        Mat3<R> u;
+        u.m[0] = {v0.x, v0.y};
+        u.m[3] = {v1.x, v1.y};
+        u.m[6] = {v2.x, v2.y};
+        u.m[1] = {v3.x, v3.y};
+        u.m[4] = {v4.x, v4.y};
+        u.m[7] = {v5.x, v5.y};
+        recon_col2(u);
+        return u;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// clover blocks: y = M w for a packed Hermitian 6x6 M
+// ---------------------------------------------------------------------------
+template <class R> struct Herm6 {
+    R d[6];
+    cx<R> o[15];  // (0,1) (0,2) .. (0,5) (1,2) .. (4,5)
+};
+
+template <class R> WC_HD void herm6_apply(const Herm6<R> &M, const cx<R> *w, cx<R> *y) {
+#pragma unroll
+    for (int i = 0; i < 6; i++) y[i] = M.d[i] * w[i];
+    int k = 0;
+#pragma unroll
+    for (int i = 0; i < 6; i++) {
+#pragma unroll
+        for (int j = i + 1; j < 6; j++) {
+            cmac(y[i], M.o[k], w[j]);
+            cmacc(y[j], M.o[k], w[i]);
+            k++;
+        }
+    }
+}
+
+template <int P> struct CloverIO;
+
+template <> struct CloverIO<P64> {
+    using R = double;
+    // block b (0: g5 = +1, 1: g5 = -1) of site i
+    __device__ static Herm6<R> load(const void *slab, int Vh, int i, int b) {
+        const double2 *p = (const double2 *)slab + (size_t)(18 * b) * Vh;
+        Herm6<R> M;
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            double2 v = ld_stream(p + (size_t)k * Vh + i);
+            M.d[2 * k] = v.x;
+            M.d[2 * k + 1] = v.y;
+        }
+#pragma unroll
+        for (int k = 0; k < 15; k++) {
+            double2 v = ld_stream(p + (size_t)(3 + k) * Vh + i);
+            M.o[k] = {v.x, v.y};
+        }
+        return M;
+    }
+};
+
+template <> struct CloverIO<P32> {
+    using R = float;
+    __device__ static Herm6<R> load(const void *slab, int Vh, int i, int b) {
+        const float4 *p = (const float4 *)slab + (size_t)(9 * b) * Vh;
+        float f[36];
+#pragma unroll
+        for (int k = 0; k < 9; k++) {
+            float4 v = ld_stream(p + (size_t)k * Vh + i);
+            f[4 * k] = v.x;
+            f[4 * k + 1] = v.y;
+            f[4 * k + 2] = v.z;
+            f[4 * k + 3] = v.w;
+        }
+        Herm6<R> M;
+#pragma unroll
+        for (int k = 0; k < 6; k++) M.d[k] = f[k];
+#pragma unroll
+        for (int k = 0; k < 15; k++) M.o[k] = {f[6 + 2 * k], f[7 + 2 * k]};
+        return M;
+    }
+};
+
+// FP16 clover: per block b, 4 uint4 planes then 1 uint2 plane (36 halves = 72 B per
+// site and block, block b starting at byte b * 72 Vh), then one FP32 scale per site
+// at byte 144 Vh; entry = scale * half.
+template <> struct CloverIO<P16> {
+    using R = float;
+    __device__ static Herm6<R> load(const void *slab, int Vh, int i, int b) {
+        const char *base = (const char *)slab + (size_t)b * 72 * Vh;
+        const uint4 *p = (const uint4 *)base;
+        const uint2 *q = (const uint2 *)(base + (size_t)64 * Vh);
+        const float *sc = (const float *)((const char *)slab + (size_t)Vh * 144);
+        float s = sc[i];
+        uint32_t w[18];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            uint4 v = ld_stream(p + (size_t)k * Vh + i);
+            w[4 * k] = v.x;
+            w[4 * k + 1] = v.y;
+            w[4 * k + 2] = v.z;
+            w[4 * k + 3] = v.w;
+        }
+        uint2 v = ld_stream(q + i);
+        w[16] = v.x;
+        w[17] = v.y;
+        float f[36];
+#pragma unroll
+        for (int k = 0; k < 18; k++) {
+            float2 h = h2f(w[k]);
+            f[2 * k] = s * h.x;
+            f[2 * k + 1] = s * h.y;
+        }
+        Herm6<R> M;
+#pragma unroll
+        for (int k = 0; k < 6; k++) M.d[k] = f[k];
+#pragma unroll
+        for (int k = 0; k < 15; k++) M.o[k] = {f[6 + 2 * k], f[7 + 2 * k]};
+        return M;
+    }
+};
+
+// Apply a site's clover pair to a spinor in the Dirac basis.
+// The pair holds M1 = (A - B)/2 on the g5 = +1 space (u, -u) and M2 = (A + B)/2 on
+// the g5 = -1 space (u, u), where F = [[A, B], [B, A]] in upper/lower spin blocks.
+// Then  up = M2 (psi_u + psi_d) + M1 (psi_u - psi_d),
+//       dn = M2 (psi_u + psi_d) - M1 (psi_u - psi_d).
+template <int P, class R>
+__device__ __forceinline__ void clover_apply(const void *slab, int Vh, int i, const Spinor<R> &in, Spinor<R> &out) {
+    cx<R> wm[6], wp[6], ym[6], yp[6];
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+        wm[k] = in.c[k] - in.c[k + 6];
+        wp[k] = in.c[k] + in.c[k + 6];
+    }
+    {
+        Herm6<R> M = CloverIO<P>::load(slab, Vh, i, 0);
+        herm6_apply(M, wm, ym);
+    }
+    {
+        Herm6<R> M = CloverIO<P>::load(slab, Vh, i, 1);
+        herm6_apply(M, wp, yp);
+    }
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+        out.c[k] = yp[k] + ym[k];
+        out.c[k + 6] = yp[k] - ym[k];
+    }
+}

@@ -1,0 +1,255 @@
+// The hopping stencil with spin projection and its clover epilogues (MULT of
+// Sec. II-B, eq. 9, and the Schur operator D-hat_ee of eq. 8).
+//
+// One thread per output site of one parity.  For each of the 8 directions the
+// neighbour spinor (opposite parity) is projected to a two-spin half spinor,
+// multiplied by U_mu(n) (forward) or U_mu(n - mu)^dagger (backward), and
+// expanded back into the accumulator (eq. 4).  In the Dirac representation:
+//   (1 - g_k) psi = (h, -i s_k h),  h = psi_u + i s_k psi_d     (k = x, y, z)
+//   (1 + g_k) psi = (h',  i s_k h'), h' = psi_u - i s_k psi_d
+//   (1 - g_t) psi = (0, 2 psi_d),    (1 + g_t) psi = (2 psi_u, 0)
+// so each direction costs two 3x3 complex matrix-vector products.
+// Neighbour spinors are ordinary cached loads (each is read by 8 output sites);
+// links and clover blocks are read exactly once per launch and use
+// non-temporal loads so they do not evict the spinor working set.
+#include "reduce.hpp"
+
+namespace {
+
+struct MultKArgs {
+    Geom g;
+    int out_par;
+    void *out;
+    const void *in;
+    const void *center;
+    const void *aux;
+    const char *links;   // base of the 8 link slabs of this precision
+    size_t link_slab;    // bytes per (mu, parity) slab
+    const void *clov;    // clover slab (F or F^-1) of the output parity
+    double coef;
+    RedTarget red;
+    const int *done;
+};
+
+// g = U h (dag = false) or U^dagger h (dag = true), two spin components
+template <class R, bool DAG>
+__device__ __forceinline__ void su3_mul2(const Mat3<R> &U, const cx<R> (&h)[2][3], cx<R> (&g)[2][3]) {
+#pragma unroll
+    for (int s = 0; s < 2; s++) {
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            cx<R> acc = {R(0), R(0)};
+#pragma unroll
+            for (int b = 0; b < 3; b++) {
+                if (DAG)
+                    cmacc(acc, U.m[3 * b + a], h[s][b]);
+                else
+                    cmac(acc, U.m[3 * a + b], h[s][b]);
+            }
+            g[s][a] = acc;
+        }
+    }
+}
+
+// accumulate (1 -+ g_mu) U psi for direction mu; FWD selects the forward hop
+template <class R, int MU, bool FWD>
+__device__ __forceinline__ void hop_term(const Spinor<R> &p, const Mat3<R> &U, Spinor<R> &acc) {
+    cx<R> h[2][3], g[2][3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const cx<R> p0 = p.c[a], p1 = p.c[3 + a], p2 = p.c[6 + a], p3 = p.c[9 + a];
+        if (MU == 0) {
+            h[0][a] = FWD ? p0 + mul_i(p3) : p0 - mul_i(p3);
+            h[1][a] = FWD ? p1 + mul_i(p2) : p1 - mul_i(p2);
+        } else if (MU == 1) {
+            h[0][a] = FWD ? p0 + p3 : p0 - p3;
+            h[1][a] = FWD ? p1 - p2 : p1 + p2;
+        } else if (MU == 2) {
+            h[0][a] = FWD ? p0 + mul_i(p2) : p0 - mul_i(p2);
+            h[1][a] = FWD ? p1 - mul_i(p3) : p1 + mul_i(p3);
+        } else {
+            h[0][a] = FWD ? p2 + p2 : p0 + p0;
+            h[1][a] = FWD ? p3 + p3 : p1 + p1;
+        }
+    }
+    su3_mul2<R, !FWD>(U, h, g);
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const cx<R> g0 = g[0][a], g1 = g[1][a];
+        if (MU == 3) {
+            if (FWD) {
+                acc.c[6 + a] = acc.c[6 + a] + g0;
+                acc.c[9 + a] = acc.c[9 + a] + g1;
+            } else {
+                acc.c[a] = acc.c[a] + g0;
+                acc.c[3 + a] = acc.c[3 + a] + g1;
+            }
+            continue;
+        }
+        acc.c[a] = acc.c[a] + g0;
+        acc.c[3 + a] = acc.c[3 + a] + g1;
+        if (MU == 0) {
+            acc.c[6 + a] = acc.c[6 + a] + (FWD ? mul_mi(g1) : mul_i(g1));
+            acc.c[9 + a] = acc.c[9 + a] + (FWD ? mul_mi(g0) : mul_i(g0));
+        } else if (MU == 1) {
+            acc.c[6 + a] = FWD ? acc.c[6 + a] - g1 : acc.c[6 + a] + g1;
+            acc.c[9 + a] = FWD ? acc.c[9 + a] + g0 : acc.c[9 + a] - g0;
+        } else {
+            acc.c[6 + a] = acc.c[6 + a] + (FWD ? mul_mi(g0) : mul_i(g0));
+            acc.c[9 + a] = acc.c[9 + a] + (FWD ? mul_i(g1) : mul_mi(g1));
+        }
+    }
+}
+
+template <int P, int MU>
+__device__ __forceinline__ void hop_dir(const MultKArgs &a, const SiteCoord &c, int i,
+                                        Spinor<typename Real<P>::T> &acc) {
+    using R = typename Real<P>::T;
+    const int Vh = a.g.Vh;
+    {
+        const int nf = eo_neighbour(a.g, c, MU, +1);
+        const Spinor<R> psi = SpinorIO<P>::load(a.in, Vh, nf);
+        const Mat3<R> U = LinkIO<P>::load(a.links + (size_t)(2 * MU + a.out_par) * a.link_slab, Vh, i);
+        hop_term<R, MU, true>(psi, U, acc);
+    }
+    {
+        const int nb = eo_neighbour(a.g, c, MU, -1);
+        const Spinor<R> psi = SpinorIO<P>::load(a.in, Vh, nb);
+        const Mat3<R> U = LinkIO<P>::load(a.links + (size_t)(2 * MU + 1 - a.out_par) * a.link_slab, Vh, nb);
+        hop_term<R, MU, false>(psi, U, acc);
+    }
+}
+
+template <int P, int MODE, int RED>
+__global__ __launch_bounds__(kBlock) void k_mult(MultKArgs a) {
+    using R = typename Real<P>::T;
+    if (a.done && *a.done) return;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const bool active = i < a.g.Vh;
+    const int Vh = a.g.Vh;
+    Spinor<R> out;
+    if (active) {
+        Spinor<R> acc;
+#pragma unroll
+        for (int k = 0; k < 12; k++) acc.c[k] = {R(0), R(0)};
+        if (MODE != M_CLOV) {
+            const SiteCoord c = eo_coords(a.g, i, a.out_par);
+            hop_dir<P, 0>(a, c, i, acc);
+            hop_dir<P, 1>(a, c, i, acc);
+            hop_dir<P, 2>(a, c, i, acc);
+            hop_dir<P, 3>(a, c, i, acc);
+        }
+        const R coef = (R)a.coef;
+        if (MODE == M_HOPINV) {
+            clover_apply<P, R>(a.clov, Vh, i, acc, out);
+        } else if (MODE == M_DHAT) {
+            Spinor<R> t;
+            clover_apply<P, R>(a.clov, Vh, i, acc, t);
+            const Spinor<R> cen = SpinorIO<P>::load(a.center, Vh, i);
+#pragma unroll
+            for (int k = 0; k < 12; k++) out.c[k] = cen.c[k] + coef * t.c[k];
+        } else if (MODE == M_DFULL) {
+            const Spinor<R> cen = SpinorIO<P>::load(a.center, Vh, i);
+            clover_apply<P, R>(a.clov, Vh, i, cen, out);
+#pragma unroll
+            for (int k = 0; k < 12; k++) out.c[k] = out.c[k] + coef * acc.c[k];
+        } else if (MODE == M_INVSRC) {
+            Spinor<R> s = SpinorIO<P>::load(a.center, Vh, i);
+#pragma unroll
+            for (int k = 0; k < 12; k++) s.c[k] = s.c[k] + coef * acc.c[k];
+            clover_apply<P, R>(a.clov, Vh, i, s, out);
+        } else if (MODE == M_CLOV) {
+            const Spinor<R> cen = SpinorIO<P>::load(a.center, Vh, i);
+            clover_apply<P, R>(a.clov, Vh, i, cen, out);
+        } else {
+            out = acc;
+        }
+        SpinorIO<P>::store(a.out, Vh, i, out);
+    }
+    if (RED != R_NONE) {
+        constexpr int N = (RED == R_DOT) ? 2 : 3;
+        double v[N], tot[N];
+#pragma unroll
+        for (int k = 0; k < N; k++) v[k] = 0.0;
+        if (active) {
+            const Spinor<R> ax = SpinorIO<P>::load(a.aux, Vh, i);
+#pragma unroll
+            for (int k = 0; k < 12; k++) {
+                const double ar = ax.c[k].re, ai = ax.c[k].im, orr = out.c[k].re, oi = out.c[k].im;
+                v[0] += ar * orr + ai * oi;
+                v[1] += ar * oi - ai * orr;
+                if (N == 3) v[N - 1] += orr * orr + oi * oi;
+            }
+        }
+        grid_reduce<N>(v, a.red, tot);
+    }
+}
+
+template <int P, int MODE, int RED> void launch_one(const MultKArgs &a, int blocks, hipStream_t s) {
+    hipLaunchKernelGGL((k_mult<P, MODE, RED>), dim3(blocks), dim3(kBlock), 0, s, a);
+}
+
+template <int P> void dispatch_mode(const MultKArgs &a, int mode, int red, int blocks, hipStream_t s) {
+    switch (mode) {
+    case M_HOPINV: launch_one<P, M_HOPINV, R_NONE>(a, blocks, s); break;
+    case M_DHAT:
+        if (red == R_DOT) launch_one<P, M_DHAT, R_DOT>(a, blocks, s);
+        else if (red == R_DOTNORM) launch_one<P, M_DHAT, R_DOTNORM>(a, blocks, s);
+        else launch_one<P, M_DHAT, R_NONE>(a, blocks, s);
+        break;
+    case M_DFULL: launch_one<P, M_DFULL, R_NONE>(a, blocks, s); break;
+    case M_INVSRC: launch_one<P, M_INVSRC, R_NONE>(a, blocks, s); break;
+    case M_HOP: launch_one<P, M_HOP, R_NONE>(a, blocks, s); break;
+    case M_CLOV: launch_one<P, M_CLOV, R_NONE>(a, blocks, s); break;
+    }
+}
+
+// algorithmic bytes of one launch (per output site: inputs and outputs at the
+// stored precision, each link once, one clover pair; see the byte model in the
+// documentation of the benchmark)
+double mult_bytes(int prec, int mode, int red, int Vh) {
+    const double S = (double)spinor_bytes(prec, Vh), L = (double)link_slab_bytes(prec, Vh),
+                 C = (double)clover_slab_bytes(prec, Vh);
+    double b = 0;
+    if (mode != M_CLOV) b += 2 * S + 8 * L;  // input (counted once) + output, 8 link slabs
+    else b += 2 * S;
+    if (mode != M_HOP) b += C;
+    if (mode == M_DHAT || mode == M_DFULL || mode == M_INVSRC) b += S;  // centre vector
+    if (red != R_NONE) b += S;                                           // aux vector
+    return b;
+}
+
+}  // namespace
+
+int launch_mult(wc_lattice *lat, const MultCall &c) {
+    MultKArgs a;
+    a.g = lat->g;
+    a.out_par = c.out_par;
+    a.out = c.out;
+    a.in = c.in;
+    a.center = c.center;
+    a.aux = c.aux;
+    a.links = (const char *)lat->links[c.prec];
+    a.link_slab = link_slab_bytes(c.prec, lat->Vh);
+    const bool use_inv = (c.mode == M_HOPINV || c.mode == M_DHAT || c.mode == M_INVSRC ||
+                          (c.mode == M_CLOV && c.inverse));
+    const char *cb = (const char *)(use_inv ? lat->clovinv[c.prec] : lat->clov[c.prec]);
+    a.clov = cb + (size_t)c.out_par * clover_slab_bytes(c.prec, lat->Vh);
+    a.coef = c.coef;
+    a.red = c.red_to;
+    a.done = c.done;
+    const int blocks = (lat->Vh + kBlock - 1) / kBlock;
+
+    int slot = KS_MULT_OTHER;
+    if (c.mode == M_HOPINV) slot = KS_MULT_HOPINV_P64 + c.prec;
+    if (c.mode == M_DHAT) slot = KS_MULT_DHAT_P64 + c.prec;
+    TimedLaunch t;
+    if (lat->timing) timing_begin(lat, slot, mult_bytes(c.prec, c.mode, c.red, lat->Vh), t);
+    if (c.prec == P64) dispatch_mode<P64>(a, c.mode, c.red, blocks, lat->stream);
+    else if (c.prec == P32) dispatch_mode<P32>(a, c.mode, c.red, blocks, lat->stream);
+    else dispatch_mode<P16>(a, c.mode, c.red, blocks, lat->stream);
+    WC_HIP(hipGetLastError());
+    if (lat->timing) timing_end(lat, t);
+    if (c.mode != M_CLOV) lat->dslash_count++;
+    return WC_OK;
+}

@@ -1,0 +1,112 @@
+// Layout kernels: canonical complex128 fields <-> the structure-of-arrays
+// even-odd layout, and the per-precision copies of the gauge links.
+#include "reduce.hpp"
+
+namespace {
+
+__global__ __launch_bounds__(kBlock) void k_load_links(Geom g, const double2 *U, double2 *l64, float4 *l32,
+                                                       char *l16) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const int slab = blockIdx.y;  // 2 mu + parity
+    if (i >= g.Vh) return;
+    const int mu = slab >> 1, par = slab & 1;
+    const SiteCoord c = eo_coords(g, i, par);
+    const size_t n = (size_t)c.x + (size_t)g.L[0] * c.row;
+    const size_t V = (size_t)2 * g.Vh;
+    const double2 *src = U + ((size_t)mu * V + n) * 9;
+    double2 m[9];
+#pragma unroll
+    for (int k = 0; k < 9; k++) m[k] = src[k];
+    double2 *d64 = l64 + (size_t)slab * 9 * g.Vh;
+#pragma unroll
+    for (int k = 0; k < 9; k++) d64[(size_t)k * g.Vh + i] = m[k];
+    // columns 0 and 1: U00 U10 | U20 U01 | U11 U21
+    float4 *d32 = l32 + (size_t)slab * 3 * g.Vh;
+    d32[i] = make_float4((float)m[0].x, (float)m[0].y, (float)m[3].x, (float)m[3].y);
+    d32[(size_t)g.Vh + i] = make_float4((float)m[6].x, (float)m[6].y, (float)m[1].x, (float)m[1].y);
+    d32[2 * (size_t)g.Vh + i] = make_float4((float)m[4].x, (float)m[4].y, (float)m[7].x, (float)m[7].y);
+    char *b16 = l16 + (size_t)slab * 24 * g.Vh;
+    uint4 *p16 = (uint4 *)b16;
+    uint2 *q16 = (uint2 *)(b16 + (size_t)16 * g.Vh);
+    uint4 u;
+    u.x = f2h((float)m[0].x, (float)m[0].y);
+    u.y = f2h((float)m[3].x, (float)m[3].y);
+    u.z = f2h((float)m[6].x, (float)m[6].y);
+    u.w = f2h((float)m[1].x, (float)m[1].y);
+    p16[i] = u;
+    q16[i] = make_uint2(f2h((float)m[4].x, (float)m[4].y), f2h((float)m[7].x, (float)m[7].y));
+}
+
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_pack(Geom g, char *eo, const double2 *canon, size_t slab_bytes) {
+    using R = typename Real<P>::T;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const int par = blockIdx.y;
+    if (i >= g.Vh) return;
+    const SiteCoord c = eo_coords(g, i, par);
+    const size_t n = (size_t)c.x + (size_t)g.L[0] * c.row;
+    const double2 *src = canon + n * 12;
+    Spinor<R> s;
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        double2 v = src[k];
+        s.c[k] = {(R)v.x, (R)v.y};
+    }
+    SpinorIO<P>::store(eo + par * slab_bytes, g.Vh, i, s);
+}
+
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_unpack(Geom g, double2 *canon, const char *eo, size_t slab_bytes) {
+    using R = typename Real<P>::T;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const int par = blockIdx.y;
+    if (i >= g.Vh) return;
+    const SiteCoord c = eo_coords(g, i, par);
+    const size_t n = (size_t)c.x + (size_t)g.L[0] * c.row;
+    const Spinor<R> s = SpinorIO<P>::load(eo + par * slab_bytes, g.Vh, i);
+    double2 *dst = canon + n * 12;
+#pragma unroll
+    for (int k = 0; k < 12; k++) dst[k] = make_double2((double)s.c[k].re, (double)s.c[k].im);
+}
+
+}  // namespace
+
+int launch_load_links(wc_lattice *lat, const void *U) {
+    dim3 grid((lat->Vh + kBlock - 1) / kBlock, 8);
+    hipLaunchKernelGGL(k_load_links, grid, dim3(kBlock), 0, lat->stream, lat->g, (const double2 *)U,
+                       (double2 *)lat->links[P64], (float4 *)lat->links[P32], (char *)lat->links[P16]);
+    WC_HIP(hipGetLastError());
+    return WC_OK;
+}
+
+int launch_pack_spinor(wc_lattice *lat, int prec, void *eo_out, const void *canon_in) {
+    dim3 grid((lat->Vh + kBlock - 1) / kBlock, 2);
+    const size_t sb = spinor_bytes(prec, lat->Vh);
+    if (prec == P64)
+        hipLaunchKernelGGL(k_pack<P64>, grid, dim3(kBlock), 0, lat->stream, lat->g, (char *)eo_out,
+                           (const double2 *)canon_in, sb);
+    else if (prec == P32)
+        hipLaunchKernelGGL(k_pack<P32>, grid, dim3(kBlock), 0, lat->stream, lat->g, (char *)eo_out,
+                           (const double2 *)canon_in, sb);
+    else
+        hipLaunchKernelGGL(k_pack<P16>, grid, dim3(kBlock), 0, lat->stream, lat->g, (char *)eo_out,
+                           (const double2 *)canon_in, sb);
+    WC_HIP(hipGetLastError());
+    return WC_OK;
+}
+
+int launch_unpack_spinor(wc_lattice *lat, int prec, void *canon_out, const void *eo_in) {
+    dim3 grid((lat->Vh + kBlock - 1) / kBlock, 2);
+    const size_t sb = spinor_bytes(prec, lat->Vh);
+    if (prec == P64)
+        hipLaunchKernelGGL(k_unpack<P64>, grid, dim3(kBlock), 0, lat->stream, lat->g, (double2 *)canon_out,
+                           (const char *)eo_in, sb);
+    else if (prec == P32)
+        hipLaunchKernelGGL(k_unpack<P32>, grid, dim3(kBlock), 0, lat->stream, lat->g, (double2 *)canon_out,
+                           (const char *)eo_in, sb);
+    else
+        hipLaunchKernelGGL(k_unpack<P16>, grid, dim3(kBlock), 0, lat->stream, lat->g, (double2 *)canon_out,
+                           (const char *)eo_in, sb);
+    WC_HIP(hipGetLastError());
+    return WC_OK;
+}

@@ -1,0 +1,69 @@
+"""The C ABI without a GPU: the library loads, exports every symbol the header
+declares, and rejects bad arguments on the host before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "wc.h")
+LIB = os.path.join(ROOT, "paper_1709_08785_amd", "libwc.so")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(wc_[A-Za-z_0-9]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        import paper_1709_08785_amd.build as b
+        b.build()
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for must in ["wc_create_lattice", "wc_load_links", "wc_build_clover", "wc_apply_D", "wc_apply_Dee_oo",
+                 "wc_solve", "wc_destroy_lattice", "wc_last_error"]:
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_create_rejects_bad_extents_before_gpu(lib):
+    lib.wc_create_lattice.argtypes = [ctypes.POINTER(ctypes.c_int), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
+    lib.wc_last_error.restype = ctypes.c_char_p
+    for dims in [(4, 4, 4, 5), (0, 4, 4, 4), (4, 4, 4, 1), (-2, 4, 4, 4)]:
+        h = ctypes.c_void_p()
+        rc = lib.wc_create_lattice((ctypes.c_int * 4)(*dims), None, ctypes.byref(h))
+        assert rc == -1 and not h.value
+        assert b"even" in lib.wc_last_error()
+    assert lib.wc_create_lattice(None, None, None) == -1
+
+
+def test_null_handles_rejected(lib):
+    lib.wc_load_links.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    lib.wc_build_clover.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double]
+    lib.wc_solve.argtypes = [ctypes.c_void_p] * 2 + [ctypes.c_double] * 3 + [ctypes.c_void_p] * 2 + [ctypes.c_int,
+                                                                                                   ctypes.c_void_p]
+    assert lib.wc_load_links(None, None) == -1
+    assert lib.wc_build_clover(None, 0.1, 1.0) == -1
+    assert lib.wc_solve(None, None, 0.1, 1.0, 1e-10, None, None, 0, None) == -1
+    lib.wc_spinor_bytes.restype = ctypes.c_size_t
+    assert lib.wc_spinor_bytes(None, 1) == 0
+    lib.wc_destroy_lattice(None)
+
+
+def test_default_params(lib):
+    import paper_1709_08785_amd as wc
+    p = wc.SolveParams()
+    lib.wc_solve_params_default(ctypes.byref(p))
+    assert p.inner_prec == wc.FP32 and p.inner_maxit > 0 and p.outer_maxit > 0 and p.check_every > 0
+    assert p.fixed_work == 0
