@@ -1,0 +1,307 @@
+"""Benchmark: nested mixed-precision BiCGStab solve of the even-odd clover Wilson
+system on one MI355X.
+
+One step = one complete solve D x = b to true relative residual 1e-10 on the
+32^3 x 64 lattice (links exp(0.3 i H), kappa = 0.135, c_SW = 1.0, one Gaussian
+source): FP64 outer flexible BiCGStab around an FP32 inner BiCGStab (inner
+tolerance 1e-6), links, clover and b resident in HBM when the clock starts.
+
+Printed (one JSON line): the solve-wide effective bandwidth (algorithmic bytes
+of every operator and BLAS kernel in the solve / solve time), the roofline of
+the dominant kernel measured with HIP events on the library's stream, the
+time to solution of the all-FP64 BiCGStab on the same system, and the FP64
+oracle timed on the host cores on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import glob
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Dslash GB/s (% HBM peak); time-to-1e-10 solve, mixed vs FP64 on 1 GPU"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1709_08785_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel: str, launches_bytes: float):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("source_hash") != source_hash():
+        return None
+    k = d.get("kernels", {}).get(kernel)
+    if not k:
+        return None
+    return k.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(U, b, dims, kappa, csw, budget_s=20.0):
+    """The FP64 oracle (plain C, OpenMP) applying the full D on the same lattice."""
+    import numpy as np
+    import oracle
+
+    nthreads = oracle.num_threads()
+    t0 = time.perf_counter()
+    F = oracle.clover_field(U, dims, kappa, csw)
+    t_clover = time.perf_counter() - t0
+    n_apply = 0
+    t0 = time.perf_counter()
+    out = None
+    while True:
+        out = oracle.apply_D(U, F, kappa, b)
+        n_apply += 1
+        el = time.perf_counter() - t0
+        if el > budget_s or n_apply >= 200:
+            break
+    el = time.perf_counter() - t0
+    V = int(np.prod(dims))
+    # algorithmic bytes of one full-lattice D in FP64: spinor in + out (2 x 192 B),
+    # each of the 4V links once (4 x 144 B per site), one 2x36-real clover (576 B)
+    bytes_per_site = 2 * 192 + 4 * 144 + 576
+    gbs = n_apply * V * bytes_per_site / el / 1e9
+    del F, out
+    return {
+        "value": round(gbs, 3),
+        "unit": "GB/s",
+        "cores": nthreads,
+        "kind": "oracle",
+        "sample": ("%d applications of the full FP64 operator D (oracle, precomputed clover; clover build "
+                   "%.1f s not counted) on the %s lattice, %d B/site algorithmic" %
+                   (n_apply, t_clover, "x".join(map(str, dims)), bytes_per_site)),
+        "seconds": round(el, 3),
+    }
+
+
+def dslash_mode(args, dims):
+    """Operator micro-benchmark: MULT and D-hat_ee in each precision, K launches each,
+    timed with HIP events on the library stream; plus a device copy of known size
+    (the calibration kernel for the HBM byte counters)."""
+    import numpy as np
+    import torch
+
+    import paper_1709_08785_amd as wc
+    import synth
+
+    U = synth.random_links(dims, 0.3, args.seed)
+    psi = synth.gaussian_source(dims, args.seed + 1000)
+    dev = torch.device("cuda:0")
+    lat = wc.Lattice(dims, device=dev)
+    lat.load_links(torch.from_numpy(U).to(dev))
+    lat.build_clover(args.kappa, args.csw)
+    psid = torch.from_numpy(psi).to(dev)
+    res = {}
+    for name, prec in [("fp32", wc.FP32), ("fp16", wc.FP16), ("fp64", wc.FP64)]:
+        eo = lat.pack(psid, prec)
+        out = lat.new_eo(prec, 1)
+        e_in = lat.parity_view(eo, 0, prec)
+        o_in = lat.parity_view(eo, 1, prec)
+        for w in range(3):
+            lat.apply_mult(out, o_in, 0, prec)
+            lat.apply_Dee_oo(out, e_in, prec)
+        torch.cuda.synchronize()
+        lat.reset_kernel_stats()
+        lat.set_timing(True)
+        for k in range(args.steps):
+            lat.apply_mult(out, o_in, 0, prec)
+        for k in range(args.steps):
+            lat.apply_Dee_oo(out, e_in, prec)
+        lat.set_timing(False)
+        st = lat.kernel_stats()
+        for kname, v in st.items():
+            if v["launches"]:
+                res[kname] = {"launches": v["launches"], "avg_us": round(v["ms"] / v["launches"] * 1e3, 2),
+                              "algorithmic_GBs": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1),
+                              "frac_hbm": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                              "bytes_per_launch": v["bytes"] / v["launches"]}
+        lat.reset_kernel_stats()
+        del eo, out
+    # calibration copy: 1 GiB read + 1 GiB written
+    n = 1 << 28
+    a = torch.ones(n, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    for k in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for k in range(args.steps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    res["copy_1GiB"] = {"avg_us": round(ms * 1e3, 2), "GBs": round(2 * 4 * n / (ms * 1e-3) / 1e9, 1),
+                        "bytes_read": 4 * n, "bytes_written": 4 * n}
+    print(json.dumps({"mode": "dslash", "lattice": list(dims), "kernels": res}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--mode", choices=["solve", "dslash"], default="solve")
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--dims", type=str, default="32,32,32,64")
+    ap.add_argument("--kappa", type=float, default=0.135)
+    ap.add_argument("--csw", type=float, default=1.0)
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--inner-tol", type=float, default=1e-6)
+    ap.add_argument("--inner", type=str, default="fp32")
+    ap.add_argument("--no-fp64-arm", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--seed", type=int, default=1002)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sharded design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1709_08785_amd as wc
+    import synth
+
+    dims = tuple(int(v) for v in args.dims.split(","))
+    if args.mode == "dslash":
+        dslash_mode(args, dims)
+        return
+    t0 = time.perf_counter()
+    U = synth.random_links(dims, 0.3, args.seed)
+    b = synth.gaussian_source(dims, args.seed + 1000)
+    log("inputs generated in %.1f s" % (time.perf_counter() - t0))
+
+    dev = torch.device("cuda:0")
+    lat = wc.Lattice(dims, device=dev)
+    Ud = torch.from_numpy(U).to(dev)
+    bd = torch.from_numpy(b).to(dev)
+    lat.load_links(Ud)
+    lat.build_clover(args.kappa, args.csw)
+    del Ud
+    torch.cuda.synchronize()
+    inner = wc._prec(args.inner)
+    solve_kw = dict(inner_prec=inner, inner_tol=args.inner_tol)
+
+    for w in range(args.warmup):
+        x, info = lat.solve(bd, args.kappa, args.csw, args.tol, **solve_kw)
+        log("warmup %d: %s" % (w, json.dumps(info)))
+
+    lat.reset_kernel_stats()
+    lat.set_timing(True)
+    infos = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        x, info = lat.solve(bd, args.kappa, args.csw, args.tol, **solve_kw)
+        infos.append(info)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat.set_timing(False)
+    stats = lat.kernel_stats()
+    for s, info in enumerate(infos):
+        log("step %d: %s" % (s, json.dumps(info)))
+    ms_per_step = wall / args.steps * 1e3
+    total_bytes = sum(v["bytes"] for v in stats.values())
+    value = total_bytes / wall / 1e9
+
+    # dominant kernel by total event time
+    dom_name, dom = max(((k, v) for k, v in stats.items() if v["launches"] > 0), key=lambda kv: kv[1]["ms"])
+    per_launch_bytes = dom["bytes"] / dom["launches"]
+    avg_ms = dom["ms"] / dom["launches"]
+    achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9
+    hbm = traffic_for(dom_name, per_launch_bytes)
+    roofline = {
+        "bound": "hbm",
+        "kernel": dom_name,
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": hbm,
+        "avg_launch_us": round(avg_ms * 1e3, 2),
+        "algorithmic_bytes_per_launch": per_launch_bytes,
+    }
+    kern = {k: {"launches": v["launches"], "avg_us": round(v["ms"] / v["launches"] * 1e3, 2),
+                "GBs": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1)}
+            for k, v in stats.items() if v["launches"] > 0}
+
+    # the all-FP64 arm on the same system
+    fp64 = None
+    if not args.no_fp64_arm:
+        x64, info64 = lat.solve(bd, args.kappa, args.csw, args.tol, inner_prec=wc.FP64)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        x64, info64 = lat.solve(bd, args.kappa, args.csw, args.tol, inner_prec=wc.FP64)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t1
+        log("fp64 arm: %s" % json.dumps(info64))
+        diff = float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64))
+        fp64 = {"seconds": round(t64, 4), "iterations": info64["inner_iters_total"],
+                "true_rel_residual": info64["true_rel_residual"], "mixed_vs_fp64_solution_rel_diff": diff}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        del x
+        torch.cuda.synchronize()
+        cpu = cpu_baseline(U, b, dims, args.kappa, args.csw)
+
+    last = infos[-1]
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if inner == wc.FP32 else ("f16s+f32+f64" if inner == wc.FP16 else "f64"),
+        "data": "synthetic",
+        "config": {"workload": "nested BiCGStab solve, %s lattice, exp(0.3 i H) links, kappa %g, c_SW %g, "
+                               "Gaussian source, %s inner (tol %g) / FP64 outer, true residual %g"
+                               % ("x".join(map(str, dims)), args.kappa, args.csw, args.inner.upper(),
+                                  args.inner_tol, args.tol),
+                   "lattice": list(dims), "kappa": args.kappa, "csw": args.csw, "tol": args.tol,
+                   "inner": args.inner, "inner_tol": args.inner_tol},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "time_to_solution_s": {"mixed": round(ms_per_step / 1e3, 4), "fp64": fp64["seconds"] if fp64 else None},
+        "speedup_mixed_vs_fp64": round(fp64["seconds"] / (ms_per_step / 1e3), 3) if fp64 else None,
+        "fp64_arm": fp64,
+        "solve": {"outer_iters": last["outer_iters"], "inner_iters": last["inner_iters_total"],
+                  "inner_calls": last["inner_calls"], "restarts": last["restarts"],
+                  "true_rel_residual": last["true_rel_residual"], "dslash_count": last["dslash_count"]},
+        "kernels": kern,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

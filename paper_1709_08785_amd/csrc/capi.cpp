@@ -135,7 +135,6 @@ static void free_all(wc_lattice *lat) {
     for (int k = 0; k < 32; k++)
         if (lat->work[k]) (void)hipFree(lat->work[k]);
     if (lat->partials) (void)hipFree(lat->partials);
-    if (lat->counter) (void)hipFree(lat->counter);
     if (lat->scalars) (void)hipFree(lat->scalars);
     if (lat->flags) (void)hipFree(lat->flags);
     if (lat->host_scalars) (void)hipHostFree(lat->host_scalars);
@@ -180,7 +179,6 @@ extern "C" int wc_create_lattice(const int dims[4], void *stream, wc_lattice **o
     lat->max_blocks = (lat->Vh + 255) / 256;
     int rc = WC_OK;
     if ((rc = dev_alloc((void **)&lat->partials, sizeof(double) * 8 * (size_t)lat->max_blocks)) ||
-        (rc = dev_alloc((void **)&lat->counter, 256)) ||
         (rc = dev_alloc((void **)&lat->scalars, sizeof(double) * NUM_LEVELS * S_COUNT)) ||
         (rc = dev_alloc((void **)&lat->flags, sizeof(int) * NUM_LEVELS * F_COUNT))) {
         free_all(lat);
@@ -196,8 +194,7 @@ extern "C" int wc_create_lattice(const int dims[4], void *stream, wc_lattice **o
         delete lat;
         return wc_fail(WC_ENOMEM, "pinned host allocation failed");
     }
-    if (hipMemsetAsync(lat->counter, 0, 256, lat->stream) != hipSuccess ||
-        hipMemsetAsync(lat->scalars, 0, sizeof(double) * NUM_LEVELS * S_COUNT, lat->stream) != hipSuccess ||
+    if (hipMemsetAsync(lat->scalars, 0, sizeof(double) * NUM_LEVELS * S_COUNT, lat->stream) != hipSuccess ||
         hipMemsetAsync(lat->flags, 0, sizeof(int) * NUM_LEVELS * F_COUNT, lat->stream) != hipSuccess ||
         hipStreamSynchronize(lat->stream) != hipSuccess) {
         std::string m = hipGetErrorString(hipGetLastError());

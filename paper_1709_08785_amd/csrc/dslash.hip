@@ -12,6 +12,11 @@
 // Neighbour spinors are ordinary cached loads (each is read by 8 output sites);
 // links and clover blocks are read exactly once per launch and use
 // non-temporal loads so they do not evict the spinor working set.
+//
+// Workgroups are handed to the 8 XCDs round-robin, and each XCD has its own
+// L2.  The block index is remapped so that XCD k sweeps one contiguous slab of
+// the lattice: the y, z and t neighbours a block needs were then loaded by
+// blocks of the same XCD shortly before, and hit in that XCD's L2.
 #include "reduce.hpp"
 
 namespace {
@@ -120,11 +125,18 @@ __device__ __forceinline__ void hop_dir(const MultKArgs &a, const SiteCoord &c, 
     }
 }
 
+// logical block of hardware block b: XCD (b mod 8) takes the slab
+// [(b mod 8) per, (b mod 8 + 1) per); a ragged tail keeps its own index
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    const int per = nb >> 3;
+    return (b < (per << 3)) ? (b & 7) * per + (b >> 3) : b;
+}
+
 template <int P, int MODE, int RED>
 __global__ __launch_bounds__(kBlock) void k_mult(MultKArgs a) {
     using R = typename Real<P>::T;
     if (a.done && *a.done) return;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     const bool active = i < a.g.Vh;
     const int Vh = a.g.Vh;
     Spinor<R> out;
@@ -168,7 +180,7 @@ __global__ __launch_bounds__(kBlock) void k_mult(MultKArgs a) {
     }
     if (RED != R_NONE) {
         constexpr int N = (RED == R_DOT) ? 2 : 3;
-        double v[N], tot[N];
+        double v[N];
 #pragma unroll
         for (int k = 0; k < N; k++) v[k] = 0.0;
         if (active) {
@@ -181,7 +193,7 @@ __global__ __launch_bounds__(kBlock) void k_mult(MultKArgs a) {
                 if (N == 3) v[N - 1] += orr * orr + oi * oi;
             }
         }
-        grid_reduce<N>(v, a.red, tot);
+        block_partials<N>(v, a.red.partials);
     }
 }
 
@@ -251,5 +263,15 @@ int launch_mult(wc_lattice *lat, const MultCall &c) {
     WC_HIP(hipGetLastError());
     if (lat->timing) timing_end(lat, t);
     if (c.mode != M_CLOV) lat->dslash_count++;
+    if (c.red != R_NONE && (c.mode == M_DHAT)) {
+        FinArgs f{};
+        f.n = c.red == R_DOT ? 2 : 3;
+        f.blocks = blocks;
+        f.op = FIN_STORE;
+        f.partials = c.red_to.partials;
+        f.result = c.red_to.result;
+        f.guard = c.done;
+        return launch_finalize(lat, f);
+    }
     return WC_OK;
 }

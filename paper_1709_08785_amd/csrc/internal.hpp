@@ -66,7 +66,6 @@ struct wc_lattice {
 
     // reductions
     double *partials = nullptr;      // [8][max_blocks]
-    unsigned *counter = nullptr;     // last-block-done ticket
     double *scalars = nullptr;       // [NUM_LEVELS][S_COUNT]
     int *flags = nullptr;            // [NUM_LEVELS][F_COUNT]
     double *host_scalars = nullptr;  // pinned mirror of scalars
@@ -110,13 +109,35 @@ void timing_end(wc_lattice *lat, TimedLaunch &t);
 // ---------------------------------------------------------------------------
 struct RedTarget {
     double *partials;
-    unsigned *counter;
     double *result;  // final sums written here (nres doubles)
 };
 
 inline RedTarget red_target(wc_lattice *lat, int lvl, int slot) {
-    return RedTarget{lat->partials, lat->counter, lat->level_scalars(lvl) + slot};
+    return RedTarget{lat->partials, lat->level_scalars(lvl) + slot};
 }
+
+// second stage of a reduction (blas.hip): sums the per-block partials in block
+// order, then applies `op` in one thread
+enum FinOp {
+    FIN_STORE = 0,   // result[0..n) = sums
+    FIN_INIT,        // rho0 = (sum, 0); reset the level's done flag and iteration count
+    FIN_INNER_A,     // ||s||^2; done = HALF below tol2, BREAK on a non-finite alpha or sum
+    FIN_INNER_B,     // ||r||^2, rho1 = <r~, r>, iterations = iter + 1; done = FULL / BREAK
+    FIN_OUTER_B      // ||r||^2, rho1 = <r~, r>
+};
+struct FinArgs {
+    int n;             // values per block (1..3)
+    int blocks;        // number of partials per value
+    int op;
+    const double *partials;
+    double *result;    // FIN_STORE destination
+    double *sc;        // scalar block of the level
+    int *fl;           // flag block of the level
+    const int *guard;  // skip when *guard != 0 (the producing kernel skipped too); may be null
+    int iter;
+    double tol2;
+};
+int launch_finalize(wc_lattice *lat, const FinArgs &f);
 
 // ---------------------------------------------------------------------------
 // launchers (layout.hip, clover.hip, dslash.hip, blas.hip)

@@ -1,10 +1,13 @@
-// Deterministic single-pass grid reduction for 64-wide wavefronts.
+// Deterministic two-stage reductions for 64-wide wavefronts.
 //
-// Each block folds its per-thread values with a wave shuffle tree and an LDS
-// pass in a fixed order, publishes one partial per value, and takes a ticket.
-// The block that draws the last ticket sums all partials in block order (a
-// fixed strided split over its threads, then the same fixed tree), so the
-// result does not depend on block scheduling.  Accumulation is in FP64.
+// Stage 1 (inside the producing kernel): each block folds its per-thread
+// values with a wave shuffle tree and an LDS pass in a fixed order and writes
+// one partial per value with a plain store.  Stage 2 is a separate one-block
+// kernel (k_finalize, blas.hip) that sums the partials in block order and runs
+// the scalar logic of the solver.  The kernel boundary makes the partials
+// visible; no block ever waits on, or fences against, another block, so the
+// per-XCD L2 caches keep the stencil's working set.  Accumulation is FP64 and
+// the summation order is fixed, so results are bit-reproducible.
 #pragma once
 
 #include "common.hpp"
@@ -40,47 +43,15 @@ template <int N> __device__ __forceinline__ void block_fold(double (&v)[N], doub
     }
 }
 
-// Returns true in thread 0 of the last block, after the grid totals have been
-// written to t.result[0..N).  `tot` then holds the totals in that thread.
-// Every thread of every block must call this (no early returns before it).
-template <int N>
-__device__ __forceinline__ bool grid_reduce(double (&v)[N], const RedTarget &t, double (&tot)[N]) {
+// Stage 1: per-block partials, laid out [k][gridDim.x].  Every thread of the
+// block must call this.
+template <int N> __device__ __forceinline__ void block_partials(double (&v)[N], double *partials) {
     __shared__ double sh[N][kWaves];
-    __shared__ int last;
     block_fold<N>(v, sh);
-    const int G = gridDim.x;
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < N; k++)
-            __hip_atomic_store(t.partials + (size_t)k * G + blockIdx.x, v[k], __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        unsigned prev = __hip_atomic_fetch_add(t.counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        last = (prev == (unsigned)G - 1u);
+        for (int k = 0; k < N; k++) partials[(size_t)k * gridDim.x + blockIdx.x] = v[k];
     }
-    __syncthreads();
-    if (!last) return false;
-    __threadfence();
-    double a[N];
-#pragma unroll
-    for (int k = 0; k < N; k++) a[k] = 0.0;
-    for (int j = threadIdx.x; j < G; j += blockDim.x) {
-#pragma unroll
-        for (int k = 0; k < N; k++)
-            a[k] += __hip_atomic_load(t.partials + (size_t)k * G + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __syncthreads();  // sh is reused
-    block_fold<N>(a, sh);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < N; k++) {
-            tot[k] = a[k];
-            t.result[k] = a[k];
-        }
-        __hip_atomic_store(t.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        return true;
-    }
-    return false;
 }
 
 // complex helpers on the device scalar block

@@ -5,7 +5,7 @@ closed form worked out by hand (free-field momentum-space operator, constant
 abelian flux), a symmetry of the operator (gamma5-hermiticity, gauge and
 translation covariance), an independent library route (dense LU), or
 arithmetic printed in the paper (Table 1 flop counts, the byte model of
-Sec. IV).
+Sec. IV-B).
 """
 import numpy as np
 import pytest
@@ -401,7 +401,7 @@ def test_apply_D_sites_matches_whole_lattice():
 
 
 # ---------------------------------------------------------------------------
-# arithmetic printed in the paper (Table 1; Sec. IV byte model)
+# arithmetic printed in the paper (Table 1; Sec. IV-B byte model)
 # ---------------------------------------------------------------------------
 
 def test_table1_flop_identities():
