@@ -19,6 +19,9 @@ Functions and the passage each one follows:
 * ``bhat_e``, ``dhat_ee``, ``x_o``  even-odd Schur pieces (Sec. II-B, eqs. 5-9)
 * ``free_solve_fft``  D^-1 b for unit links by Fourier transform (eqs. 3-4
                       with U = 1 and F = 1)
+* ``link_grad``       gradient of -Re<lam, D[U] x> with respect to the links
+                      (the chain rule through eqs. 3-4 and the clover term)
+* ``gamma5``, ``adjoint_solve``  D^-dagger = g5 D^-1 g5 (gamma5-hermiticity)
 """
 from __future__ import annotations
 
@@ -63,6 +66,7 @@ def _load():
         lib.or_residual.argtypes = [P, P, D, D, P, P, P, P]
         lib.or_bicgstab.argtypes = [P, P, P, D, P, P, D, ctypes.c_int, P, P]
         lib.or_bicgstab.restype = ctypes.c_int
+        lib.or_link_grad.argtypes = [P, P, P, P, D, D, ctypes.c_int, P]
         lib.or_num_threads.restype = ctypes.c_int
         lib.or_set_num_threads.argtypes = [ctypes.c_int]
         _lib = lib
@@ -291,3 +295,32 @@ def free_solve_fft(b, kappa: float) -> np.ndarray:
     bt = np.fft.fftn(b, axes=(0, 1, 2, 3))
     xt = np.linalg.solve(Dp, bt)          # colour index acts as 3 right-hand sides
     return np.fft.ifftn(xt, axes=(0, 1, 2, 3))
+
+
+# ---------------------------------------------------------------------------
+# gradients
+# ---------------------------------------------------------------------------
+
+def gamma5(psi) -> np.ndarray:
+    """g5 psi with g5 = g_x g_y g_z g_t."""
+    return np.einsum("ab,...bc->...ac", gamma(4), psi)
+
+
+def adjoint_solve(U, F, kappa: float, eta, tol: float = 1e-13):
+    """lam = D^-dagger eta = g5 D^-1 g5 eta (D is gamma5-Hermitian)."""
+    y, _, _ = solve(U, F, kappa, gamma5(eta), tol=tol)
+    return gamma5(y)
+
+
+def link_grad(U, lam, x, kappa: float, csw: float, include_clover: bool = True) -> np.ndarray:
+    """G with dg = Re sum conj(G) dU for g(U) = -Re<lam, D[U] x> (lam, x fixed).
+
+    At lam = D^-dagger eta, x = D^-1 b it is the link gradient of
+    L = Re<eta, D^-1 b> in torch's complex convention (dL/dRe U + i dL/dIm U).
+    """
+    dims = dims_of_spinor(x)
+    U, lam, x = _c(U), _c(lam), _c(x)
+    G = np.zeros_like(U)
+    _load().or_link_grad(_p(_dims(dims)), _p(U), _p(lam), _p(x), float(kappa), float(csw),
+                         int(bool(include_clover)), _p(G))
+    return G

@@ -503,6 +503,130 @@ int or_bicgstab(const int *L, const cplx *U, const cplx *F, double kappa, const 
     return status;
 }
 
+/* ------------------------------------------------------------------ */
+/* link gradient                                                        */
+/* ------------------------------------------------------------------ */
+
+/* Gradient, in the convention dg = Re sum_links sum_ab conj(G_ab) dU_ab, of
+     g(U) = -Re <lam, D[U] x>          (lam and x held fixed).
+   At lam = D^-dagger eta and x = D^-1 b this is the gradient of
+   L = Re <eta, D^-1 b> with respect to the links, because
+   dL = -Re <lam, (dD) x> with dD = dF - kappa dH (eq. 3).
+   Hopping part (eq. 4), for link U_mu(m):
+     G += kappa sum_alpha [ lam(m)_alpha conj(((1 - g_mu) x(m+mu))_alpha)^T
+                          + ((1 + g_mu) x(m))_alpha conj(lam(m+mu)_alpha)^T ]   (outer products in colour)
+   Clover part: dF = -kappa c_SW sum_{mu<nu} g_mu g_nu (x) dFhat_{mu nu}, dFhat = (dQ - dQ^dag)/8,
+   so dg = (kappa c_SW / 8) Re tr(N^T dQ) per site and plane with
+     M_ab = sum_{alpha beta} conj(lam_{alpha a}) (g_mu g_nu)_{alpha beta} x_{beta b},  N = M - M^dag.
+   A leaf W = f1 f2 f3 f4 whose factor k is a link (or its dagger) contributes, with
+   A = f1..f_{k-1} and B = f_{k+1}..f4:  G += (kappa c_SW / 8) (B N^T A)^dagger for an
+   undaggered factor and (kappa c_SW / 8) B N^T A for a daggered one.
+   G has the canonical link layout. */
+
+/* the four counter-clockwise leaves of Q_{mu nu}(n): per factor (0 = mu-link,
+   1 = nu-link), its root offset along (mu, nu), and whether it is daggered */
+static const int kLeaf[4][4][4] = {
+    {{0, 0, 0, 0}, {1, 1, 0, 0}, {0, 0, 1, 1}, {1, 0, 0, 1}},
+    {{1, 0, 0, 0}, {0, -1, 1, 1}, {1, -1, 0, 1}, {0, -1, 0, 0}},
+    {{0, -1, 0, 1}, {1, -1, -1, 1}, {0, -1, -1, 0}, {1, 0, -1, 0}},
+    {{1, 0, -1, 1}, {0, 0, -1, 0}, {1, 1, -1, 0}, {0, 0, 0, 1}},
+};
+
+void or_link_grad(const int *L, const cplx *U, const cplx *lam, const cplx *x, double kappa, double csw,
+                  int include_clover, cplx *G)
+{
+    long V = volume(L);
+    memset(G, 0, sizeof(cplx) * 36 * V);
+#pragma omp parallel for schedule(static)
+    for (long m = 0; m < V; m++) {
+        int c[4];
+        coords(L, m, c);
+        for (int mu = 0; mu < 4; mu++) {
+            cplx g[4][4];
+            gamma_mat(mu, g);
+            long mp = shifted(L, c, mu, +1);
+            cplx y[12], z[12];   /* y = (1 - g) x(m+mu), z = (1 + g) x(m) */
+            for (int al = 0; al < 4; al++)
+                for (int a = 0; a < 3; a++) {
+                    cplx sy = 0, sz = 0;
+                    for (int be = 0; be < 4; be++) {
+                        cplx d = (al == be) ? 1.0 : 0.0;
+                        sy += (d - g[al][be]) * x[mp * 12 + 3 * be + a];
+                        sz += (d + g[al][be]) * x[m * 12 + 3 * be + a];
+                    }
+                    y[3 * al + a] = sy;
+                    z[3 * al + a] = sz;
+                }
+            cplx *Gl = G + ((long)mu * V + m) * 9;
+            for (int a = 0; a < 3; a++)
+                for (int b = 0; b < 3; b++) {
+                    cplx s = 0;
+                    for (int al = 0; al < 4; al++)
+                        s += lam[m * 12 + 3 * al + a] * conj(y[3 * al + b]) + z[3 * al + a] * conj(lam[mp * 12 + 3 * al + b]);
+                    Gl[3 * a + b] += kappa * s;
+                }
+        }
+    }
+    if (!include_clover || csw == 0.0) return;
+    const double fac = kappa * csw / 8.0;
+    for (long n = 0; n < V; n++) {
+        int c[4];
+        coords(L, n, c);
+        for (int mu = 0; mu < 4; mu++)
+            for (int nu = mu + 1; nu < 4; nu++) {
+                cplx gm[4][4], gn[4][4], gg[4][4], M[9], N[9], NT[9];
+                gamma_mat(mu, gm);
+                gamma_mat(nu, gn);
+                for (int i = 0; i < 4; i++)
+                    for (int j = 0; j < 4; j++) {
+                        gg[i][j] = 0;
+                        for (int k = 0; k < 4; k++) gg[i][j] += gm[i][k] * gn[k][j];
+                    }
+                for (int a = 0; a < 3; a++)
+                    for (int b = 0; b < 3; b++) {
+                        cplx s = 0;
+                        for (int al = 0; al < 4; al++)
+                            for (int be = 0; be < 4; be++)
+                                s += conj(lam[n * 12 + 3 * al + a]) * gg[al][be] * x[n * 12 + 3 * be + b];
+                        M[3 * a + b] = s;
+                    }
+                for (int a = 0; a < 3; a++)
+                    for (int b = 0; b < 3; b++) N[3 * a + b] = M[3 * a + b] - conj(M[3 * b + a]);
+                for (int a = 0; a < 3; a++)
+                    for (int b = 0; b < 3; b++) NT[3 * a + b] = N[3 * b + a];
+                for (int lf = 0; lf < 4; lf++) {
+                    cplx f[4][9];
+                    long site_of[4];
+                    int dir_of[4];
+                    for (int k = 0; k < 4; k++) {
+                        const int *e = kLeaf[lf][k];
+                        int dir = e[0] == 0 ? mu : nu;
+                        long sn = shifted2(L, c, mu, e[1], nu, e[2]);
+                        site_of[k] = sn;
+                        dir_of[k] = dir;
+                        if (e[3]) m3_dag(link(U, V, dir, sn), f[k]);
+                        else memcpy(f[k], link(U, V, dir, sn), sizeof(cplx) * 9);
+                    }
+                    for (int k = 0; k < 4; k++) {
+                        cplx A[9], B[9], P[9];
+                        for (int q = 0; q < 9; q++) { A[q] = (q % 4 == 0) ? 1.0 : 0.0; B[q] = A[q]; }
+                        for (int j = 0; j < k; j++) m3_mul(A, f[j], A);
+                        for (int j = k + 1; j < 4; j++) m3_mul(B, f[j], B);
+                        m3_mul(B, NT, P);
+                        m3_mul(P, A, P);
+                        cplx *Gl = G + ((long)dir_of[k] * V + site_of[k]) * 9;
+                        if (kLeaf[lf][k][3]) {
+                            for (int q = 0; q < 9; q++) Gl[q] += fac * P[q];
+                        } else {
+                            for (int a = 0; a < 3; a++)
+                                for (int b = 0; b < 3; b++) Gl[3 * a + b] += fac * conj(P[3 * b + a]);
+                        }
+                    }
+                }
+            }
+    }
+}
+
 int or_num_threads(void)
 {
 #ifdef _OPENMP
