@@ -82,6 +82,8 @@ typedef struct {
     int fixed_work;       /* >0: run exactly this many inner iterations per inner call, no
                              convergence test (the fixed-count timing mode of Sec. IV) */
     int check_every;      /* inner iterations queued between host convergence reads (default 8) */
+    int adjoint;          /* != 0: solve D^dagger x = b instead, as g5 D^-1 g5 b (D is
+                             gamma5-Hermitian: g5 D g5 = D^dagger); default 0 */
 } wc_solve_params;
 
 /* What a solve did.  Iteration counts follow Algorithms 1 and 2. */
@@ -154,6 +156,18 @@ int wc_apply_clover(wc_lattice *lat, void *out, const void *in, int parity, int 
    are reached. */
 int wc_solve(wc_lattice *lat, const void *b_dev, double kappa, double csw, double tol,
              const wc_solve_params *p, void *x_dev, int x0_is_guess, wc_solve_info *info);
+
+/* Gradient of a real loss through a solve, with respect to the links.  With
+   x = D^-1 b and lam = D^-dagger g (g = dL/dRe x + i dL/dIm x, the adjoint solve),
+   dL = -Re<lam, (dD) x> for dD = dF - kappa dH (eqs. 3-4, and the clover term of
+   Sec. II-A).  Writes gradU (canonical link layout, complex128, device) with
+   dL = Re sum conj(gradU_ab) dU_ab over all links: the hopping outer products
+   kappa [lam(n) ((1 - g_mu) x(n+mu))^dag + ((1 + g_mu) x(n)) lam(n+mu)^dag] (traced
+   over spin), plus, when include_clover != 0, the clover force pushed through the
+   four leaves of every plane.  lam and x are canonical complex128 spinors.  Needs
+   wc_load_links; FP64 throughout.  The gradient with respect to b is lam itself. */
+int wc_link_grad(wc_lattice *lat, const void *lam_dev, const void *x_dev, double kappa, double csw,
+                 int include_clover, void *gradU_dev);
 
 /* Per-kernel timing with HIP events on the lattice's stream.  While enabled, every
    launch of the hot kernels is bracketed by an event pair; wc_kernel_stats()

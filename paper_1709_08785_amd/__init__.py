@@ -17,7 +17,7 @@ import os
 
 import torch
 
-__all__ = ["Lattice", "SolveParams", "FP64", "FP32", "FP16", "WCError", "library_path", "load_library"]
+__all__ = ["Lattice", "SolveParams", "FP64", "FP32", "FP16", "WCError", "library_path", "load_library", "solve"]
 
 FP64, FP32, FP16 = 0, 1, 2
 _PREC_NAMES = {"fp64": FP64, "fp32": FP32, "fp16": FP16}
@@ -37,7 +37,8 @@ class WCError(RuntimeError):
 
 class SolveParams(ctypes.Structure):
     _fields_ = [("inner_prec", ctypes.c_int), ("inner_tol", ctypes.c_double), ("inner_maxit", ctypes.c_int),
-                ("outer_maxit", ctypes.c_int), ("fixed_work", ctypes.c_int), ("check_every", ctypes.c_int)]
+                ("outer_maxit", ctypes.c_int), ("fixed_work", ctypes.c_int), ("check_every", ctypes.c_int),
+                ("adjoint", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -79,6 +80,7 @@ def load_library():
         "wc_apply_Dee_oo": (I, [P, P, P, I]),
         "wc_apply_clover": (I, [P, P, P, I, I, I]),
         "wc_solve": (I, [P, P, D, D, D, ctypes.POINTER(SolveParams), P, I, ctypes.POINTER(SolveInfo)]),
+        "wc_link_grad": (I, [P, P, P, D, D, I, P]),
         "wc_set_timing": (I, [P, I]),
         "wc_kernel_slots": (I, []),
         "wc_kernel_stats": (I, [P, I, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_long),
@@ -152,6 +154,14 @@ class Lattice:
         assert U.dtype == torch.complex128 and tuple(U.shape) == self.link_shape
         self._sync_stream()
         _check(self.lib.wc_load_links(self.h, _ptr(U)))
+        self._links_key = None
+
+    def _ensure_links(self, U: torch.Tensor):
+        """Load U unless it is the tensor (same storage and version) loaded last."""
+        key = (U.data_ptr(), U._version, tuple(U.shape))
+        if getattr(self, "_links_key", None) != key:
+            self.load_links(U.detach().contiguous())
+            self._links_key = key
 
     def build_clover(self, kappa: float, csw: float):
         self._sync_stream()
@@ -230,6 +240,17 @@ class Lattice:
         d["rc"] = rc
         return x, d
 
+    def link_grad(self, lam: torch.Tensor, x: torch.Tensor, kappa: float, csw: float,
+                  include_clover: bool = True) -> torch.Tensor:
+        """Gradient of -Re<lam, D[U] x> with respect to the loaded links (torch convention)."""
+        assert lam.dtype == torch.complex128 and tuple(lam.shape) == self.spinor_shape
+        assert x.dtype == torch.complex128 and tuple(x.shape) == self.spinor_shape
+        G = torch.empty(self.link_shape, dtype=torch.complex128, device=self.device)
+        self._sync_stream()
+        _check(self.lib.wc_link_grad(self.h, _ptr(lam), _ptr(x), float(kappa), float(csw),
+                                     int(bool(include_clover)), _ptr(G)))
+        return G
+
     # ---- timing --------------------------------------------------------------------
     def set_timing(self, on: bool):
         _check(self.lib.wc_set_timing(self.h, int(bool(on))))
@@ -248,3 +269,36 @@ class Lattice:
                                             ctypes.byref(by)))
             out[name.value.decode()] = {"launches": n.value, "ms": ms.value, "bytes": by.value}
         return out
+
+
+class _Solve(torch.autograd.Function):
+    """x = D[U]^-1 b with a hand-written backward: the adjoint solve
+    lam = D^-dagger g = g5 D^-1 g5 g gives grad_b = lam, and the link gradient
+    kernel gives grad_U from (lam, x)."""
+
+    @staticmethod
+    def forward(ctx, b, U, lat, kappa, csw, tol, params):
+        lat._ensure_links(U)
+        x, info = lat.solve(b.detach().contiguous(), kappa, csw, tol, **params)
+        ctx.lat, ctx.kappa, ctx.csw, ctx.tol, ctx.params = lat, kappa, csw, tol, params
+        ctx.info = info
+        ctx.save_for_backward(x, U)
+        return x
+
+    @staticmethod
+    def backward(ctx, gx):
+        x, U = ctx.saved_tensors
+        lat = ctx.lat
+        lat._ensure_links(U)
+        params = dict(ctx.params)
+        params["adjoint"] = 1
+        lam, _ = lat.solve(gx.detach().contiguous(), ctx.kappa, ctx.csw, ctx.tol, **params)
+        gb = lam if ctx.needs_input_grad[0] else None
+        gU = lat.link_grad(lam, x, ctx.kappa, ctx.csw) if ctx.needs_input_grad[1] else None
+        return gb, gU, None, None, None, None, None
+
+
+def solve(lat: "Lattice", b: torch.Tensor, U: torch.Tensor, kappa: float, csw: float, tol: float = 1e-10,
+          **params) -> torch.Tensor:
+    """Differentiable x = D[U]^-1 b (b and U may require grad)."""
+    return _Solve.apply(b, U, lat, float(kappa), float(csw), float(tol), params)

@@ -227,6 +227,7 @@ extern "C" void wc_solve_params_default(wc_solve_params *p) {
     p->outer_maxit = 100;
     p->fixed_work = 0;
     p->check_every = 8;
+    p->adjoint = 0;
 }
 
 extern "C" size_t wc_spinor_bytes(const wc_lattice *lat, int prec) {
@@ -361,4 +362,21 @@ extern "C" int wc_apply_clover(wc_lattice *lat, void *out, const void *in, int p
     MultCall c = mult_call(prec, M_CLOV, parity, out, nullptr, in, 0.0);
     c.inverse = inverse != 0;
     return launch_mult(lat, c);
+}
+
+extern "C" int wc_link_grad(wc_lattice *lat, const void *lam_dev, const void *x_dev, double kappa, double csw,
+                            int include_clover, void *gradU_dev) {
+    if (!lat || !lam_dev || !x_dev || !gradU_dev) return wc_fail(WC_EINVAL, "null argument");
+    if (!lat->have_links) return wc_fail(WC_ENOTREADY, "wc_link_grad before wc_load_links");
+    if (!(kappa >= 0.0) || !(csw >= 0.0)) return wc_fail(WC_EINVAL, "need kappa >= 0 and csw >= 0");
+    const size_t sb = spinor_bytes(P64, lat->Vh);
+    void *lam, *x, *N = nullptr;
+    if (int rc = work_get(lat, W_GLAM, 2 * sb, &lam)) return rc;
+    if (int rc = work_get(lat, W_GX, 2 * sb, &x)) return rc;
+    const bool clover = include_clover && csw != 0.0;
+    if (clover)
+        if (int rc = work_get(lat, W_GN, (size_t)6 * 2 * 9 * 16 * lat->Vh, &N)) return rc;
+    if (int rc = launch_pack_spinor(lat, P64, lam, lam_dev)) return rc;
+    if (int rc = launch_pack_spinor(lat, P64, x, x_dev)) return rc;
+    return launch_link_grad(lat, lam, x, gradU_dev, N, kappa, csw, clover);
 }

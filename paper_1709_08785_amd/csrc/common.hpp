@@ -457,3 +457,34 @@ __device__ __forceinline__ void clover_apply(const void *slab, int Vh, int i, co
         out.c[k + 6] = yp[k] - ym[k];
     }
 }
+
+// ---------------------------------------------------------------------------
+// FP64 links and site fields addressed by lattice coordinates (used by the
+// one-time clover build and by the gradient kernels; the stencil itself uses
+// the EO neighbour arithmetic above)
+// ---------------------------------------------------------------------------
+struct SiteRef {
+    int par, i;  // parity and EO index
+};
+
+WC_HD SiteRef site_ref(const Geom &g, int x, int y, int z, int t) {
+    const int L0 = g.L[0], L1 = g.L[1], L2 = g.L[2], L3 = g.L[3];
+    x = (x % L0 + L0) % L0;
+    y = (y % L1 + L1) % L1;
+    z = (z % L2 + L2) % L2;
+    t = (t % L3 + L3) % L3;
+    const int n = x + L0 * (y + L1 * (z + L2 * t));
+    return SiteRef{(x + y + z + t) & 1, n >> 1};
+}
+
+// U_mu at a site from the FP64 link copy ([mu][parity][9][Vh] double2)
+__device__ __forceinline__ Mat3<double> link64(const double2 *l64, const Geom &g, int mu, SiteRef s) {
+    const double2 *p = l64 + (size_t)(2 * mu + s.par) * 9 * g.Vh;
+    Mat3<double> u;
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+        double2 v = p[(size_t)k * g.Vh + s.i];
+        u.m[k] = {v.x, v.y};
+    }
+    return u;
+}

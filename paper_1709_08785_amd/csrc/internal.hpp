@@ -186,3 +186,8 @@ int launch_inner_final(wc_lattice *lat, int xprec, void *v64, const void *x, int
 int launch_outer_a(wc_lattice *lat, void *x, void *r, const void *v, const void *q, int iter, int lvl);
 int launch_outer_b(wc_lattice *lat, void *x, void *r, const void *v, const void *t, const void *rt, int iter,
                    int lvl);
+
+// gradient kernels (grad.hip)
+int launch_gamma5_p64(wc_lattice *lat, void *eo, int nslabs);
+int launch_link_grad(wc_lattice *lat, const void *lam_eo, const void *x_eo, void *G, void *Nbuf, double kappa,
+                     double csw, bool clover);

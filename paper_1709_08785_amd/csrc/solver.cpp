@@ -271,8 +271,11 @@ extern "C" int wc_solve(wc_lattice *lat, const void *b_dev, double kappa, double
         if (int rc = work_get(lat, bf.id, bf.bytes, bf.p)) return rc;
     const long dslash0 = lat->dslash_count;
 
-    // b -> EO FP64; ||b||
+    // b -> EO FP64; ||b||.  The adjoint system D^dag x = b is solved as
+    // D y = g5 b, x = g5 y (g5 D g5 = D^dag).
     if (int rc = launch_pack_spinor(lat, P64, C.b, b_dev)) return rc;
+    if (P.adjoint)
+        if (int rc = launch_gamma5_p64(lat, C.b, 2)) return rc;
     char *be = (char *)C.b, *bo = (char *)C.b + C.sb64;
     if (int rc = launch_norm2_p64(lat, be, red_target(lat, 1, S_AUX))) return rc;
     if (int rc = sync_scalars(lat)) return rc;
@@ -303,6 +306,8 @@ extern "C" int wc_solve(wc_lattice *lat, const void *b_dev, double kappa, double
     bool x_zero = true;
     if (x0_is_guess) {
         if (int rc = launch_pack_spinor(lat, P64, C.x, x_dev)) return rc;
+        if (P.adjoint)
+            if (int rc = launch_gamma5_p64(lat, C.x, 2)) return rc;
         x_zero = false;
     } else {
         if (int rc = launch_zero(lat, C.x, 2 * C.sb64)) return rc;
@@ -332,6 +337,8 @@ extern "C" int wc_solve(wc_lattice *lat, const void *b_dev, double kappa, double
         if (!conv && C.iprec != WC_FP64) break;  // iteration cap: give up
         C.info.restarts++;
     }
+    if (P.adjoint)
+        if (int rc = launch_gamma5_p64(lat, C.x, 2)) return rc;
     if (int rc = launch_unpack_spinor(lat, P64, x_dev, C.x)) return rc;
     WC_HIP(hipStreamSynchronize(lat->stream));
     auto t1 = std::chrono::steady_clock::now();

@@ -12,6 +12,8 @@ enum WorkId {
     W_R, W_RT, W_P, W_V, W_Q, W_T, W_TMP64, W_RES,   // single parity
     // inner (low precision) state
     W_IR, W_IRT, W_IP, W_IQ, W_IT, W_ITMP, W_IX,
+    // gradient
+    W_GLAM, W_GX, W_GN,
     W_COUNT
 };
 static_assert(W_COUNT <= 32, "work table too small");
