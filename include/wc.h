@@ -157,6 +157,25 @@ int wc_apply_clover(wc_lattice *lat, void *out, const void *in, int parity, int 
 int wc_solve(wc_lattice *lat, const void *b_dev, double kappa, double csw, double tol,
              const wc_solve_params *p, void *x_dev, int x0_is_guess, wc_solve_info *info);
 
+/* Batched solves (many solutions per gauge field, Sec. II-A): n systems,
+   1 <= n <= 16, solved together.  Every phase of the two BiCGStab loops is one
+   launch over all systems that are still iterating; each system keeps its own
+   scalars, convergence flag and caps, so the results equal n separate wc_solve
+   calls up to rounding.
+   wc_solve_batch: n right-hand sides b_dev[k] -> x_dev[k] on one lattice (canonical
+   complex128 device pointers).  Blocks of the n systems that read the same links and
+   clover run back to back on one XCD, so those operands are fetched from HBM about
+   once for all n.
+   wc_solve_multi: system k on lattice lats[k] (lattices of different sizes allowed;
+   systems on one lattice must share kappa and csw), all work on lats[0]'s stream.
+   info (n entries) may be NULL.  Returns WC_OK when every system met tol, else the
+   first failing system's status; x0 guesses are not taken. */
+int wc_solve_batch(wc_lattice *lat, int n, const void *const *b_dev, void *const *x_dev, double kappa,
+                   double csw, double tol, const wc_solve_params *p, wc_solve_info *info);
+int wc_solve_multi(int n, wc_lattice *const *lats, const void *const *b_dev, void *const *x_dev,
+                   const double *kappa, const double *csw, double tol, const wc_solve_params *p,
+                   wc_solve_info *info);
+
 /* Gradient of a real loss through a solve, with respect to the links.  With
    x = D^-1 b and lam = D^-dagger g (g = dL/dRe x + i dL/dIm x, the adjoint solve),
    dL = -Re<lam, (dD) x> for dD = dF - kappa dH (eqs. 3-4, and the clover term of

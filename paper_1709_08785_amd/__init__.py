@@ -17,7 +17,8 @@ import os
 
 import torch
 
-__all__ = ["Lattice", "SolveParams", "FP64", "FP32", "FP16", "WCError", "library_path", "load_library", "solve"]
+__all__ = ["Lattice", "SolveParams", "FP64", "FP32", "FP16", "WCError", "library_path", "load_library", "solve",
+           "solve_multi"]
 
 FP64, FP32, FP16 = 0, 1, 2
 _PREC_NAMES = {"fp64": FP64, "fp32": FP32, "fp16": FP16}
@@ -81,6 +82,10 @@ def load_library():
         "wc_apply_clover": (I, [P, P, P, I, I, I]),
         "wc_solve": (I, [P, P, D, D, D, ctypes.POINTER(SolveParams), P, I, ctypes.POINTER(SolveInfo)]),
         "wc_link_grad": (I, [P, P, P, D, D, I, P]),
+        "wc_solve_batch": (I, [P, I, ctypes.POINTER(P), ctypes.POINTER(P), D, D, D, ctypes.POINTER(SolveParams),
+                               ctypes.POINTER(SolveInfo)]),
+        "wc_solve_multi": (I, [I, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(D),
+                               ctypes.POINTER(D), D, ctypes.POINTER(SolveParams), ctypes.POINTER(SolveInfo)]),
         "wc_set_timing": (I, [P, I]),
         "wc_kernel_slots": (I, []),
         "wc_kernel_stats": (I, [P, I, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_long),
@@ -240,6 +245,22 @@ class Lattice:
         d["rc"] = rc
         return x, d
 
+    def solve_batch(self, bs, kappa: float, csw: float, tol: float, raise_on_error: bool = True, **params):
+        """Solve D x_k = b_k for up to 16 sources together; returns ([x_k], [info_k])."""
+        n = len(bs)
+        for b in bs:
+            assert b.dtype == torch.complex128 and tuple(b.shape) == self.spinor_shape
+        xs = [torch.empty_like(b) for b in bs]
+        p = self.default_params(**params)
+        infos = (SolveInfo * n)()
+        B = (ctypes.c_void_p * n)(*[_ptr(b).value for b in bs])
+        X = (ctypes.c_void_p * n)(*[_ptr(x).value for x in xs])
+        self._sync_stream()
+        rc = self.lib.wc_solve_batch(self.h, n, B, X, float(kappa), float(csw), float(tol), ctypes.byref(p), infos)
+        if rc != 0 and raise_on_error:
+            _check(rc)
+        return xs, [dict(infos[k].as_dict(), rc=rc) for k in range(n)]
+
     def link_grad(self, lam: torch.Tensor, x: torch.Tensor, kappa: float, csw: float,
                   include_clover: bool = True) -> torch.Tensor:
         """Gradient of -Re<lam, D[U] x> with respect to the loaded links (torch convention)."""
@@ -269,6 +290,26 @@ class Lattice:
                                             ctypes.byref(by)))
             out[name.value.decode()] = {"launches": n.value, "ms": ms.value, "bytes": by.value}
         return out
+
+
+def solve_multi(lats, bs, kappas, csws, tol: float, raise_on_error: bool = True, **params):
+    """Solve D_k x_k = b_k on lattices lats[k] (sizes may differ) together, on
+    lats[0]'s stream; returns ([x_k], [info_k])."""
+    n = len(lats)
+    lib = load_library()
+    xs = [torch.empty_like(b) for b in bs]
+    p = Lattice.default_params(**params)
+    infos = (SolveInfo * n)()
+    lats[0]._sync_stream()
+    L = (ctypes.c_void_p * n)(*[lat.h.value for lat in lats])
+    B = (ctypes.c_void_p * n)(*[_ptr(b).value for b in bs])
+    X = (ctypes.c_void_p * n)(*[_ptr(x).value for x in xs])
+    K = (ctypes.c_double * n)(*[float(k) for k in kappas])
+    C = (ctypes.c_double * n)(*[float(c) for c in csws])
+    rc = lib.wc_solve_multi(n, L, B, X, K, C, float(tol), ctypes.byref(p), infos)
+    if rc != 0 and raise_on_error:
+        _check(rc)
+    return xs, [dict(infos[k].as_dict(), rc=rc) for k in range(n)]
 
 
 class _Solve(torch.autograd.Function):

@@ -1,14 +1,15 @@
 // BLAS-1 with fused global reductions, and the vector updates of the two
-// BiCGStab loops (Algorithms 1 and 2), one thread per site.
+// BiCGStab loops (Algorithms 1 and 2), one thread per site, batched over
+// systems: one launch serves every active system of a solve.
 //
 // The BiCGStab coefficients never travel through the host: every update
 // kernel recomputes alpha = rho0 / <r~, q>, omega = <t, s> / ||t||^2 and
-// beta = (rho1 / rho0) (alpha / omega) from the device scalar block written
-// by the preceding reductions.  rho alternates between two slots, so the
-// value that becomes rho1 never overwrites the rho0 still in use.  The
-// finalize stage of a reduction also raises the level's done flag; every
-// later kernel of the level returns at once when the flag is set, so the
-// host may queue several iterations between convergence reads.
+// beta = (rho1 / rho0) (alpha / omega) from its system's device scalar block,
+// written by the preceding reductions.  rho alternates between two slots, so
+// the value that becomes rho1 never overwrites the rho0 still in use.  The
+// finalize stage of a reduction also raises the system's done flag; every
+// later kernel of the loop skips a system whose flag is set, so the host may
+// queue several iterations between convergence reads.
 #include "reduce.hpp"
 
 namespace {
@@ -17,249 +18,232 @@ __device__ __forceinline__ int rho_slot(int iter) { return (iter & 1) ? S_RHO1 :
 
 __device__ __forceinline__ bool finite_c(cx<double> a) { return isfinite(a.re) && isfinite(a.im); }
 
-// ------------------------------------------------------------------ FP64 helpers
-// ||v||^2 into result[0], and 0 into result[1] (so the pair reads as a complex number)
-__global__ __launch_bounds__(kBlock) void k_norm2_p64(int Vh, const void *v, RedTarget to) {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    double a[2] = {0.0, 0.0};
-    if (i < Vh) {
-        const Spinor<double> s = SpinorIO<P64>::load(v, Vh, i);
-#pragma unroll
-        for (int k = 0; k < 12; k++) a[0] += norm2(s.c[k]);
-    }
-    block_partials<2>(a, to.partials);
+struct VecBatch {
+    BatchHdr h;
+    VecCall c[kMaxSys];
+};
+
+template <class R> __device__ __forceinline__ cx<R> to(cx<double> a) { return {(R)a.re, (R)a.im}; }
+
+// number of reduced values of each op (0: no reduction)
+__host__ __device__ constexpr int red_count(int op) {
+    return op == V_NORM2 ? 2
+         : (op == V_SUB_NORM || op == V_INNER_INIT || op == V_INNER_A || op == V_OUTER_A) ? 1
+         : (op == V_INNER_B || op == V_OUTER_B) ? 3
+         : 0;
 }
 
-__global__ __launch_bounds__(kBlock) void k_sub_norm_p64(int Vh, void *r, const void *x, const void *y, RedTarget to) {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    double a[1] = {0.0};
-    if (i < Vh) {
-        const Spinor<double> s = SpinorIO<P64>::load(x, Vh, i);
-        const Spinor<double> t = SpinorIO<P64>::load(y, Vh, i);
-        Spinor<double> o;
-#pragma unroll
-        for (int k = 0; k < 12; k++) {
-            o.c[k] = s.c[k] - t.c[k];
-            a[0] += norm2(o.c[k]);
-        }
-        SpinorIO<P64>::store(r, Vh, i, o);
-    }
-    block_partials<1>(a, to.partials);
-}
-
-__global__ __launch_bounds__(kBlock) void k_axpy_p64(int Vh, void *y, const void *x, double alpha) {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= Vh) return;
-    Spinor<double> a = SpinorIO<P64>::load(y, Vh, i);
-    const Spinor<double> b = SpinorIO<P64>::load(x, Vh, i);
-#pragma unroll
-    for (int k = 0; k < 12; k++) a.c[k] = a.c[k] + alpha * b.c[k];
-    SpinorIO<P64>::store(y, Vh, i, a);
-}
-
-__global__ __launch_bounds__(kBlock) void k_zero(size_t n16, uint4 *p) {
-    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < n16) p[i] = make_uint4(0, 0, 0, 0);
-}
-
-// ------------------------------------------------------------------ Algorithm 2
-// b = src / ||src||; x = 0; r = r~ = p = b; rho0 = <r~, r>
-template <int P, int XP>
-__global__ __launch_bounds__(kBlock) void k_inner_init(int Vh, const void *src, void *r, void *rt, void *p, void *x,
-                                                       const double *sc, double *partials) {
+template <int OP, int P, int XP> __global__ __launch_bounds__(kBlock) void k_vec(VecBatch B) {
     using R = typename Real<P>::T;
     using RX = typename Real<XP>::T;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    double a[1] = {0.0};
-    if (i < Vh) {
-        const double inv = 1.0 / sqrt(sc[S_NORM]);
-        const Spinor<double> s = SpinorIO<P64>::load(src, Vh, i);
-        Spinor<R> b;
+    constexpr int N = red_count(OP);
+    constexpr int NA = N > 0 ? N : 1;
+    int s, lb;
+    batch_locate(B.h, blockIdx.x, s, lb);
+    const VecCall &c = B.c[s];
+    if (c.guard && c.fl[F_DONE]) return;
+    const int Vh = c.Vh;
+    const int i = lb * kBlock + threadIdx.x;
+    const bool active = i < Vh;
+    double a[NA];
 #pragma unroll
-        for (int k = 0; k < 12; k++) b.c[k] = {(R)(inv * s.c[k].re), (R)(inv * s.c[k].im)};
-        SpinorIO<P>::store(r, Vh, i, b);
-        SpinorIO<P>::store(rt, Vh, i, b);
-        SpinorIO<P>::store(p, Vh, i, b);
-        Spinor<RX> z;
-#pragma unroll
-        for (int k = 0; k < 12; k++) z.c[k] = {RX(0), RX(0)};
-        SpinorIO<XP>::store(x, Vh, i, z);
-        const Spinor<R> bs = SpinorIO<P>::load(r, Vh, i);  // the stored (rounded) value
-#pragma unroll
-        for (int k = 0; k < 12; k++) a[0] += norm2(bs.c[k]);
-    }
-    block_partials<1>(a, partials);
-}
+    for (int k = 0; k < NA; k++) a[k] = 0.0;
 
-// alpha = rho0 / <r~, q>;  s = r - alpha q (in place in r);  ||s||^2
-template <int P>
-__global__ __launch_bounds__(kBlock) void k_inner_a(int Vh, void *r, const void *q, const double *sc, const int *fl,
-                                                    int iter, double *partials) {
-    using R = typename Real<P>::T;
-    if (fl[F_DONE]) return;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    const cx<double> al = cdiv(ld_c(sc, rho_slot(iter)), ld_c(sc, S_RQ));
-    const cx<R> alpha = {(R)al.re, (R)al.im};
-    double a[1] = {0.0};
-    if (i < Vh) {
-        Spinor<R> rv = SpinorIO<P>::load(r, Vh, i);
-        const Spinor<R> qv = SpinorIO<P>::load(q, Vh, i);
+    if (OP == V_NORM2) {
+        if (active) {
+            const Spinor<double> v = SpinorIO<P64>::load(c.a, Vh, i);
 #pragma unroll
-        for (int k = 0; k < 12; k++) rv.c[k] = rv.c[k] - alpha * qv.c[k];
-        SpinorIO<P>::store(r, Vh, i, rv);
-#pragma unroll
-        for (int k = 0; k < 12; k++) a[0] += norm2(rv.c[k]);
-    }
-    block_partials<1>(a, partials);
-}
-
-// omega = <t, s> / ||t||^2;  x += alpha p + omega s;  r = s - omega t;  ||r||^2, rho1 = <r~, r>
-template <int P, int XP>
-__global__ __launch_bounds__(kBlock) void k_inner_b(int Vh, void *x, void *r, const void *p, const void *t,
-                                                    const void *rt, const double *sc, const int *fl, int iter,
-                                                    double *partials) {
-    using R = typename Real<P>::T;
-    using RX = typename Real<XP>::T;
-    if (fl[F_DONE]) return;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    const cx<double> al = cdiv(ld_c(sc, rho_slot(iter)), ld_c(sc, S_RQ));
-    const double tt = sc[S_TT];
-    const cx<double> om = {sc[S_ST] / tt, -sc[S_ST + 1] / tt};
-    const cx<RX> alx = {(RX)al.re, (RX)al.im}, omx = {(RX)om.re, (RX)om.im};
-    const cx<R> omega = {(R)om.re, (R)om.im};
-    double a[3] = {0.0, 0.0, 0.0};
-    if (i < Vh) {
-        Spinor<R> sv = SpinorIO<P>::load(r, Vh, i);
-        const Spinor<R> pv = SpinorIO<P>::load(p, Vh, i);
-        Spinor<RX> xv = SpinorIO<XP>::load(x, Vh, i);
-#pragma unroll
-        for (int k = 0; k < 12; k++) {
-            const cx<RX> pk = {(RX)pv.c[k].re, (RX)pv.c[k].im}, sk = {(RX)sv.c[k].re, (RX)sv.c[k].im};
-            xv.c[k] = xv.c[k] + alx * pk + omx * sk;
+            for (int k = 0; k < 12; k++) a[0] += norm2(v.c[k]);
         }
-        SpinorIO<XP>::store(x, Vh, i, xv);
-        const Spinor<R> tv = SpinorIO<P>::load(t, Vh, i);
+    } else if (OP == V_SUB_NORM) {
+        if (active) {
+            const Spinor<double> x = SpinorIO<P64>::load(c.b, Vh, i);
+            const Spinor<double> y = SpinorIO<P64>::load(c.c, Vh, i);
+            Spinor<double> o;
 #pragma unroll
-        for (int k = 0; k < 12; k++) sv.c[k] = sv.c[k] - omega * tv.c[k];
-        SpinorIO<P>::store(r, Vh, i, sv);
-        const Spinor<R> rtv = SpinorIO<P>::load(rt, Vh, i);
+            for (int k = 0; k < 12; k++) {
+                o.c[k] = x.c[k] - y.c[k];
+                a[0] += norm2(o.c[k]);
+            }
+            SpinorIO<P64>::store(c.a, Vh, i, o);
+        }
+    } else if (OP == V_AXPY) {
+        if (active) {
+            Spinor<double> y = SpinorIO<P64>::load(c.a, Vh, i);
+            const Spinor<double> x = SpinorIO<P64>::load(c.b, Vh, i);
 #pragma unroll
-        for (int k = 0; k < 12; k++) {
-            a[0] += norm2(sv.c[k]);
-            const double ar = rtv.c[k].re, ai = rtv.c[k].im, br = sv.c[k].re, bi = sv.c[k].im;
-            a[1] += ar * br + ai * bi;
-            a[2] += ar * bi - ai * br;
+            for (int k = 0; k < 12; k++) y.c[k] = y.c[k] + c.coef * x.c[k];
+            SpinorIO<P64>::store(c.a, Vh, i, y);
+        }
+    } else if (OP == V_COPY) {
+        if (active) SpinorIO<P64>::store(c.a, Vh, i, SpinorIO<P64>::load(c.b, Vh, i));
+    } else if (OP == V_ZERO) {
+        if (active) {
+            Spinor<double> z;
+#pragma unroll
+            for (int k = 0; k < 12; k++) z.c[k] = {0.0, 0.0};
+            SpinorIO<P64>::store(c.a, Vh, i, z);
+        }
+    } else if (OP == V_GAMMA5) {
+        // g5 = -[[0, 1], [1, 0]] in upper/lower spin blocks, both parity slabs
+        if (active) {
+            for (int par = 0; par < 2; par++) {
+                double2 *v = (double2 *)c.a + (size_t)par * 12 * Vh;
+#pragma unroll
+                for (int k = 0; k < 6; k++) {
+                    const double2 up = v[(size_t)k * Vh + i], dn = v[(size_t)(k + 6) * Vh + i];
+                    v[(size_t)k * Vh + i] = make_double2(-dn.x, -dn.y);
+                    v[(size_t)(k + 6) * Vh + i] = make_double2(-up.x, -up.y);
+                }
+            }
+        }
+    } else if (OP == V_INNER_INIT) {
+        // b = src / ||src||; x = 0; r = r~ = p = b; rho0 = <r~, r> of the stored values
+        if (active) {
+            const double nrm2 = c.sc[S_NORM];
+            const double inv = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
+            const Spinor<double> v = SpinorIO<P64>::load(c.a, Vh, i);
+            Spinor<R> b;
+#pragma unroll
+            for (int k = 0; k < 12; k++) b.c[k] = {(R)(inv * v.c[k].re), (R)(inv * v.c[k].im)};
+            SpinorIO<P>::store(c.b, Vh, i, b);
+            SpinorIO<P>::store(c.c, Vh, i, b);
+            SpinorIO<P>::store(c.d, Vh, i, b);
+            Spinor<RX> z;
+#pragma unroll
+            for (int k = 0; k < 12; k++) z.c[k] = {RX(0), RX(0)};
+            SpinorIO<XP>::store(c.e, Vh, i, z);
+            const Spinor<R> bs = SpinorIO<P>::load(c.b, Vh, i);
+#pragma unroll
+            for (int k = 0; k < 12; k++) a[0] += norm2(bs.c[k]);
+        }
+    } else if (OP == V_INNER_A) {
+        // alpha = rho0 / <r~, q>;  s = r - alpha q (in place in r);  ||s||^2
+        const cx<R> alpha = to<R>(cdiv(ld_c(c.sc, rho_slot(c.iter)), ld_c(c.sc, S_RQ)));
+        if (active) {
+            Spinor<R> rv = SpinorIO<P>::load(c.a, Vh, i);
+            const Spinor<R> qv = SpinorIO<P>::load(c.b, Vh, i);
+#pragma unroll
+            for (int k = 0; k < 12; k++) rv.c[k] = rv.c[k] - alpha * qv.c[k];
+            SpinorIO<P>::store(c.a, Vh, i, rv);
+#pragma unroll
+            for (int k = 0; k < 12; k++) a[0] += norm2(rv.c[k]);
+        }
+    } else if (OP == V_INNER_B) {
+        // omega = <t, s> / ||t||^2;  x += alpha p + omega s;  r = s - omega t;  ||r||^2, <r~, r>
+        const cx<double> al = cdiv(ld_c(c.sc, rho_slot(c.iter)), ld_c(c.sc, S_RQ));
+        const double tt = c.sc[S_TT];
+        const cx<double> om = {c.sc[S_ST] / tt, -c.sc[S_ST + 1] / tt};
+        const cx<RX> alx = to<RX>(al), omx = to<RX>(om);
+        const cx<R> omega = to<R>(om);
+        if (active) {
+            Spinor<R> sv = SpinorIO<P>::load(c.b, Vh, i);
+            const Spinor<R> pv = SpinorIO<P>::load(c.c, Vh, i);
+            Spinor<RX> xv = SpinorIO<XP>::load(c.a, Vh, i);
+#pragma unroll
+            for (int k = 0; k < 12; k++) {
+                const cx<RX> pk = {(RX)pv.c[k].re, (RX)pv.c[k].im}, sk = {(RX)sv.c[k].re, (RX)sv.c[k].im};
+                xv.c[k] = xv.c[k] + alx * pk + omx * sk;
+            }
+            SpinorIO<XP>::store(c.a, Vh, i, xv);
+            const Spinor<R> tv = SpinorIO<P>::load(c.d, Vh, i);
+#pragma unroll
+            for (int k = 0; k < 12; k++) sv.c[k] = sv.c[k] - omega * tv.c[k];
+            SpinorIO<P>::store(c.b, Vh, i, sv);
+            const Spinor<R> rtv = SpinorIO<P>::load(c.e, Vh, i);
+#pragma unroll
+            for (int k = 0; k < 12; k++) {
+                a[0] += norm2(sv.c[k]);
+                const double ar = rtv.c[k].re, ai = rtv.c[k].im, br = sv.c[k].re, bi = sv.c[k].im;
+                a[1 % NA] += ar * br + ai * bi;
+                a[2 % NA] += ar * bi - ai * br;
+            }
+        }
+    } else if (OP == V_INNER_C) {
+        // beta = (rho1 / rho0) (alpha / omega);  p = r + beta (p - omega q)
+        if (active) {
+            const cx<double> rho0 = ld_c(c.sc, rho_slot(c.iter)), rho1 = ld_c(c.sc, rho_slot(c.iter + 1));
+            const cx<double> al = cdiv(rho0, ld_c(c.sc, S_RQ));
+            const double tt = c.sc[S_TT];
+            const cx<double> om = {c.sc[S_ST] / tt, -c.sc[S_ST + 1] / tt};
+            const cx<R> beta = to<R>(cdiv(rho1, rho0) * cdiv(al, om)), omega = to<R>(om);
+            Spinor<R> pv = SpinorIO<P>::load(c.a, Vh, i);
+            const Spinor<R> rv = SpinorIO<P>::load(c.b, Vh, i);
+            const Spinor<R> qv = SpinorIO<P>::load(c.c, Vh, i);
+#pragma unroll
+            for (int k = 0; k < 12; k++) pv.c[k] = rv.c[k] + beta * (pv.c[k] - omega * qv.c[k]);
+            SpinorIO<P>::store(c.a, Vh, i, pv);
+        }
+    } else if (OP == V_INNER_FIX) {
+        // x += alpha p (the update skipped when the half step already converged)
+        if (active) {
+            const cx<RX> alx = to<RX>(cdiv(ld_c(c.sc, rho_slot(c.iter)), ld_c(c.sc, S_RQ)));
+            Spinor<RX> xv = SpinorIO<XP>::load(c.a, Vh, i);
+            const Spinor<R> pv = SpinorIO<P>::load(c.b, Vh, i);
+#pragma unroll
+            for (int k = 0; k < 12; k++) xv.c[k] = xv.c[k] + alx * cx<RX>{(RX)pv.c[k].re, (RX)pv.c[k].im};
+            SpinorIO<XP>::store(c.a, Vh, i, xv);
+        }
+    } else if (OP == V_INNER_FINAL) {
+        // v = ||src|| x into FP64 (Algorithm 2, last step)
+        if (active) {
+            const double nrm = sqrt(c.sc[S_NORM]);
+            const Spinor<RX> xv = SpinorIO<XP>::load(c.b, Vh, i);
+            Spinor<double> o;
+#pragma unroll
+            for (int k = 0; k < 12; k++) o.c[k] = {nrm * (double)xv.c[k].re, nrm * (double)xv.c[k].im};
+            SpinorIO<P64>::store(c.a, Vh, i, o);
+        }
+    } else if (OP == V_OUTER_A) {
+        // alpha = rho0 / <r~, q>;  x += alpha v;  r -= alpha q;  ||r||^2
+        const cx<double> al = cdiv(ld_c(c.sc, rho_slot(c.iter)), ld_c(c.sc, S_RQ));
+        if (active) {
+            Spinor<double> xv = SpinorIO<P64>::load(c.a, Vh, i);
+            Spinor<double> rv = SpinorIO<P64>::load(c.b, Vh, i);
+            const Spinor<double> vv = SpinorIO<P64>::load(c.c, Vh, i);
+            const Spinor<double> qv = SpinorIO<P64>::load(c.d, Vh, i);
+#pragma unroll
+            for (int k = 0; k < 12; k++) {
+                xv.c[k] = xv.c[k] + al * vv.c[k];
+                rv.c[k] = rv.c[k] - al * qv.c[k];
+                a[0] += norm2(rv.c[k]);
+            }
+            SpinorIO<P64>::store(c.a, Vh, i, xv);
+            SpinorIO<P64>::store(c.b, Vh, i, rv);
+        }
+    } else if (OP == V_OUTER_B) {
+        // omega = <t, r> / ||t||^2;  x += omega v;  r -= omega t;  ||r||^2, <r~, r>
+        const double tt = c.sc[S_TT];
+        const cx<double> om = {c.sc[S_ST] / tt, -c.sc[S_ST + 1] / tt};
+        if (active) {
+            Spinor<double> xv = SpinorIO<P64>::load(c.a, Vh, i);
+            Spinor<double> rv = SpinorIO<P64>::load(c.b, Vh, i);
+            const Spinor<double> vv = SpinorIO<P64>::load(c.c, Vh, i);
+            const Spinor<double> tv = SpinorIO<P64>::load(c.d, Vh, i);
+            const Spinor<double> rtv = SpinorIO<P64>::load(c.e, Vh, i);
+#pragma unroll
+            for (int k = 0; k < 12; k++) {
+                xv.c[k] = xv.c[k] + om * vv.c[k];
+                rv.c[k] = rv.c[k] - om * tv.c[k];
+                a[0] += norm2(rv.c[k]);
+                const double ar = rtv.c[k].re, ai = rtv.c[k].im, br = rv.c[k].re, bi = rv.c[k].im;
+                a[1 % NA] += ar * br + ai * bi;
+                a[2 % NA] += ar * bi - ai * br;
+            }
+            SpinorIO<P64>::store(c.a, Vh, i, xv);
+            SpinorIO<P64>::store(c.b, Vh, i, rv);
         }
     }
-    block_partials<3>(a, partials);
-}
-
-// beta = (rho1 / rho0) (alpha / omega);  p = r + beta (p - omega q)
-template <int P>
-__global__ __launch_bounds__(kBlock) void k_inner_c(int Vh, void *p, const void *r, const void *q, const double *sc,
-                                                    const int *fl, int iter) {
-    using R = typename Real<P>::T;
-    if (fl && fl[F_DONE]) return;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= Vh) return;
-    const cx<double> rho0 = ld_c(sc, rho_slot(iter)), rho1 = ld_c(sc, rho_slot(iter + 1));
-    const cx<double> al = cdiv(rho0, ld_c(sc, S_RQ));
-    const double tt = sc[S_TT];
-    const cx<double> om = {sc[S_ST] / tt, -sc[S_ST + 1] / tt};
-    const cx<double> be = cdiv(rho1, rho0) * cdiv(al, om);
-    const cx<R> beta = {(R)be.re, (R)be.im}, omega = {(R)om.re, (R)om.im};
-    Spinor<R> pv = SpinorIO<P>::load(p, Vh, i);
-    const Spinor<R> rv = SpinorIO<P>::load(r, Vh, i);
-    const Spinor<R> qv = SpinorIO<P>::load(q, Vh, i);
-#pragma unroll
-    for (int k = 0; k < 12; k++) pv.c[k] = rv.c[k] + beta * (pv.c[k] - omega * qv.c[k]);
-    SpinorIO<P>::store(p, Vh, i, pv);
-}
-
-// x += alpha p (the update skipped when the half step already converged)
-template <int P, int XP>
-__global__ __launch_bounds__(kBlock) void k_inner_fix(int Vh, void *x, const void *p, const double *sc, int iter) {
-    using R = typename Real<P>::T;
-    using RX = typename Real<XP>::T;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= Vh) return;
-    const cx<double> al = cdiv(ld_c(sc, rho_slot(iter)), ld_c(sc, S_RQ));
-    const cx<RX> alx = {(RX)al.re, (RX)al.im};
-    Spinor<RX> xv = SpinorIO<XP>::load(x, Vh, i);
-    const Spinor<R> pv = SpinorIO<P>::load(p, Vh, i);
-#pragma unroll
-    for (int k = 0; k < 12; k++) xv.c[k] = xv.c[k] + alx * cx<RX>{(RX)pv.c[k].re, (RX)pv.c[k].im};
-    SpinorIO<XP>::store(x, Vh, i, xv);
-}
-
-// v = ||src|| x  (Algorithm 2, last step), into FP64
-template <int XP>
-__global__ __launch_bounds__(kBlock) void k_inner_final(int Vh, void *v, const void *x, const double *sc) {
-    using RX = typename Real<XP>::T;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= Vh) return;
-    const double nrm = sqrt(sc[S_NORM]);
-    const Spinor<RX> xv = SpinorIO<XP>::load(x, Vh, i);
-    Spinor<double> o;
-#pragma unroll
-    for (int k = 0; k < 12; k++) o.c[k] = {nrm * (double)xv.c[k].re, nrm * (double)xv.c[k].im};
-    SpinorIO<P64>::store(v, Vh, i, o);
-}
-
-// ------------------------------------------------------------------ Algorithm 1 (FP64)
-// alpha = rho0 / <r~, q>;  x += alpha v;  r -= alpha q;  ||r||^2
-__global__ __launch_bounds__(kBlock) void k_outer_a(int Vh, void *x, void *r, const void *v, const void *q,
-                                                    const double *sc, int iter, double *partials) {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    const cx<double> al = cdiv(ld_c(sc, rho_slot(iter)), ld_c(sc, S_RQ));
-    double a[1] = {0.0};
-    if (i < Vh) {
-        Spinor<double> xv = SpinorIO<P64>::load(x, Vh, i);
-        Spinor<double> rv = SpinorIO<P64>::load(r, Vh, i);
-        const Spinor<double> vv = SpinorIO<P64>::load(v, Vh, i);
-        const Spinor<double> qv = SpinorIO<P64>::load(q, Vh, i);
-#pragma unroll
-        for (int k = 0; k < 12; k++) {
-            xv.c[k] = xv.c[k] + al * vv.c[k];
-            rv.c[k] = rv.c[k] - al * qv.c[k];
-            a[0] += norm2(rv.c[k]);
-        }
-        SpinorIO<P64>::store(x, Vh, i, xv);
-        SpinorIO<P64>::store(r, Vh, i, rv);
-    }
-    block_partials<1>(a, partials);
-}
-
-// omega = <t, r> / ||t||^2;  x += omega v;  r -= omega t;  ||r||^2, rho1 = <r~, r>
-__global__ __launch_bounds__(kBlock) void k_outer_b(int Vh, void *x, void *r, const void *v, const void *t,
-                                                    const void *rt, const double *sc, double *partials) {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    const double tt = sc[S_TT];
-    const cx<double> om = {sc[S_ST] / tt, -sc[S_ST + 1] / tt};
-    double a[3] = {0.0, 0.0, 0.0};
-    if (i < Vh) {
-        Spinor<double> xv = SpinorIO<P64>::load(x, Vh, i);
-        Spinor<double> rv = SpinorIO<P64>::load(r, Vh, i);
-        const Spinor<double> vv = SpinorIO<P64>::load(v, Vh, i);
-        const Spinor<double> tv = SpinorIO<P64>::load(t, Vh, i);
-        const Spinor<double> rtv = SpinorIO<P64>::load(rt, Vh, i);
-#pragma unroll
-        for (int k = 0; k < 12; k++) {
-            xv.c[k] = xv.c[k] + om * vv.c[k];
-            rv.c[k] = rv.c[k] - om * tv.c[k];
-            a[0] += norm2(rv.c[k]);
-            const double ar = rtv.c[k].re, ai = rtv.c[k].im, br = rv.c[k].re, bi = rv.c[k].im;
-            a[1] += ar * br + ai * bi;
-            a[2] += ar * bi - ai * br;
-        }
-        SpinorIO<P64>::store(x, Vh, i, xv);
-        SpinorIO<P64>::store(r, Vh, i, rv);
-    }
-    block_partials<3>(a, partials);
+    if (N > 0) block_partials<NA>(a, c.partials, (Vh + kBlock - 1) / kBlock, lb);
 }
 
 // ------------------------------------------------------------------ reduction stage 2
-template <int N> __global__ __launch_bounds__(kBlock) void k_finalize(FinArgs f) {
+struct FinBatch {
+    FinArgs f[kMaxSys];
+};
+
+template <int N> __global__ __launch_bounds__(kBlock) void k_finalize(FinBatch B) {
+    const FinArgs &f = B.f[blockIdx.x];
     if (f.guard && *f.guard) return;
     __shared__ double sh[N][kWaves];
     double a[N];
@@ -273,6 +257,7 @@ template <int N> __global__ __launch_bounds__(kBlock) void k_finalize(FinArgs f)
     if (threadIdx.x != 0) return;
     double *sc = f.sc;
     int *fl = f.fl;
+    const double a1 = a[1 % N], a2 = a[2 % N];
     switch (f.op) {
     case FIN_STORE:
         for (int k = 0; k < N; k++) f.result[k] = a[k];
@@ -295,10 +280,10 @@ template <int N> __global__ __launch_bounds__(kBlock) void k_finalize(FinArgs f)
         const double tt = sc[S_TT];
         const cx<double> om = {sc[S_ST] / tt, -sc[S_ST + 1] / tt};
         sc[S_RR] = a[0];
-        sc[nxt] = a[1];
-        sc[nxt + 1] = a[2];
+        sc[nxt] = a1;
+        sc[nxt + 1] = a2;
         fl[F_ITERS] = f.iter + 1;
-        if (!(tt > 0.0) || !finite_c(om) || !isfinite(a[0]) || (a[1] == 0.0 && a[2] == 0.0))
+        if (!(tt > 0.0) || !finite_c(om) || !isfinite(a[0]) || (a1 == 0.0 && a2 == 0.0))
             fl[F_DONE] = (a[0] < f.tol2) ? DONE_FULL : DONE_BREAK;
         else if (a[0] < f.tol2)
             fl[F_DONE] = DONE_FULL;
@@ -307,8 +292,8 @@ template <int N> __global__ __launch_bounds__(kBlock) void k_finalize(FinArgs f)
     case FIN_OUTER_B: {
         const int nxt = rho_slot(f.iter + 1);
         sc[S_RR] = a[0];
-        sc[nxt] = a[1];
-        sc[nxt + 1] = a[2];
+        sc[nxt] = a1;
+        sc[nxt + 1] = a2;
         break;
     }
     }
@@ -316,196 +301,115 @@ template <int N> __global__ __launch_bounds__(kBlock) void k_finalize(FinArgs f)
 
 inline int nblk(int Vh) { return (Vh + kBlock - 1) / kBlock; }
 
-template <class F> int timed_blas(wc_lattice *lat, double bytes, F &&launch) {
-    TimedLaunch t;
-    if (lat->timing) timing_begin(lat, KS_BLAS, bytes, t);
-    launch();
-    WC_HIP(hipGetLastError());
-    if (lat->timing) timing_end(lat, t);
-    return WC_OK;
+// algorithmic bytes of one op on one system (vectors read and written)
+double vec_bytes(int op, int prec, int xprec, int Vh) {
+    const double S = (double)spinor_bytes(prec, Vh), X = (double)spinor_bytes(xprec, Vh),
+                 D = (double)spinor_bytes(P64, Vh);
+    switch (op) {
+    case V_NORM2: return D;
+    case V_SUB_NORM: return 3 * D;
+    case V_AXPY: return 3 * D;
+    case V_COPY: return 2 * D;
+    case V_ZERO: return D;
+    case V_GAMMA5: return 4 * D;
+    case V_INNER_INIT: return D + 3 * S + X;
+    case V_INNER_A: return 3 * S;
+    case V_INNER_B: return 5 * S + 2 * X;
+    case V_INNER_C: return 4 * S;
+    case V_INNER_FIX: return S + 2 * X;
+    case V_INNER_FINAL: return X + D;
+    case V_OUTER_A: return 6 * D;
+    case V_OUTER_B: return 7 * D;
+    }
+    return 0;
 }
 
-inline double S(int prec, int Vh) { return (double)spinor_bytes(prec, Vh); }
+template <int OP, int P, int XP> void launch_op(hipStream_t s, const VecBatch &B, int blocks) {
+    hipLaunchKernelGGL((k_vec<OP, P, XP>), dim3(blocks), dim3(kBlock), 0, s, B);
+}
+
+// the inner-loop ops exist for every storage precision; x is FP32 for the
+// FP32 and FP16 inner loops and FP64 for the all-FP64 loop
+template <int OP> void dispatch_inner(hipStream_t s, const VecBatch &B, int blocks, int prec) {
+    if (prec == P64) launch_op<OP, P64, P64>(s, B, blocks);
+    else if (prec == P32) launch_op<OP, P32, P32>(s, B, blocks);
+    else launch_op<OP, P16, P32>(s, B, blocks);
+}
 
 }  // namespace
 
-int launch_finalize(wc_lattice *lat, const FinArgs &f) {
-    switch (f.n) {
-    case 1: hipLaunchKernelGGL(k_finalize<1>, dim3(1), dim3(kBlock), 0, lat->stream, f); break;
-    case 2: hipLaunchKernelGGL(k_finalize<2>, dim3(1), dim3(kBlock), 0, lat->stream, f); break;
-    default: hipLaunchKernelGGL(k_finalize<3>, dim3(1), dim3(kBlock), 0, lat->stream, f); break;
+int launch_fin_batch(hipStream_t s, const FinArgs *f, int n, int nvals) {
+    if (n <= 0) return WC_OK;
+    FinBatch B;
+    for (int k = 0; k < n; k++) B.f[k] = f[k];
+    switch (nvals) {
+    case 1: hipLaunchKernelGGL(k_finalize<1>, dim3(n), dim3(kBlock), 0, s, B); break;
+    case 2: hipLaunchKernelGGL(k_finalize<2>, dim3(n), dim3(kBlock), 0, s, B); break;
+    default: hipLaunchKernelGGL(k_finalize<3>, dim3(n), dim3(kBlock), 0, s, B); break;
     }
     WC_HIP(hipGetLastError());
     return WC_OK;
 }
 
-static FinArgs fin(wc_lattice *lat, int n, int op, int lvl, double *result, const int *guard, int iter) {
-    FinArgs f{};
-    f.n = n;
-    f.blocks = nblk(lat->Vh);
-    f.op = op;
-    f.partials = lat->partials;
-    f.result = result;
-    f.sc = lat->level_scalars(lvl);
-    f.fl = lat->level_flags(lvl);
-    f.guard = guard;
-    f.iter = iter;
-    f.tol2 = lat->host_tol2[lvl];
-    return f;
-}
-
-int launch_norm2_p64(wc_lattice *lat, const void *v, RedTarget to) {
-    int rc = timed_blas(lat, S(P64, lat->Vh), [&] {
-        hipLaunchKernelGGL(k_norm2_p64, dim3(nblk(lat->Vh)), dim3(kBlock), 0, lat->stream, lat->Vh, v, to);
-    });
-    if (rc) return rc;
-    return launch_finalize(lat, fin(lat, 2, FIN_STORE, 0, to.result, nullptr, 0));
-}
-
-int launch_sub_norm_p64(wc_lattice *lat, void *r, const void *a, const void *b, RedTarget to) {
-    int rc = timed_blas(lat, 3 * S(P64, lat->Vh), [&] {
-        hipLaunchKernelGGL(k_sub_norm_p64, dim3(nblk(lat->Vh)), dim3(kBlock), 0, lat->stream, lat->Vh, r, a, b, to);
-    });
-    if (rc) return rc;
-    return launch_finalize(lat, fin(lat, 1, FIN_STORE, 0, to.result, nullptr, 0));
-}
-
-int launch_axpy_p64(wc_lattice *lat, void *y, const void *x, double a) {
-    return timed_blas(lat, 3 * S(P64, lat->Vh), [&] {
-        hipLaunchKernelGGL(k_axpy_p64, dim3(nblk(lat->Vh)), dim3(kBlock), 0, lat->stream, lat->Vh, y, x, a);
-    });
-}
-
-int launch_copy(wc_lattice *lat, void *dst, const void *src, size_t bytes) {
-    WC_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, lat->stream));
-    return WC_OK;
-}
-
-int launch_zero(wc_lattice *lat, void *dst, size_t bytes) {
-    // sizes here are multiples of 16 bytes (every field is a whole number of uint4)
-    const size_t n16 = bytes / 16;
-    const unsigned blocks = (unsigned)((n16 + kBlock - 1) / kBlock);
-    if (blocks == 0) return WC_OK;
-    hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(kBlock), 0, lat->stream, n16, (uint4 *)dst);
+int launch_vec_batch(hipStream_t s, wc_lattice *tlat, int op, int prec, const VecCall *calls, int n) {
+    if (n <= 0) return WC_OK;
+    if (n > kMaxSys) return wc_fail(WC_EINVAL, "too many systems in one batch");
+    VecBatch B;
+    B.h.S = n;
+    B.h.interleave = 0;
+    B.h.off[0] = 0;
+    const int xprec = prec == P64 ? P64 : P32;
+    double bytes = 0;
+    for (int k = 0; k < n; k++) {
+        B.c[k] = calls[k];
+        B.h.off[k + 1] = B.h.off[k] + nblk(calls[k].Vh);
+        bytes += vec_bytes(op, prec, xprec, calls[k].Vh);
+    }
+    const int blocks = B.h.off[n];
+    TimedLaunch t;
+    if (tlat && tlat->timing) timing_begin(tlat, KS_BLAS, bytes, t);
+    switch (op) {
+    case V_NORM2: launch_op<V_NORM2, P64, P64>(s, B, blocks); break;
+    case V_SUB_NORM: launch_op<V_SUB_NORM, P64, P64>(s, B, blocks); break;
+    case V_AXPY: launch_op<V_AXPY, P64, P64>(s, B, blocks); break;
+    case V_COPY: launch_op<V_COPY, P64, P64>(s, B, blocks); break;
+    case V_ZERO: launch_op<V_ZERO, P64, P64>(s, B, blocks); break;
+    case V_GAMMA5: launch_op<V_GAMMA5, P64, P64>(s, B, blocks); break;
+    case V_INNER_INIT: dispatch_inner<V_INNER_INIT>(s, B, blocks, prec); break;
+    case V_INNER_A: dispatch_inner<V_INNER_A>(s, B, blocks, prec); break;
+    case V_INNER_B: dispatch_inner<V_INNER_B>(s, B, blocks, prec); break;
+    case V_INNER_C: dispatch_inner<V_INNER_C>(s, B, blocks, prec); break;
+    case V_INNER_FIX: dispatch_inner<V_INNER_FIX>(s, B, blocks, prec); break;
+    case V_INNER_FINAL: dispatch_inner<V_INNER_FINAL>(s, B, blocks, prec); break;
+    case V_OUTER_A: launch_op<V_OUTER_A, P64, P64>(s, B, blocks); break;
+    case V_OUTER_B: launch_op<V_OUTER_B, P64, P64>(s, B, blocks); break;
+    default: return wc_fail(WC_EINVAL, "unknown vector op");
+    }
     WC_HIP(hipGetLastError());
-    return WC_OK;
-}
+    if (tlat && tlat->timing) timing_end(tlat, t);
 
-#define WC_PREC_SWITCH(prec, BODY)      \
-    do {                                \
-        if ((prec) == P64) {            \
-            constexpr int PP = P64;     \
-            BODY;                       \
-        } else if ((prec) == P32) {     \
-            constexpr int PP = P32;     \
-            BODY;                       \
-        } else {                        \
-            constexpr int PP = P16;     \
-            BODY;                       \
-        }                               \
-    } while (0)
-
-#define WC_XPREC_SWITCH(xprec, BODY)    \
-    do {                                \
-        if ((xprec) == P64) {           \
-            constexpr int XX = P64;     \
-            BODY;                       \
-        } else {                        \
-            constexpr int XX = P32;     \
-            BODY;                       \
-        }                               \
-    } while (0)
-
-int launch_inner_init(wc_lattice *lat, int prec, int xprec, const void *src64, void *r, void *rt, void *p, void *x,
-                      int lvl) {
-    const int Vh = lat->Vh;
-    const double *sc = lat->level_scalars(lvl);
-    double *part = lat->partials;
-    int rc = timed_blas(lat, S(P64, Vh) + 3 * S(prec, Vh) + S(xprec, Vh), [&] {
-        WC_PREC_SWITCH(prec, WC_XPREC_SWITCH(xprec, hipLaunchKernelGGL((k_inner_init<PP, XX>), dim3(nblk(Vh)),
-                                                                        dim3(kBlock), 0, lat->stream, Vh, src64, r,
-                                                                        rt, p, x, sc, part)));
-    });
-    if (rc) return rc;
-    return launch_finalize(lat, fin(lat, 1, FIN_INIT, lvl, nullptr, nullptr, 0));
-}
-
-int launch_inner_a(wc_lattice *lat, int prec, void *r, const void *q, int iter, int lvl) {
-    const int Vh = lat->Vh;
-    const double *sc = lat->level_scalars(lvl);
-    const int *fl = lat->level_flags(lvl);
-    double *part = lat->partials;
-    int rc = timed_blas(lat, 3 * S(prec, Vh), [&] {
-        WC_PREC_SWITCH(prec, hipLaunchKernelGGL((k_inner_a<PP>), dim3(nblk(Vh)), dim3(kBlock), 0, lat->stream, Vh,
-                                                r, q, sc, fl, iter, part));
-    });
-    if (rc) return rc;
-    return launch_finalize(lat, fin(lat, 1, FIN_INNER_A, lvl, nullptr, fl, iter));
-}
-
-int launch_inner_b(wc_lattice *lat, int prec, int xprec, void *x, void *r, const void *p, const void *t,
-                   const void *rt, int iter, int lvl) {
-    const int Vh = lat->Vh;
-    const double *sc = lat->level_scalars(lvl);
-    const int *fl = lat->level_flags(lvl);
-    double *part = lat->partials;
-    int rc = timed_blas(lat, 5 * S(prec, Vh) + 2 * S(xprec, Vh), [&] {
-        WC_PREC_SWITCH(prec, WC_XPREC_SWITCH(xprec, hipLaunchKernelGGL((k_inner_b<PP, XX>), dim3(nblk(Vh)),
-                                                                        dim3(kBlock), 0, lat->stream, Vh, x, r, p, t,
-                                                                        rt, sc, fl, iter, part)));
-    });
-    if (rc) return rc;
-    return launch_finalize(lat, fin(lat, 3, FIN_INNER_B, lvl, nullptr, fl, iter));
-}
-
-int launch_inner_c(wc_lattice *lat, int prec, void *p, const void *r, const void *q, int iter, int lvl, bool guard) {
-    const int Vh = lat->Vh;
-    const double *sc = lat->level_scalars(lvl);
-    const int *fl = guard ? lat->level_flags(lvl) : nullptr;
-    return timed_blas(lat, 4 * S(prec, Vh), [&] {
-        WC_PREC_SWITCH(prec, hipLaunchKernelGGL((k_inner_c<PP>), dim3(nblk(Vh)), dim3(kBlock), 0, lat->stream, Vh,
-                                                p, r, q, sc, fl, iter));
-    });
-}
-
-int launch_inner_fix(wc_lattice *lat, int prec, int xprec, void *x, const void *p, int iter, int lvl) {
-    const int Vh = lat->Vh;
-    const double *sc = lat->level_scalars(lvl);
-    return timed_blas(lat, S(prec, Vh) + 2 * S(xprec, Vh), [&] {
-        WC_PREC_SWITCH(prec, WC_XPREC_SWITCH(xprec, hipLaunchKernelGGL((k_inner_fix<PP, XX>), dim3(nblk(Vh)),
-                                                                        dim3(kBlock), 0, lat->stream, Vh, x, p, sc,
-                                                                        iter)));
-    });
-}
-
-int launch_inner_final(wc_lattice *lat, int xprec, void *v64, const void *x, int lvl) {
-    const int Vh = lat->Vh;
-    const double *sc = lat->level_scalars(lvl);
-    return timed_blas(lat, S(xprec, Vh) + S(P64, Vh), [&] {
-        WC_XPREC_SWITCH(xprec, hipLaunchKernelGGL((k_inner_final<XX>), dim3(nblk(Vh)), dim3(kBlock), 0, lat->stream,
-                                                  Vh, v64, x, sc));
-    });
-}
-
-int launch_outer_a(wc_lattice *lat, void *x, void *r, const void *v, const void *q, int iter, int lvl) {
-    const int Vh = lat->Vh;
-    const double *sc = lat->level_scalars(lvl);
-    double *part = lat->partials;
-    int rc = timed_blas(lat, 6 * S(P64, Vh), [&] {
-        hipLaunchKernelGGL(k_outer_a, dim3(nblk(Vh)), dim3(kBlock), 0, lat->stream, Vh, x, r, v, q, sc, iter, part);
-    });
-    if (rc) return rc;
-    return launch_finalize(lat, fin(lat, 1, FIN_STORE, lvl, lat->level_scalars(lvl) + S_RR, nullptr, iter));
-}
-
-int launch_outer_b(wc_lattice *lat, void *x, void *r, const void *v, const void *t, const void *rt, int iter,
-                   int lvl) {
-    const int Vh = lat->Vh;
-    const double *sc = lat->level_scalars(lvl);
-    double *part = lat->partials;
-    int rc = timed_blas(lat, 7 * S(P64, Vh), [&] {
-        hipLaunchKernelGGL(k_outer_b, dim3(nblk(Vh)), dim3(kBlock), 0, lat->stream, Vh, x, r, v, t, rt, sc, part);
-    });
-    if (rc) return rc;
-    return launch_finalize(lat, fin(lat, 3, FIN_OUTER_B, lvl, nullptr, nullptr, iter));
+    // second stage of the reductions
+    const int N = red_count(op);
+    if (N == 0) return WC_OK;
+    FinArgs f[kMaxSys];
+    for (int k = 0; k < n; k++) {
+        const VecCall &c = calls[k];
+        FinArgs &a = f[k];
+        a = FinArgs{};
+        a.blocks = nblk(c.Vh);
+        a.partials = c.partials;
+        a.result = c.result;
+        a.sc = c.sc;
+        a.fl = c.fl;
+        a.guard = c.guard ? c.fl : nullptr;
+        a.iter = c.iter;
+        a.tol2 = c.tol2;
+        a.op = (op == V_INNER_INIT) ? FIN_INIT
+             : (op == V_INNER_A)    ? FIN_INNER_A
+             : (op == V_INNER_B)    ? FIN_INNER_B
+             : (op == V_OUTER_B)    ? FIN_OUTER_B
+                                    : FIN_STORE;
+        if (op == V_OUTER_A) a.result = c.sc + S_RR;
+    }
+    return launch_fin_batch(s, f, n, N);
 }

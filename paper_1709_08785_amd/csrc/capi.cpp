@@ -2,11 +2,12 @@
 // applications and the per-kernel event timing.  Solvers live in solver.cpp.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "internal.hpp"
-#include "work.hpp"
 
 static thread_local std::string g_last_error;
 
@@ -18,27 +19,98 @@ int wc_fail(int code, const std::string &msg) {
 extern "C" const char *wc_last_error(void) { return g_last_error.c_str(); }
 
 // ---------------------------------------------------------------------------
-// work buffers
+// allocation helpers
 // ---------------------------------------------------------------------------
-int work_get(wc_lattice *lat, int id, size_t bytes, void **out) {
-    if (lat->work[id] && lat->work_bytes[id] >= bytes) {
-        *out = lat->work[id];
-        return WC_OK;
-    }
-    if (lat->work[id]) {
-        WC_HIP(hipStreamSynchronize(lat->stream));
-        WC_HIP(hipFree(lat->work[id]));
-        lat->work[id] = nullptr;
-        lat->work_bytes[id] = 0;
-    }
-    void *p = nullptr;
-    if (hipMalloc(&p, bytes) != hipSuccess) {
+int dev_alloc(void **p, size_t bytes) {
+    if (hipMalloc(p, bytes) != hipSuccess) {
         (void)hipGetLastError();
-        return wc_fail(WC_ENOMEM, "work buffer allocation of " + std::to_string(bytes) + " bytes failed");
+        *p = nullptr;
+        return wc_fail(WC_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
     }
-    lat->work[id] = p;
-    lat->work_bytes[id] = bytes;
-    *out = p;
+    return WC_OK;
+}
+
+int buf_get(void **slot, size_t *have, size_t bytes, hipStream_t s) {
+    if (*slot && *have >= bytes) return WC_OK;
+    if (*slot) {
+        WC_HIP(hipStreamSynchronize(s));
+        WC_HIP(hipFree(*slot));
+        *slot = nullptr;
+        *have = 0;
+    }
+    if (int rc = dev_alloc(slot, bytes)) return rc;
+    *have = bytes;
+    return WC_OK;
+}
+
+int arena_alloc(Arena &a, int S, hipStream_t s) {
+    a.S = S;
+    const size_t nd = sizeof(double) * NUM_LEVELS * S_COUNT * S, ni = sizeof(int) * NUM_LEVELS * F_COUNT * S;
+    if (int rc = dev_alloc((void **)&a.scalars, nd)) return rc;
+    if (int rc = dev_alloc((void **)&a.flags, ni)) return rc;
+    if (hipHostMalloc((void **)&a.h_scalars, nd, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&a.h_flags, ni, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return wc_fail(WC_ENOMEM, "pinned host allocation failed");
+    }
+    std::memset(a.h_scalars, 0, nd);
+    std::memset(a.h_flags, 0, ni);
+    WC_HIP(hipMemsetAsync(a.scalars, 0, nd, s));
+    WC_HIP(hipMemsetAsync(a.flags, 0, ni, s));
+    return WC_OK;
+}
+
+void arena_free(Arena &a) {
+    if (a.scalars) (void)hipFree(a.scalars);
+    if (a.flags) (void)hipFree(a.flags);
+    if (a.h_scalars) (void)hipHostFree(a.h_scalars);
+    if (a.h_flags) (void)hipHostFree(a.h_flags);
+    a = Arena{};
+}
+
+void arena_bind(Arena &a, int k, SysState &st) {
+    st.scalars = a.scalars + (size_t)k * NUM_LEVELS * S_COUNT;
+    st.flags = a.flags + (size_t)k * NUM_LEVELS * F_COUNT;
+    st.h_scalars = a.h_scalars + (size_t)k * NUM_LEVELS * S_COUNT;
+    st.h_flags = a.h_flags + (size_t)k * NUM_LEVELS * F_COUNT;
+}
+
+int sync_arena(const Arena &a, hipStream_t s) {
+    WC_HIP(hipMemcpyAsync(a.h_scalars, a.scalars, sizeof(double) * NUM_LEVELS * S_COUNT * a.S, hipMemcpyDeviceToHost,
+                          s));
+    WC_HIP(hipMemcpyAsync(a.h_flags, a.flags, sizeof(int) * NUM_LEVELS * F_COUNT * a.S, hipMemcpyDeviceToHost, s));
+    WC_HIP(hipStreamSynchronize(s));
+    return WC_OK;
+}
+
+static int lwork(wc_lattice *lat, int id, size_t bytes, void **out) {
+    if (int rc = buf_get(&lat->lwork[id], &lat->lwork_bytes[id], bytes, lat->stream)) return rc;
+    *out = lat->lwork[id];
+    return WC_OK;
+}
+
+static void free_work(SysWork &w) {
+    for (int k = 0; k < W_SYS_COUNT; k++)
+        if (w.buf[k]) (void)hipFree(w.buf[k]);
+    w = SysWork{};
+}
+
+static void free_batch(BatchCache *b) {
+    if (!b) return;
+    arena_free(b->arena);
+    for (auto &st : b->sys)
+        if (st.partials) (void)hipFree(st.partials);
+    for (auto &w : b->work) free_work(w);
+    delete b;
+}
+
+// allocate (or keep) the solve vectors of one system on lattice lat
+static int ensure_work(wc_lattice *lat, SysWork &w, int iprec) {
+    const size_t d = spinor_bytes(P64, lat->Vh), i = spinor_bytes(iprec, lat->Vh),
+                 x = spinor_bytes(iprec == P64 ? P64 : P32, lat->Vh);
+    const size_t need[W_SYS_COUNT] = {2 * d, 2 * d, d, d, d, d, d, d, d, d, d, i, i, i, i, i, i, x};
+    for (int k = 0; k < W_SYS_COUNT; k++)
+        if (int rc = buf_get(&w.buf[k], &w.bytes[k], need[k], lat->stream)) return rc;
     return WC_OK;
 }
 
@@ -132,27 +204,18 @@ static void free_all(wc_lattice *lat) {
         if (lat->clov[p]) (void)hipFree(lat->clov[p]);
         if (lat->clovinv[p]) (void)hipFree(lat->clovinv[p]);
     }
-    for (int k = 0; k < 32; k++)
-        if (lat->work[k]) (void)hipFree(lat->work[k]);
-    if (lat->partials) (void)hipFree(lat->partials);
-    if (lat->scalars) (void)hipFree(lat->scalars);
-    if (lat->flags) (void)hipFree(lat->flags);
-    if (lat->host_scalars) (void)hipHostFree(lat->host_scalars);
-    if (lat->host_flags) (void)hipHostFree(lat->host_flags);
+    for (int k = 0; k < LW_COUNT; k++)
+        if (lat->lwork[k]) (void)hipFree(lat->lwork[k]);
+    free_work(lat->swork);
+    if (lat->sys.partials) (void)hipFree(lat->sys.partials);
+    arena_free(lat->arena);
+    free_batch(lat->batch);
+    lat->batch = nullptr;
     for (auto &t : lat->launches) {
         (void)hipEventDestroy(t.a);
         (void)hipEventDestroy(t.b);
     }
     for (auto e : lat->event_pool) (void)hipEventDestroy(e);
-}
-
-static int dev_alloc(void **p, size_t bytes) {
-    if (hipMalloc(p, bytes) != hipSuccess) {
-        (void)hipGetLastError();
-        *p = nullptr;
-        return wc_fail(WC_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
-    }
-    return WC_OK;
 }
 
 extern "C" int wc_create_lattice(const int dims[4], void *stream, wc_lattice **out) {
@@ -176,31 +239,18 @@ extern "C" int wc_create_lattice(const int dims[4], void *stream, wc_lattice **o
     lat->g.Lxh = dims[0] / 2;
     lat->g.Vh = lat->Vh;
     lat->stream = (hipStream_t)stream;
-    lat->max_blocks = (lat->Vh + 255) / 256;
-    int rc = WC_OK;
-    if ((rc = dev_alloc((void **)&lat->partials, sizeof(double) * 8 * (size_t)lat->max_blocks)) ||
-        (rc = dev_alloc((void **)&lat->scalars, sizeof(double) * NUM_LEVELS * S_COUNT)) ||
-        (rc = dev_alloc((void **)&lat->flags, sizeof(int) * NUM_LEVELS * F_COUNT))) {
+    lat->nblocks = (lat->Vh + 255) / 256;
+    int rc = arena_alloc(lat->arena, 1, lat->stream);
+    if (!rc) {
+        arena_bind(lat->arena, 0, lat->sys);
+        rc = dev_alloc((void **)&lat->sys.partials, sizeof(double) * 8 * (size_t)lat->nblocks);
+    }
+    if (!rc && hipStreamSynchronize(lat->stream) != hipSuccess)
+        rc = wc_fail(WC_EHIP, std::string("initialising lattice scratch: ") + hipGetErrorString(hipGetLastError()));
+    if (rc) {
         free_all(lat);
         delete lat;
         return rc;
-    }
-    if (hipHostMalloc((void **)&lat->host_scalars, sizeof(double) * NUM_LEVELS * S_COUNT, hipHostMallocDefault) !=
-            hipSuccess ||
-        hipHostMalloc((void **)&lat->host_flags, sizeof(int) * NUM_LEVELS * F_COUNT, hipHostMallocDefault) !=
-            hipSuccess) {
-        (void)hipGetLastError();
-        free_all(lat);
-        delete lat;
-        return wc_fail(WC_ENOMEM, "pinned host allocation failed");
-    }
-    if (hipMemsetAsync(lat->scalars, 0, sizeof(double) * NUM_LEVELS * S_COUNT, lat->stream) != hipSuccess ||
-        hipMemsetAsync(lat->flags, 0, sizeof(int) * NUM_LEVELS * F_COUNT, lat->stream) != hipSuccess ||
-        hipStreamSynchronize(lat->stream) != hipSuccess) {
-        std::string m = hipGetErrorString(hipGetLastError());
-        free_all(lat);
-        delete lat;
-        return wc_fail(WC_EHIP, "initialising lattice scratch: " + m);
     }
     *out = lat;
     return WC_OK;
@@ -228,6 +278,138 @@ extern "C" void wc_solve_params_default(wc_solve_params *p) {
     p->fixed_work = 0;
     p->check_every = 8;
     p->adjoint = 0;
+}
+
+static int check_params(const wc_solve_params &P, double tol) {
+    if (!(tol > 0.0) || !(tol < 1.0)) return wc_fail(WC_EINVAL, "tol must lie in (0, 1)");
+    if (P.inner_prec < 0 || P.inner_prec > 2) return wc_fail(WC_EINVAL, "bad inner precision");
+    if (P.inner_maxit < 1 || P.outer_maxit < 1 || P.check_every < 1 || P.fixed_work < 0 || P.inner_tol < 0.0 ||
+        P.inner_tol >= 1.0)
+        return wc_fail(WC_EINVAL, "bad solver parameters");
+    return WC_OK;
+}
+
+static int prepare_lattice(wc_lattice *lat, double kappa, double csw) {
+    if (!lat->have_links) return wc_fail(WC_ENOTREADY, "solve before wc_load_links");
+    if (!lat->have_clover || lat->kappa != kappa || lat->csw != csw)
+        if (int rc = wc_build_clover(lat, kappa, csw)) return rc;
+    return WC_OK;
+}
+
+static int report(std::vector<SolveSys> &sys, wc_solve_info *info) {
+    int worst = WC_OK;
+    for (size_t k = 0; k < sys.size(); k++) {
+        if (info) info[k] = sys[k].info;
+        if (sys[k].status != WC_OK && worst == WC_OK) worst = sys[k].status;
+    }
+    if (worst != WC_OK) {
+        double r = 0;
+        for (auto &s : sys) r = std::max(r, s.info.true_rel_residual);
+        return wc_fail(worst, "solve stopped at true relative residual " + std::to_string(r));
+    }
+    return WC_OK;
+}
+
+extern "C" int wc_solve(wc_lattice *lat, const void *b_dev, double kappa, double csw, double tol,
+                        const wc_solve_params *pin, void *x_dev, int x0_is_guess, wc_solve_info *info) {
+    if (!lat || !b_dev || !x_dev) return wc_fail(WC_EINVAL, "null argument");
+    wc_solve_params P;
+    wc_solve_params_default(&P);
+    if (pin) P = *pin;
+    if (int rc = check_params(P, tol)) return rc;
+    if (int rc = prepare_lattice(lat, kappa, csw)) return rc;
+    if (int rc = ensure_work(lat, lat->swork, P.inner_prec)) return rc;
+    std::vector<SolveSys> sys(1);
+    sys[0].lat = lat;
+    sys[0].st = &lat->sys;
+    sys[0].work = &lat->swork;
+    sys[0].b_dev = b_dev;
+    sys[0].x_dev = x_dev;
+    sys[0].kappa = kappa;
+    sys[0].csw = csw;
+    if (int rc = solve_systems(sys, lat->arena, tol, P, x0_is_guess)) return rc;
+    return report(sys, info);
+}
+
+extern "C" int wc_solve_multi(int n, wc_lattice *const *lats, const void *const *b_dev, void *const *x_dev,
+                              const double *kappa, const double *csw, double tol, const wc_solve_params *pin,
+                              wc_solve_info *info) {
+    if (n < 1 || n > kMaxSys) return wc_fail(WC_EINVAL, "n must lie in [1, 16]");
+    if (!lats || !b_dev || !x_dev || !kappa || !csw) return wc_fail(WC_EINVAL, "null argument");
+    for (int k = 0; k < n; k++)
+        if (!lats[k] || !b_dev[k] || !x_dev[k]) return wc_fail(WC_EINVAL, "null lattice or field");
+    wc_solve_params P;
+    wc_solve_params_default(&P);
+    if (pin) P = *pin;
+    if (int rc = check_params(P, tol)) return rc;
+    for (int k = 0; k < n; k++) {
+        for (int j = 0; j < k; j++)
+            if (lats[j] == lats[k] && (kappa[j] != kappa[k] || csw[j] != csw[k]))
+                return wc_fail(WC_EINVAL, "systems on one lattice must share kappa and csw");
+        if (int rc = prepare_lattice(lats[k], kappa[k], csw[k])) return rc;
+    }
+    wc_lattice *lead = lats[0];
+    // every lattice works on the lead lattice's stream for the duration
+    std::vector<hipStream_t> saved(n);
+    for (int k = 0; k < n; k++) saved[k] = lats[k]->stream;
+    for (int k = 0; k < n; k++) lats[k]->stream = lead->stream;
+    auto restore = [&] {
+        for (int k = 0; k < n; k++) lats[k]->stream = saved[k];
+    };
+    BatchCache *bc = lead->batch;
+    bool reuse = bc && (int)bc->lats.size() == n;
+    for (int k = 0; reuse && k < n; k++) reuse = bc->lats[k] == lats[k];
+    if (!reuse) {
+        free_batch(bc);
+        lead->batch = bc = new BatchCache();
+        bc->lats.assign(lats, lats + n);
+        bc->sys.resize(n);
+        bc->work.resize(n);
+        if (int rc = arena_alloc(bc->arena, n, lead->stream)) {
+            restore();
+            return rc;
+        }
+        for (int k = 0; k < n; k++) {
+            arena_bind(bc->arena, k, bc->sys[k]);
+            if (int rc = buf_get((void **)&bc->sys[k].partials, &bc->sys[k].partials_bytes,
+                                 sizeof(double) * 8 * (size_t)lats[k]->nblocks, lead->stream)) {
+                restore();
+                return rc;
+            }
+        }
+    }
+    std::vector<SolveSys> sys(n);
+    for (int k = 0; k < n; k++) {
+        if (int rc = ensure_work(lats[k], bc->work[k], P.inner_prec)) {
+            restore();
+            return rc;
+        }
+        sys[k].lat = lats[k];
+        sys[k].st = &bc->sys[k];
+        sys[k].work = &bc->work[k];
+        sys[k].b_dev = b_dev[k];
+        sys[k].x_dev = x_dev[k];
+        sys[k].kappa = kappa[k];
+        sys[k].csw = csw[k];
+    }
+    int rc = solve_systems(sys, bc->arena, tol, P, 0);
+    restore();
+    if (rc) return rc;
+    return report(sys, info);
+}
+
+extern "C" int wc_solve_batch(wc_lattice *lat, int n, const void *const *b_dev, void *const *x_dev, double kappa,
+                              double csw, double tol, const wc_solve_params *p, wc_solve_info *info) {
+    if (!lat) return wc_fail(WC_EINVAL, "null lattice");
+    if (n < 1 || n > kMaxSys) return wc_fail(WC_EINVAL, "n must lie in [1, 16]");
+    wc_lattice *lats[kMaxSys];
+    double ks[kMaxSys], cs[kMaxSys];
+    for (int k = 0; k < n; k++) {
+        lats[k] = lat;
+        ks[k] = kappa;
+        cs[k] = csw;
+    }
+    return wc_solve_multi(n, lats, b_dev, x_dev, ks, cs, tol, p, info);
 }
 
 extern "C" size_t wc_spinor_bytes(const wc_lattice *lat, int prec) {
@@ -321,8 +503,8 @@ extern "C" int wc_apply_D(wc_lattice *lat, void *out_dev, const void *in_dev, in
     if (int rc = check_ready(lat)) return rc;
     const size_t sb = spinor_bytes(prec, lat->Vh);
     void *in2, *out2;
-    if (int rc = work_get(lat, W_APPLY_IN, 2 * sb, &in2)) return rc;
-    if (int rc = work_get(lat, W_APPLY_OUT, 2 * sb, &out2)) return rc;
+    if (int rc = lwork(lat, LW_APPLY_IN, 2 * sb, &in2)) return rc;
+    if (int rc = lwork(lat, LW_APPLY_OUT, 2 * sb, &out2)) return rc;
     if (int rc = launch_pack_spinor(lat, prec, in2, in_dev)) return rc;
     for (int par = 0; par < 2; par++) {
         MultCall c = mult_call(prec, M_DFULL, par, (char *)out2 + par * sb, (const char *)in2 + (1 - par) * sb,
@@ -347,7 +529,7 @@ extern "C" int wc_apply_Dee_oo(wc_lattice *lat, void *out_e, const void *in_e, i
     if (out_e == in_e) return wc_fail(WC_EINVAL, "wc_apply_Dee_oo cannot work in place");
     if (int rc = check_ready(lat)) return rc;
     void *tmp;
-    if (int rc = work_get(lat, W_APPLY_TMP, spinor_bytes(prec, lat->Vh), &tmp)) return rc;
+    if (int rc = lwork(lat, LW_APPLY_TMP, spinor_bytes(prec, lat->Vh), &tmp)) return rc;
     MultCall c1 = mult_call(prec, M_HOPINV, 1, tmp, in_e, nullptr, 0.0);
     if (int rc = launch_mult(lat, c1)) return rc;
     MultCall c2 = mult_call(prec, M_DHAT, 0, out_e, tmp, in_e, -lat->kappa * lat->kappa);
@@ -371,11 +553,11 @@ extern "C" int wc_link_grad(wc_lattice *lat, const void *lam_dev, const void *x_
     if (!(kappa >= 0.0) || !(csw >= 0.0)) return wc_fail(WC_EINVAL, "need kappa >= 0 and csw >= 0");
     const size_t sb = spinor_bytes(P64, lat->Vh);
     void *lam, *x, *N = nullptr;
-    if (int rc = work_get(lat, W_GLAM, 2 * sb, &lam)) return rc;
-    if (int rc = work_get(lat, W_GX, 2 * sb, &x)) return rc;
+    if (int rc = lwork(lat, LW_GLAM, 2 * sb, &lam)) return rc;
+    if (int rc = lwork(lat, LW_GX, 2 * sb, &x)) return rc;
     const bool clover = include_clover && csw != 0.0;
     if (clover)
-        if (int rc = work_get(lat, W_GN, (size_t)6 * 2 * 9 * 16 * lat->Vh, &N)) return rc;
+        if (int rc = lwork(lat, LW_GN, (size_t)6 * 2 * 9 * 16 * lat->Vh, &N)) return rc;
     if (int rc = launch_pack_spinor(lat, P64, lam, lam_dev)) return rc;
     if (int rc = launch_pack_spinor(lat, P64, x, x_dev)) return rc;
     return launch_link_grad(lat, lam, x, gradU_dev, N, kappa, csw, clover);

@@ -34,6 +34,12 @@ struct MultKArgs {
     double coef;
     RedTarget red;
     const int *done;
+    int nblk;            // blocks of this system
+};
+
+struct MultBatch {
+    BatchHdr h;
+    MultKArgs d[kMaxSys];
 };
 
 // g = U h (dag = false) or U^dagger h (dag = true), two spin components
@@ -133,10 +139,13 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 }
 
 template <int P, int MODE, int RED>
-__global__ __launch_bounds__(kBlock) void k_mult(MultKArgs a) {
+__global__ __launch_bounds__(kBlock) void k_mult(MultBatch B) {
     using R = typename Real<P>::T;
+    int s, lb;
+    batch_locate(B.h, xcd_block(blockIdx.x, gridDim.x), s, lb);
+    const MultKArgs &a = B.d[s];
     if (a.done && *a.done) return;
-    const int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const int i = lb * kBlock + threadIdx.x;
     const bool active = i < a.g.Vh;
     const int Vh = a.g.Vh;
     Spinor<R> out;
@@ -193,32 +202,31 @@ __global__ __launch_bounds__(kBlock) void k_mult(MultKArgs a) {
                 if (N == 3) v[N - 1] += orr * orr + oi * oi;
             }
         }
-        block_partials<N>(v, a.red.partials);
+        block_partials<N>(v, a.red.partials, a.nblk, lb);
     }
 }
 
-template <int P, int MODE, int RED> void launch_one(const MultKArgs &a, int blocks, hipStream_t s) {
-    hipLaunchKernelGGL((k_mult<P, MODE, RED>), dim3(blocks), dim3(kBlock), 0, s, a);
+template <int P, int MODE, int RED> void launch_one(const MultBatch &B, int blocks, hipStream_t s) {
+    hipLaunchKernelGGL((k_mult<P, MODE, RED>), dim3(blocks), dim3(kBlock), 0, s, B);
 }
 
-template <int P> void dispatch_mode(const MultKArgs &a, int mode, int red, int blocks, hipStream_t s) {
+template <int P> void dispatch_mode(const MultBatch &B, int mode, int red, int blocks, hipStream_t s) {
     switch (mode) {
-    case M_HOPINV: launch_one<P, M_HOPINV, R_NONE>(a, blocks, s); break;
+    case M_HOPINV: launch_one<P, M_HOPINV, R_NONE>(B, blocks, s); break;
     case M_DHAT:
-        if (red == R_DOT) launch_one<P, M_DHAT, R_DOT>(a, blocks, s);
-        else if (red == R_DOTNORM) launch_one<P, M_DHAT, R_DOTNORM>(a, blocks, s);
-        else launch_one<P, M_DHAT, R_NONE>(a, blocks, s);
+        if (red == R_DOT) launch_one<P, M_DHAT, R_DOT>(B, blocks, s);
+        else if (red == R_DOTNORM) launch_one<P, M_DHAT, R_DOTNORM>(B, blocks, s);
+        else launch_one<P, M_DHAT, R_NONE>(B, blocks, s);
         break;
-    case M_DFULL: launch_one<P, M_DFULL, R_NONE>(a, blocks, s); break;
-    case M_INVSRC: launch_one<P, M_INVSRC, R_NONE>(a, blocks, s); break;
-    case M_HOP: launch_one<P, M_HOP, R_NONE>(a, blocks, s); break;
-    case M_CLOV: launch_one<P, M_CLOV, R_NONE>(a, blocks, s); break;
+    case M_DFULL: launch_one<P, M_DFULL, R_NONE>(B, blocks, s); break;
+    case M_INVSRC: launch_one<P, M_INVSRC, R_NONE>(B, blocks, s); break;
+    case M_HOP: launch_one<P, M_HOP, R_NONE>(B, blocks, s); break;
+    case M_CLOV: launch_one<P, M_CLOV, R_NONE>(B, blocks, s); break;
     }
 }
 
-// algorithmic bytes of one launch (per output site: inputs and outputs at the
-// stored precision, each link once, one clover pair; see the byte model in the
-// documentation of the benchmark)
+// algorithmic bytes of one call (per output site: inputs and outputs at the
+// stored precision, each link once, one clover pair)
 double mult_bytes(int prec, int mode, int red, int Vh) {
     const double S = (double)spinor_bytes(prec, Vh), L = (double)link_slab_bytes(prec, Vh),
                  C = (double)clover_slab_bytes(prec, Vh);
@@ -233,45 +241,66 @@ double mult_bytes(int prec, int mode, int red, int Vh) {
 
 }  // namespace
 
-int launch_mult(wc_lattice *lat, const MultCall &c) {
-    MultKArgs a;
-    a.g = lat->g;
-    a.out_par = c.out_par;
-    a.out = c.out;
-    a.in = c.in;
-    a.center = c.center;
-    a.aux = c.aux;
-    a.links = (const char *)lat->links[c.prec];
-    a.link_slab = link_slab_bytes(c.prec, lat->Vh);
-    const bool use_inv = (c.mode == M_HOPINV || c.mode == M_DHAT || c.mode == M_INVSRC ||
-                          (c.mode == M_CLOV && c.inverse));
-    const char *cb = (const char *)(use_inv ? lat->clovinv[c.prec] : lat->clov[c.prec]);
-    a.clov = cb + (size_t)c.out_par * clover_slab_bytes(c.prec, lat->Vh);
-    a.coef = c.coef;
-    a.red = c.red_to;
-    a.done = c.done;
-    const int blocks = (lat->Vh + kBlock - 1) / kBlock;
-
+int launch_mult_batch(hipStream_t s, const MultCall *calls, int n) {
+    if (n <= 0) return WC_OK;
+    if (n > kMaxSys) return wc_fail(WC_EINVAL, "too many systems in one batch");
+    const MultCall &c0 = calls[0];
+    MultBatch B;
+    B.h.S = n;
+    B.h.off[0] = 0;
+    bool same = true;
+    double bytes = 0;
+    for (int k = 0; k < n; k++) {
+        const MultCall &c = calls[k];
+        wc_lattice *lat = c.lat;
+        if (c.prec != c0.prec || c.mode != c0.mode || c.red != c0.red || c.out_par != c0.out_par)
+            return wc_fail(WC_EINVAL, "batched stencil calls must share precision, mode, reduction and parity");
+        same = same && (lat == c0.lat);
+        MultKArgs &a = B.d[k];
+        a.g = lat->g;
+        a.out_par = c.out_par;
+        a.out = c.out;
+        a.in = c.in;
+        a.center = c.center;
+        a.aux = c.aux;
+        a.links = (const char *)lat->links[c.prec];
+        a.link_slab = link_slab_bytes(c.prec, lat->Vh);
+        const bool use_inv = (c.mode == M_HOPINV || c.mode == M_DHAT || c.mode == M_INVSRC ||
+                              (c.mode == M_CLOV && c.inverse));
+        const char *cb = (const char *)(use_inv ? lat->clovinv[c.prec] : lat->clov[c.prec]);
+        a.clov = cb + (size_t)c.out_par * clover_slab_bytes(c.prec, lat->Vh);
+        a.coef = c.coef;
+        a.red = c.red_to;
+        a.done = c.done;
+        a.nblk = lat->nblocks;
+        B.h.off[k + 1] = B.h.off[k] + lat->nblocks;
+        bytes += mult_bytes(c.prec, c.mode, c.red, lat->Vh);
+        if (c.mode != M_CLOV) lat->dslash_count++;
+    }
+    B.h.interleave = (same && n > 1) ? 1 : 0;
+    const int blocks = B.h.off[n];
+    wc_lattice *tl = c0.lat;
     int slot = KS_MULT_OTHER;
-    if (c.mode == M_HOPINV) slot = KS_MULT_HOPINV_P64 + c.prec;
-    if (c.mode == M_DHAT) slot = KS_MULT_DHAT_P64 + c.prec;
+    if (c0.mode == M_HOPINV) slot = KS_MULT_HOPINV_P64 + c0.prec;
+    if (c0.mode == M_DHAT) slot = KS_MULT_DHAT_P64 + c0.prec;
     TimedLaunch t;
-    if (lat->timing) timing_begin(lat, slot, mult_bytes(c.prec, c.mode, c.red, lat->Vh), t);
-    if (c.prec == P64) dispatch_mode<P64>(a, c.mode, c.red, blocks, lat->stream);
-    else if (c.prec == P32) dispatch_mode<P32>(a, c.mode, c.red, blocks, lat->stream);
-    else dispatch_mode<P16>(a, c.mode, c.red, blocks, lat->stream);
+    if (tl->timing) timing_begin(tl, slot, bytes, t);
+    if (c0.prec == P64) dispatch_mode<P64>(B, c0.mode, c0.red, blocks, s);
+    else if (c0.prec == P32) dispatch_mode<P32>(B, c0.mode, c0.red, blocks, s);
+    else dispatch_mode<P16>(B, c0.mode, c0.red, blocks, s);
     WC_HIP(hipGetLastError());
-    if (lat->timing) timing_end(lat, t);
-    if (c.mode != M_CLOV) lat->dslash_count++;
-    if (c.red != R_NONE && (c.mode == M_DHAT)) {
-        FinArgs f{};
-        f.n = c.red == R_DOT ? 2 : 3;
-        f.blocks = blocks;
-        f.op = FIN_STORE;
-        f.partials = c.red_to.partials;
-        f.result = c.red_to.result;
-        f.guard = c.done;
-        return launch_finalize(lat, f);
+    if (tl->timing) timing_end(tl, t);
+    if (c0.red != R_NONE && c0.mode == M_DHAT) {
+        FinArgs f[kMaxSys];
+        for (int k = 0; k < n; k++) {
+            f[k] = FinArgs{};
+            f[k].blocks = calls[k].lat->nblocks;
+            f[k].op = FIN_STORE;
+            f[k].partials = calls[k].red_to.partials;
+            f[k].result = calls[k].red_to.result;
+            f[k].guard = calls[k].done;
+        }
+        return launch_fin_batch(s, f, n, c0.red == R_DOT ? 2 : 3);
     }
     return WC_OK;
 }

@@ -1,4 +1,4 @@
-// Gradient of a solve with respect to the gauge links, and gamma5.
+// Gradient of a solve with respect to the gauge links.
 //
 // For L = Re<eta, D^-1 b> (or any real loss with dL = Re<eta, dx>) the adjoint
 // solve gives lam = D^-dagger eta = g5 D^-1 g5 eta (D is gamma5-Hermitian),
@@ -111,19 +111,6 @@ __device__ void gamma_pair(int plane, const Spinor<double> &p, Spinor<double> &o
 __device__ __forceinline__ int plane_of(int mu, int nu) {
     // mu < nu
     return mu == 0 ? nu - 1 : (mu == 1 ? nu + 1 : 5);
-}
-
-__global__ __launch_bounds__(kBlock) void k_gamma5(int Vh, double2 *v) {
-    // g5 = -[[0, 1], [1, 0]] in upper/lower spin blocks
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= Vh) return;
-    double2 *s = v + (size_t)blockIdx.y * 12 * Vh;
-#pragma unroll
-    for (int k = 0; k < 6; k++) {
-        const double2 up = s[(size_t)k * Vh + i], dn = s[(size_t)(k + 6) * Vh + i];
-        s[(size_t)k * Vh + i] = make_double2(-dn.x, -dn.y);
-        s[(size_t)(k + 6) * Vh + i] = make_double2(-up.x, -up.y);
-    }
 }
 
 // canonical gradient slot of link (mu, site n) -> 9 complex128
@@ -267,13 +254,6 @@ __global__ __launch_bounds__(64) void k_grad_clover(Geom g, const double2 *l64, 
 }
 
 }  // namespace
-
-int launch_gamma5_p64(wc_lattice *lat, void *eo, int nslabs) {
-    dim3 grid((lat->Vh + kBlock - 1) / kBlock, nslabs);
-    hipLaunchKernelGGL(k_gamma5, grid, dim3(kBlock), 0, lat->stream, lat->Vh, (double2 *)eo);
-    WC_HIP(hipGetLastError());
-    return WC_OK;
-}
 
 int launch_link_grad(wc_lattice *lat, const void *lam_eo, const void *x_eo, void *G, void *Nbuf, double kappa,
                      double csw, bool clover) {

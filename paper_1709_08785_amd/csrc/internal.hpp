@@ -1,5 +1,6 @@
-// Host-side view of a lattice: device buffers, scalar blocks, timing, and the
-// kernel launchers shared between the C ABI and the solver drivers.
+// Host-side view of lattices and linear systems: device buffers, solver state,
+// timing, and the batched kernel launchers shared by the C ABI and the solver
+// drivers.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -11,9 +12,9 @@
 #include "common.hpp"
 
 // ---------------------------------------------------------------------------
-// device scalar block: one per solver level (inner, outer, batch slots).
-// Reductions write their final sums here and the update kernels read the
-// BiCGStab coefficients from it, so no scalar round-trips through the host.
+// device scalar block: one per solver level of each system.  Reductions write
+// their final sums here and the update kernels read the BiCGStab coefficients
+// from it, so no scalar round-trips through the host.
 // ---------------------------------------------------------------------------
 enum ScalarSlot {
     S_RQ = 0,      // <r~, q>            (complex, 2 doubles)
@@ -23,9 +24,8 @@ enum ScalarSlot {
     S_RR = 6,      // ||r||^2
     S_RHO0 = 7,    // rho, slot 0        (complex)
     S_RHO1 = 9,    // rho, slot 1        (complex)
-    S_NORM = 11,   // source norm ||p|| of the inner call (Algorithm 2, first step)
+    S_NORM = 11,   // ||p||^2 of the inner call's source (Algorithm 2, first step)
     S_AUX = 12,    // scratch norm / dot (3 doubles)
-    S_TOL2 = 15,   // tol^2 * ||b||^2 target of the running loop
     S_COUNT = 16
 };
 // flags block (ints): done code, iterations completed
@@ -33,6 +33,7 @@ enum FlagSlot { F_DONE = 0, F_ITERS = 1, F_COUNT = 4 };
 enum DoneCode { DONE_NO = 0, DONE_FULL = 1, DONE_HALF = 2, DONE_BREAK = 4 };
 
 enum { NUM_LEVELS = 2 };  // 0 = inner loop, 1 = outer / FP64 loop
+constexpr int kMaxSys = 16;  // systems per batched launch
 
 // kinds of timed kernel launches
 enum KernelSlot {
@@ -49,11 +50,66 @@ struct TimedLaunch {
     hipEvent_t a, b;
 };
 
+// One linear system's device-side solver state: scalar and flag blocks per
+// level, reduction partials, and pinned host mirrors.  The scalars and flags
+// of the systems of one solve sit in one contiguous arena so that a single
+// copy brings all of them to the host.
+struct SysState {
+    double *scalars = nullptr;     // [NUM_LEVELS][S_COUNT]
+    int *flags = nullptr;          // [NUM_LEVELS][F_COUNT]
+    double *partials = nullptr;    // [8][blocks of the system's lattice]
+    size_t partials_bytes = 0;
+    double *h_scalars = nullptr;   // pinned mirror
+    int *h_flags = nullptr;
+    double *sc(int lvl) const { return scalars + lvl * S_COUNT; }
+    int *fl(int lvl) const { return flags + lvl * F_COUNT; }
+    double hs(int lvl, int slot) const { return h_scalars[lvl * S_COUNT + slot]; }
+    int hf(int lvl, int slot) const { return h_flags[lvl * F_COUNT + slot]; }
+};
+
+struct Arena {
+    int S = 0;
+    double *scalars = nullptr;
+    int *flags = nullptr;
+    double *h_scalars = nullptr;
+    int *h_flags = nullptr;
+};
+
+struct wc_lattice;
+
+// work buffers of one system in a solve (FP64 state and inner-precision state)
+enum WorkId {
+    W_B = 0,  // b, both parities
+    W_X,      // x, both parities
+    W_BHAT,   // b-hat_e
+    W_R, W_RT, W_P, W_V, W_Q, W_T, W_TMP64, W_RES,   // single parity
+    W_IR, W_IRT, W_IP, W_IQ, W_IT, W_ITMP, W_IX,     // inner precision
+    W_SYS_COUNT
+};
+
+struct SysWork {
+    void *buf[W_SYS_COUNT] = {};
+    size_t bytes[W_SYS_COUNT] = {};
+};
+
+// A cached set of systems (arena, per-system partials and work vectors) for
+// batched solves on a given list of lattices.
+struct BatchCache {
+    std::vector<wc_lattice *> lats;
+    Arena arena;
+    std::vector<SysState> sys;
+    std::vector<SysWork> work;
+};
+
+// lattice-owned scratch buffers (operator applications, gradients)
+enum LatWorkId { LW_APPLY_IN = 0, LW_APPLY_OUT, LW_APPLY_TMP, LW_GLAM, LW_GX, LW_GN, LW_COUNT };
+
 struct wc_lattice {
     Geom g;
     int dims[4];
     long V;
     int Vh;
+    int nblocks;   // 256-thread blocks covering one parity
     hipStream_t stream = nullptr;
 
     // gauge links per precision: 8 slabs ([mu][parity]) of link_slab_bytes
@@ -64,27 +120,19 @@ struct wc_lattice {
     bool have_links = false, have_clover = false;
     double kappa = 0.0, csw = 0.0;
 
-    // reductions
-    double *partials = nullptr;      // [8][max_blocks]
-    double *scalars = nullptr;       // [NUM_LEVELS][S_COUNT]
-    int *flags = nullptr;            // [NUM_LEVELS][F_COUNT]
-    double *host_scalars = nullptr;  // pinned mirror of scalars
-    int *host_flags = nullptr;       // pinned mirror of flags
-    int max_blocks = 0;
-    double host_tol2[NUM_LEVELS] = {0.0, 0.0};  // convergence target (squared) handed to the kernels
-
-    // solver work vectors, allocated on first use and kept until destroy
-    void *work[32] = {};
-    size_t work_bytes[32] = {};
+    // single-system state (operator calls and non-batched solves)
+    Arena arena;
+    SysState sys;
+    SysWork swork;
+    void *lwork[LW_COUNT] = {};
+    size_t lwork_bytes[LW_COUNT] = {};
+    BatchCache *batch = nullptr;   // last batched solve's systems, reused when the lattices match
 
     // timing
     bool timing = false;
     std::vector<TimedLaunch> launches;
     std::vector<hipEvent_t> event_pool;
     long dslash_count = 0;
-
-    double *level_scalars(int lvl) { return scalars + lvl * S_COUNT; }
-    int *level_flags(int lvl) { return flags + lvl * F_COUNT; }
 };
 
 // ---------------------------------------------------------------------------
@@ -98,6 +146,14 @@ int wc_fail(int code, const std::string &msg);
             return wc_fail(WC_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));    \
     } while (0)
 
+// allocation helpers (capi.cpp)
+int dev_alloc(void **p, size_t bytes);
+int buf_get(void **slot, size_t *have, size_t bytes, hipStream_t s);  // grow-only device buffer
+int arena_alloc(Arena &a, int S, hipStream_t s);
+void arena_free(Arena &a);
+void arena_bind(Arena &a, int k, SysState &st);
+int sync_arena(const Arena &a, hipStream_t s);
+
 // ---------------------------------------------------------------------------
 // timing hooks around launches
 // ---------------------------------------------------------------------------
@@ -105,19 +161,13 @@ void timing_begin(wc_lattice *lat, int slot, double bytes, TimedLaunch &t);
 void timing_end(wc_lattice *lat, TimedLaunch &t);
 
 // ---------------------------------------------------------------------------
-// reduction target handed to kernels
+// reductions: target of stage 1, and stage 2 (blas.hip)
 // ---------------------------------------------------------------------------
 struct RedTarget {
     double *partials;
-    double *result;  // final sums written here (nres doubles)
+    double *result;  // final sums written here (FIN_STORE)
 };
 
-inline RedTarget red_target(wc_lattice *lat, int lvl, int slot) {
-    return RedTarget{lat->partials, lat->level_scalars(lvl) + slot};
-}
-
-// second stage of a reduction (blas.hip): sums the per-block partials in block
-// order, then applies `op` in one thread
 enum FinOp {
     FIN_STORE = 0,   // result[0..n) = sums
     FIN_INIT,        // rho0 = (sum, 0); reset the level's done flag and iteration count
@@ -125,9 +175,10 @@ enum FinOp {
     FIN_INNER_B,     // ||r||^2, rho1 = <r~, r>, iterations = iter + 1; done = FULL / BREAK
     FIN_OUTER_B      // ||r||^2, rho1 = <r~, r>
 };
+// second stage of one system's reduction: sums `blocks` partials per value in
+// block order, then applies `op` in one thread
 struct FinArgs {
-    int n;             // values per block (1..3)
-    int blocks;        // number of partials per value
+    int blocks;
     int op;
     const double *partials;
     double *result;    // FIN_STORE destination
@@ -137,20 +188,20 @@ struct FinArgs {
     int iter;
     double tol2;
 };
-int launch_finalize(wc_lattice *lat, const FinArgs &f);
+// one block per system; nvals values per system (1..3)
+int launch_fin_batch(hipStream_t s, const FinArgs *f, int n, int nvals);
 
 // ---------------------------------------------------------------------------
-// launchers (layout.hip, clover.hip, dslash.hip, blas.hip)
+// stencil launches (dslash.hip).  A batch is a list of calls with the same
+// precision, mode, reduction and output parity; one launch covers all of
+// them.  Calls on one lattice are interleaved block by block so that the
+// blocks that read the same links and clover run together on one XCD.
 // ---------------------------------------------------------------------------
-int launch_pack_spinor(wc_lattice *lat, int prec, void *eo_out, const void *canon_in);
-int launch_unpack_spinor(wc_lattice *lat, int prec, void *canon_out, const void *eo_in);
-int launch_load_links(wc_lattice *lat, const void *U);
-int launch_build_clover(wc_lattice *lat, double kappa, double csw);
-
 enum MultMode { M_HOPINV = 0, M_DHAT = 1, M_DFULL = 2, M_INVSRC = 3, M_HOP = 4, M_CLOV = 5 };
 enum MultRed { R_NONE = 0, R_DOT = 1, R_DOTNORM = 2 };
 
 struct MultCall {
+    wc_lattice *lat;
     int prec;
     int mode;
     int red;
@@ -162,32 +213,75 @@ struct MultCall {
     double coef;
     bool inverse;        // CLOV: use F^-1 instead of F
     RedTarget red_to;
-    const int *done;     // skip the launch body when *done != 0
+    const int *done;     // skip this call when *done != 0
 };
-int launch_mult(wc_lattice *lat, const MultCall &c);
+int launch_mult_batch(hipStream_t s, const MultCall *calls, int n);
+inline int launch_mult(wc_lattice *lat, MultCall c) {
+    c.lat = lat;
+    return launch_mult_batch(lat->stream, &c, 1);
+}
 
-// BLAS-1 (blas.hip); all vectors are single-parity EO slabs
-int launch_norm2_p64(wc_lattice *lat, const void *v, RedTarget to);
-int launch_sub_norm_p64(wc_lattice *lat, void *r, const void *a, const void *b, RedTarget to);  // r = a - b
-int launch_copy(wc_lattice *lat, void *dst, const void *src, size_t bytes);
-int launch_zero(wc_lattice *lat, void *dst, size_t bytes);
-int launch_axpy_p64(wc_lattice *lat, void *y, const void *x, double a);  // y += a x
+// ---------------------------------------------------------------------------
+// vector kernels (blas.hip), batched the same way; one call per system
+// ---------------------------------------------------------------------------
+enum VecOp {
+    V_NORM2,        // a: v (FP64)                       -> result[0] = ||v||^2, result[1] = 0
+    V_SUB_NORM,     // a = b - c (FP64)                   -> result[0] = ||a||^2
+    V_AXPY,         // a += coef b (FP64)
+    V_INNER_INIT,   // a: src (FP64), b: r, c: r~, d: p, e: x   (Algorithm 2 set-up)
+    V_INNER_A,      // a: r, b: q                         r -= alpha q
+    V_INNER_B,      // a: x, b: r, c: p, d: t, e: r~      x += alpha p + omega s, r = s - omega t
+    V_INNER_C,      // a: p, b: r, c: q                   p = r + beta (p - omega q)
+    V_INNER_FIX,    // a: x, b: p                         x += alpha p
+    V_INNER_FINAL,  // a: v (FP64), b: x                  v = ||src|| x
+    V_OUTER_A,      // a: x, b: r, c: v, d: q             x += alpha v, r -= alpha q
+    V_OUTER_B,      // a: x, b: r, c: v, d: t, e: r~      x += omega v, r -= omega t
+    V_GAMMA5,       // a: FP64 two-parity field, in place
+    V_COPY,         // a = b (FP64 single parity)
+    V_ZERO          // a = 0 (FP64 single parity)
+};
 
-// inner BiCGStab (Algorithm 2) on storage precision prec, x kept in xprec
-int launch_inner_init(wc_lattice *lat, int prec, int xprec, const void *src64, void *r, void *rt, void *p, void *x,
-                      int lvl);
-int launch_inner_a(wc_lattice *lat, int prec, void *r, const void *q, int iter, int lvl);
-int launch_inner_b(wc_lattice *lat, int prec, int xprec, void *x, void *r, const void *p, const void *t,
-                   const void *rt, int iter, int lvl);
-int launch_inner_c(wc_lattice *lat, int prec, void *p, const void *r, const void *q, int iter, int lvl, bool guard);
-int launch_inner_fix(wc_lattice *lat, int prec, int xprec, void *x, const void *p, int iter, int lvl);
-int launch_inner_final(wc_lattice *lat, int xprec, void *v64, const void *x, int lvl);
-// outer flexible BiCGStab (Algorithm 1), FP64
-int launch_outer_a(wc_lattice *lat, void *x, void *r, const void *v, const void *q, int iter, int lvl);
-int launch_outer_b(wc_lattice *lat, void *x, void *r, const void *v, const void *t, const void *rt, int iter,
-                   int lvl);
+struct VecCall {
+    int Vh;
+    void *a, *b, *c, *d, *e;
+    double *sc;        // scalar block of the system's level
+    int *fl;           // flag block of the system's level
+    double *partials;
+    double *result;    // V_NORM2 / V_SUB_NORM destination
+    double tol2;
+    double coef;
+    int iter;
+    int guard;         // skip when fl[F_DONE] != 0
+};
+// prec: storage precision of the inner vectors (the inner solution x is FP64
+// for an FP64 loop and FP32 otherwise).  timing_lat (may be null) receives the
+// timing record of the launch.
+int launch_vec_batch(hipStream_t s, wc_lattice *timing_lat, int op, int prec, const VecCall *calls, int n);
 
-// gradient kernels (grad.hip)
-int launch_gamma5_p64(wc_lattice *lat, void *eo, int nslabs);
+// ---------------------------------------------------------------------------
+// other launchers
+// ---------------------------------------------------------------------------
+int launch_pack_spinor(wc_lattice *lat, int prec, void *eo_out, const void *canon_in);
+int launch_unpack_spinor(wc_lattice *lat, int prec, void *canon_out, const void *eo_in);
+int launch_load_links(wc_lattice *lat, const void *U);
+int launch_build_clover(wc_lattice *lat, double kappa, double csw);
 int launch_link_grad(wc_lattice *lat, const void *lam_eo, const void *x_eo, void *G, void *Nbuf, double kappa,
                      double csw, bool clover);
+
+// solver entry used by wc_solve and the batched solves (solver.cpp)
+struct SolveSys {
+    wc_lattice *lat;
+    SysState *st;
+    SysWork *work;
+    const void *b_dev;
+    void *x_dev;
+    double kappa, csw;
+    wc_solve_info info;
+    int status;
+};
+// every system's SysState must be bound to `arena`; the work vectors of every
+// system must exist (capi.cpp allocates them); all work runs on the first
+// system's lattice stream.  Returns a HIP / argument error, else WC_OK with the
+// per-system outcome in sys[k].status and sys[k].info.
+int solve_systems(std::vector<SolveSys> &sys, const Arena &arena, double tol, const wc_solve_params &P,
+                  int x0_is_guess);

@@ -43,14 +43,36 @@ template <int N> __device__ __forceinline__ void block_fold(double (&v)[N], doub
     }
 }
 
-// Stage 1: per-block partials, laid out [k][gridDim.x].  Every thread of the
-// block must call this.
-template <int N> __device__ __forceinline__ void block_partials(double (&v)[N], double *partials) {
+// Stage 1: per-block partials of one system, laid out [k][G] with G the
+// system's number of blocks and blk this block's index among them.  Every
+// thread of the block must call this.
+template <int N>
+__device__ __forceinline__ void block_partials(double (&v)[N], double *partials, int G, int blk) {
     __shared__ double sh[N][kWaves];
     block_fold<N>(v, sh);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < N; k++) partials[(size_t)k * gridDim.x + blockIdx.x] = v[k];
+        for (int k = 0; k < N; k++) partials[(size_t)k * G + blk] = v[k];
+    }
+}
+
+// A batched launch covers several systems.  Concatenated: system s owns the
+// logical blocks [off[s], off[s+1]).  Interleaved (all systems on one lattice,
+// equal block counts): logical block L belongs to system L mod S, block L / S.
+struct BatchHdr {
+    int S;
+    int interleave;
+    int off[kMaxSys + 1];
+};
+
+__device__ __forceinline__ void batch_locate(const BatchHdr &h, int L, int &s, int &lb) {
+    if (h.interleave) {
+        s = L % h.S;
+        lb = L / h.S;
+    } else {
+        s = 0;
+        while (s + 1 < h.S && L >= h.off[s + 1]) s++;
+        lb = L - h.off[s];
     }
 }
 

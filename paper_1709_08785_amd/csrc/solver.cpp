@@ -1,7 +1,12 @@
 // Solver drivers: the nested BiCGStab of Algorithms 1 (FP64 outer, flexible)
 // and 2 (low-precision inner, source normalised to unit length), the
 // all-FP64 BiCGStab on the same even-odd system, and the even-odd set-up and
-// reconstruction of Sec. II-B (eqs. 6 and 7).
+// reconstruction of Sec. II-B (eqs. 6 and 7), for one or several systems.
+//
+// Several systems (several sources on one lattice, or lattices of different
+// sizes) run in lockstep: every phase is one batched launch over the systems
+// that are still iterating, each system keeps its own scalars and done flag,
+// and one copy of the scalar arena per check serves all of them.
 //
 // Readings of the printed algorithms (both listings agree on them):
 //   alpha = rho0 / <r~|q>             (the listings omit "rho0 /")
@@ -18,38 +23,39 @@
 #include <cstring>
 
 #include "internal.hpp"
-#include "work.hpp"
 
 namespace {
 
-struct Ctx {
-    wc_lattice *lat;
-    int iprec;   // inner storage precision
-    int xprec;   // inner solution precision
+// slot pairs of the outer level used for set-up norms (S_AUX..S_AUX+3)
+constexpr int S_NB_E = S_AUX;      // ||b_e||^2, then ||b-hat||^2, then ||res_e||^2
+constexpr int S_NB_O = S_AUX + 2;  // ||b_o||^2, then ||res_o||^2
+
+struct Run {
+    std::vector<SolveSys> *sys;
+    hipStream_t stream;
+    wc_lattice *tl;     // receives timing records
+    const Arena *arena;
+    int iprec;
     double itol;
     int imaxit, omaxit, fixed_work, check_every;
-    size_t sb64, sbi, sbx;
-    void *b, *x, *bhat, *r, *rt, *p, *v, *q, *t, *tmp64, *res;
-    void *ir, *irt, *ip, *iq, *it, *itmp, *ix;
-    wc_solve_info info;
-    bool inner_broke = false;
+    // per system
+    std::vector<double> src, tol_eo, tol2_in, bnorm;
+    std::vector<int> conv, dead;
+    std::vector<long> dslash;
 };
 
-int sync_scalars(wc_lattice *lat) {
-    WC_HIP(hipMemcpyAsync(lat->host_scalars, lat->scalars, sizeof(double) * NUM_LEVELS * S_COUNT,
-                          hipMemcpyDeviceToHost, lat->stream));
-    WC_HIP(hipMemcpyAsync(lat->host_flags, lat->flags, sizeof(int) * NUM_LEVELS * F_COUNT, hipMemcpyDeviceToHost,
-                          lat->stream));
-    WC_HIP(hipStreamSynchronize(lat->stream));
-    return WC_OK;
-}
+SolveSys &S_(Run &R, int k) { return (*R.sys)[k]; }
+void *W(Run &R, int k, int id) { return S_(R, k).work->buf[id]; }
+size_t sb64(Run &R, int k) { return spinor_bytes(P64, S_(R, k).lat->Vh); }
+char *par_half(Run &R, int k, int id, int par) { return (char *)W(R, k, id) + par * sb64(R, k); }
 
-double hs(wc_lattice *lat, int lvl, int slot) { return lat->host_scalars[lvl * S_COUNT + slot]; }
-int hf(wc_lattice *lat, int lvl, int slot) { return lat->host_flags[lvl * F_COUNT + slot]; }
+int sync(Run &R) { return sync_arena(*R.arena, R.stream); }
 
-MultCall mc(int prec, int mode, int out_par, void *out, const void *in, const void *center, double coef) {
+MultCall mc(Run &R, int k, int prec, int mode, int out_par, void *out, const void *in, const void *center,
+            double coef) {
     MultCall c;
     std::memset(&c, 0, sizeof(c));
+    c.lat = S_(R, k).lat;
     c.prec = prec;
     c.mode = mode;
     c.red = R_NONE;
@@ -61,292 +67,451 @@ MultCall mc(int prec, int mode, int out_par, void *out, const void *in, const vo
     return c;
 }
 
-// out_e = D-hat_ee in_e (two MULTs, eq. 8); optional fused <aux, out> (and ||out||^2)
-int dhat(wc_lattice *lat, int prec, void *out, const void *in, void *tmp, int red, const void *aux, RedTarget to,
-         const int *done) {
-    MultCall c1 = mc(prec, M_HOPINV, 1, tmp, in, nullptr, 0.0);
-    c1.done = done;
-    if (int rc = launch_mult(lat, c1)) return rc;
-    MultCall c2 = mc(prec, M_DHAT, 0, out, tmp, in, -lat->kappa * lat->kappa);
-    c2.red = red;
-    c2.aux = aux;
-    c2.red_to = to;
-    c2.done = done;
-    return launch_mult(lat, c2);
+VecCall vc(Run &R, int k, int lvl, void *a, void *b = nullptr, void *c = nullptr, void *d = nullptr,
+           void *e = nullptr) {
+    VecCall v;
+    std::memset(&v, 0, sizeof(v));
+    SolveSys &s = S_(R, k);
+    v.Vh = s.lat->Vh;
+    v.a = a;
+    v.b = b;
+    v.c = c;
+    v.d = d;
+    v.e = e;
+    v.sc = s.st->sc(lvl);
+    v.fl = s.st->fl(lvl);
+    v.partials = s.st->partials;
+    v.tol2 = R.tol2_in[k];
+    return v;
 }
 
-// v = M src: Algorithm 2 on the inner level (0) in the inner precision
-int inner_solve(Ctx &C, const void *src, void *v) {
-    wc_lattice *lat = C.lat;
-    const int L = 0;
-    const int *done = lat->level_flags(L);
-    if (int rc = launch_norm2_p64(lat, src, red_target(lat, L, S_NORM))) return rc;
-    if (int rc = launch_inner_init(lat, C.iprec, C.xprec, src, C.ir, C.irt, C.ip, C.ix, L)) return rc;
-    lat->host_tol2[L] = C.fixed_work > 0 ? 0.0 : C.itol * C.itol;
-    const int maxit = C.fixed_work > 0 ? C.fixed_work : C.imaxit;
-    const double k2 = -lat->kappa * lat->kappa;
-    (void)k2;
+// one batched stencil launch over the systems in `act`
+template <class F> int mult_over(Run &R, const std::vector<int> &act, F &&make) {
+    MultCall calls[kMaxSys];
+    int n = 0;
+    for (int k : act) {
+        calls[n++] = make(k);
+        R.dslash[k]++;
+    }
+    return launch_mult_batch(R.stream, calls, n);
+}
+
+template <class F> int vec_over(Run &R, const std::vector<int> &act, int op, int prec, F &&make) {
+    VecCall calls[kMaxSys];
+    int n = 0;
+    for (int k : act) calls[n++] = make(k);
+    return launch_vec_batch(R.stream, R.tl, op, prec, calls, n);
+}
+
+// out = D-hat_ee in (two MULTs, eq. 8) for each system, with an optional fused
+// <aux, out> (and ||out||^2) into slot `slot` of level `lvl`
+int dhat(Run &R, const std::vector<int> &act, int prec, int out_id, int in_id, int tmp_id, int red, int aux_id,
+         int lvl, int slot, bool guarded) {
+    if (int rc = mult_over(R, act, [&](int k) {
+            MultCall c = mc(R, k, prec, M_HOPINV, 1, W(R, k, tmp_id), W(R, k, in_id), nullptr, 0.0);
+            c.done = guarded ? S_(R, k).st->fl(lvl) : nullptr;
+            return c;
+        }))
+        return rc;
+    return mult_over(R, act, [&](int k) {
+        SolveSys &s = S_(R, k);
+        MultCall c = mc(R, k, prec, M_DHAT, 0, W(R, k, out_id), W(R, k, tmp_id), W(R, k, in_id),
+                        -s.lat->kappa * s.lat->kappa);
+        c.red = red;
+        c.aux = aux_id >= 0 ? W(R, k, aux_id) : nullptr;
+        c.red_to = RedTarget{s.st->partials, s.st->sc(lvl) + slot};
+        c.done = guarded ? s.st->fl(lvl) : nullptr;
+        return c;
+    });
+}
+
+// v = M src for every system in act: Algorithm 2 on the inner level (0)
+int inner_solve(Run &R, const std::vector<int> &act, int src_id, int v_id) {
+    const int L = 0, P = R.iprec;
+    if (int rc = vec_over(R, act, V_NORM2, P64, [&](int k) {
+            VecCall v = vc(R, k, L, W(R, k, src_id));
+            v.result = S_(R, k).st->sc(L) + S_NORM;
+            return v;
+        }))
+        return rc;
+    if (int rc = vec_over(R, act, V_INNER_INIT, P, [&](int k) {
+            return vc(R, k, L, W(R, k, src_id), W(R, k, W_IR), W(R, k, W_IRT), W(R, k, W_IP), W(R, k, W_IX));
+        }))
+        return rc;
+    for (int k : act) R.tol2_in[k] = R.fixed_work > 0 ? 0.0 : R.tol2_in[k];
+    const int maxit = R.fixed_work > 0 ? R.fixed_work : R.imaxit;
     int queued = 0;
     while (queued < maxit) {
-        const int n = std::min(C.check_every, maxit - queued);
+        const int n = std::min(R.check_every, maxit - queued);
         for (int j = 0; j < n; j++) {
-            const int k = queued + j;
-            if (int rc = dhat(lat, C.iprec, C.iq, C.ip, C.itmp, R_DOT, C.irt, red_target(lat, L, S_RQ), done))
+            const int it = queued + j;
+            auto guarded = [&](int k, VecCall v) {
+                v.iter = it;
+                v.guard = 1;
+                (void)k;
+                return v;
+            };
+            if (int rc = dhat(R, act, P, W_IQ, W_IP, W_ITMP, R_DOT, W_IRT, L, S_RQ, true)) return rc;
+            if (int rc = vec_over(R, act, V_INNER_A, P,
+                                  [&](int k) { return guarded(k, vc(R, k, L, W(R, k, W_IR), W(R, k, W_IQ))); }))
                 return rc;
-            if (int rc = launch_inner_a(lat, C.iprec, C.ir, C.iq, k, L)) return rc;
-            if (int rc = dhat(lat, C.iprec, C.it, C.ir, C.itmp, R_DOTNORM, C.ir, red_target(lat, L, S_ST), done))
+            if (int rc = dhat(R, act, P, W_IT, W_IR, W_ITMP, R_DOTNORM, W_IR, L, S_ST, true)) return rc;
+            if (int rc = vec_over(R, act, V_INNER_B, P, [&](int k) {
+                    return guarded(k, vc(R, k, L, W(R, k, W_IX), W(R, k, W_IR), W(R, k, W_IP), W(R, k, W_IT),
+                                         W(R, k, W_IRT)));
+                }))
                 return rc;
-            if (int rc = launch_inner_b(lat, C.iprec, C.xprec, C.ix, C.ir, C.ip, C.it, C.irt, k, L)) return rc;
-            if (int rc = launch_inner_c(lat, C.iprec, C.ip, C.ir, C.iq, k, L, true)) return rc;
+            if (int rc = vec_over(R, act, V_INNER_C, P, [&](int k) {
+                    return guarded(k, vc(R, k, L, W(R, k, W_IP), W(R, k, W_IR), W(R, k, W_IQ)));
+                }))
+                return rc;
         }
         queued += n;
-        if (int rc = sync_scalars(lat)) return rc;
-        if (hf(lat, L, F_DONE)) break;
+        if (int rc = sync(R)) return rc;
+        bool all = true;
+        for (int k : act) all = all && S_(R, k).st->hf(L, F_DONE) != DONE_NO;
+        if (all) break;
     }
-    const int code = hf(lat, L, F_DONE);
-    int iters = hf(lat, L, F_ITERS);
-    if (code == DONE_HALF) {
-        if (int rc = launch_inner_fix(lat, C.iprec, C.xprec, C.ix, C.ip, iters, L)) return rc;
-        iters += 1;
+    std::vector<int> fix;
+    for (int k : act) {
+        SolveSys &s = S_(R, k);
+        const int code = s.st->hf(L, F_DONE);
+        int iters = s.st->hf(L, F_ITERS);
+        if (code == DONE_HALF) {
+            fix.push_back(k);
+            iters += 1;
+        }
+        s.info.inner_iters_total += iters;
+        s.info.inner_calls += 1;
     }
-    if (code == DONE_BREAK) C.inner_broke = true;
-    C.info.inner_iters_total += iters;
-    C.info.inner_calls += 1;
-    return launch_inner_final(lat, C.xprec, v, C.ix, L);
+    if (!fix.empty())
+        if (int rc = vec_over(R, fix, V_INNER_FIX, P, [&](int k) {
+                VecCall v = vc(R, k, L, W(R, k, W_IX), W(R, k, W_IP));
+                v.iter = S_(R, k).st->hf(L, F_ITERS);
+                return v;
+            }))
+            return rc;
+    return vec_over(R, act, V_INNER_FINAL, P, [&](int k) { return vc(R, k, L, W(R, k, v_id), W(R, k, W_IX)); });
 }
 
 // r = b-hat - D-hat x_e, ||r||^2 to the outer level's S_RR
-int eo_residual(Ctx &C) {
-    wc_lattice *lat = C.lat;
-    if (int rc = dhat(lat, P64, C.q, C.x, C.tmp64, R_NONE, nullptr, RedTarget{}, nullptr)) return rc;
-    return launch_sub_norm_p64(lat, C.r, C.bhat, C.q, red_target(lat, 1, S_RR));
+int eo_residual(Run &R, const std::vector<int> &act) {
+    if (int rc = dhat(R, act, P64, W_Q, W_X, W_TMP64, R_NONE, -1, 1, 0, false)) return rc;
+    return vec_over(R, act, V_SUB_NORM, P64, [&](int k) {
+        VecCall v = vc(R, k, 1, W(R, k, W_R), W(R, k, W_BHAT), W(R, k, W_Q));
+        v.result = S_(R, k).st->sc(1) + S_RR;
+        return v;
+    });
 }
 
-// x_o from eq. 7 and the true residual of the full system; returns ||b - D x||^2
-int reconstruct_and_check(Ctx &C, double &res2) {
-    wc_lattice *lat = C.lat;
-    char *xe = (char *)C.x, *xo = (char *)C.x + C.sb64;
-    char *be = (char *)C.b, *bo = (char *)C.b + C.sb64;
+// x_o from eq. 7 and the squared true residual of the full system per system
+int reconstruct_and_check(Run &R, const std::vector<int> &act, std::vector<double> &res2) {
     // x_o = F_oo^-1 (b_o + kappa H_oe x_e)
-    if (int rc = launch_mult(lat, mc(P64, M_INVSRC, 1, xo, xe, bo, lat->kappa))) return rc;
+    if (int rc = mult_over(R, act, [&](int k) {
+            return mc(R, k, P64, M_INVSRC, 1, par_half(R, k, W_X, 1), par_half(R, k, W_X, 0), par_half(R, k, W_B, 1),
+                      S_(R, k).lat->kappa);
+        }))
+        return rc;
     // (D x)_e = F_ee x_e - kappa H_eo x_o, (D x)_o likewise
-    if (int rc = launch_mult(lat, mc(P64, M_DFULL, 0, C.q, xo, xe, -lat->kappa))) return rc;
-    if (int rc = launch_sub_norm_p64(lat, C.res, be, C.q, red_target(lat, 1, S_AUX))) return rc;
-    if (int rc = sync_scalars(lat)) return rc;
-    double re2 = hs(lat, 1, S_AUX);
-    if (int rc = launch_mult(lat, mc(P64, M_DFULL, 1, C.tmp64, xe, xo, -lat->kappa))) return rc;
-    if (int rc = launch_sub_norm_p64(lat, C.res, bo, C.tmp64, red_target(lat, 1, S_AUX))) return rc;
-    if (int rc = sync_scalars(lat)) return rc;
-    res2 = re2 + hs(lat, 1, S_AUX);
+    if (int rc = mult_over(R, act, [&](int k) {
+            return mc(R, k, P64, M_DFULL, 0, W(R, k, W_Q), par_half(R, k, W_X, 1), par_half(R, k, W_X, 0),
+                      -S_(R, k).lat->kappa);
+        }))
+        return rc;
+    if (int rc = vec_over(R, act, V_SUB_NORM, P64, [&](int k) {
+            VecCall v = vc(R, k, 1, W(R, k, W_RES), par_half(R, k, W_B, 0), W(R, k, W_Q));
+            v.result = S_(R, k).st->sc(1) + S_NB_E;
+            return v;
+        }))
+        return rc;
+    if (int rc = mult_over(R, act, [&](int k) {
+            return mc(R, k, P64, M_DFULL, 1, W(R, k, W_TMP64), par_half(R, k, W_X, 0), par_half(R, k, W_X, 1),
+                      -S_(R, k).lat->kappa);
+        }))
+        return rc;
+    if (int rc = vec_over(R, act, V_SUB_NORM, P64, [&](int k) {
+            VecCall v = vc(R, k, 1, W(R, k, W_RES), par_half(R, k, W_B, 1), W(R, k, W_TMP64));
+            v.result = S_(R, k).st->sc(1) + S_NB_O;
+            return v;
+        }))
+        return rc;
+    if (int rc = sync(R)) return rc;
+    for (int k : act) res2[k] = S_(R, k).st->hs(1, S_NB_E) + S_(R, k).st->hs(1, S_NB_O);
     return WC_OK;
 }
 
-// Algorithm 1 from the current x_e; returns 0 when the recursive residual met tol_eo
-int outer_flexible(Ctx &C, double src, double tol_eo, bool x_is_zero, bool &converged) {
-    wc_lattice *lat = C.lat;
+// drop converged / failed systems from act
+void prune(Run &R, std::vector<int> &act) {
+    std::vector<int> keep;
+    for (int k : act)
+        if (!R.conv[k] && !R.dead[k]) keep.push_back(k);
+    act.swap(keep);
+}
+
+// check the outer recursive residuals after an update; false on breakdown
+void outer_check(Run &R, std::vector<int> &act) {
+    for (int k : act) {
+        SolveSys &s = S_(R, k);
+        const double rr = s.st->hs(1, S_RR);
+        s.info.eo_rel_residual = std::sqrt(rr) / R.src[k];
+        if (!std::isfinite(rr)) R.dead[k] = WC_EBREAKDOWN;
+        else if (std::sqrt(rr) / R.src[k] < R.tol_eo[k]) R.conv[k] = 1;
+    }
+    prune(R, act);
+}
+
+// Algorithm 1 from the current x_e of every system in act
+int outer_flexible(Run &R, std::vector<int> act, bool x_is_zero) {
     const int L = 1;
-    converged = false;
     if (x_is_zero) {
-        if (int rc = launch_copy(lat, C.r, C.bhat, C.sb64)) return rc;
+        if (int rc = vec_over(R, act, V_COPY, P64, [&](int k) { return vc(R, k, L, W(R, k, W_R), W(R, k, W_BHAT)); }))
+            return rc;
     } else {
-        if (int rc = eo_residual(C)) return rc;
+        if (int rc = eo_residual(R, act)) return rc;
     }
-    if (int rc = launch_norm2_p64(lat, C.r, red_target(lat, L, S_RHO0))) return rc;
-    if (int rc = launch_copy(lat, C.rt, C.r, C.sb64)) return rc;
-    if (int rc = launch_copy(lat, C.p, C.r, C.sb64)) return rc;
-    if (int rc = sync_scalars(lat)) return rc;
-    double rr = hs(lat, L, S_RHO0);
-    C.info.eo_rel_residual = std::sqrt(rr) / src;
-    if (std::sqrt(rr) / src < tol_eo) {
-        converged = true;
-        return WC_OK;
+    if (int rc = vec_over(R, act, V_NORM2, P64, [&](int k) {
+            VecCall v = vc(R, k, L, W(R, k, W_R));
+            v.result = S_(R, k).st->sc(L) + S_RHO0;
+            return v;
+        }))
+        return rc;
+    if (int rc = vec_over(R, act, V_COPY, P64, [&](int k) { return vc(R, k, L, W(R, k, W_RT), W(R, k, W_R)); }))
+        return rc;
+    if (int rc = vec_over(R, act, V_COPY, P64, [&](int k) { return vc(R, k, L, W(R, k, W_P), W(R, k, W_R)); }))
+        return rc;
+    if (int rc = sync(R)) return rc;
+    for (int k : act) {
+        const double rr = S_(R, k).st->hs(L, S_RHO0);
+        S_(R, k).info.eo_rel_residual = std::sqrt(rr) / R.src[k];
+        if (std::sqrt(rr) / R.src[k] < R.tol_eo[k]) R.conv[k] = 1;
     }
-    for (int k = 0; k < C.omaxit; k++) {
-        C.info.outer_iters++;
+    prune(R, act);
+    for (int it = 0; it < R.omaxit && !act.empty(); it++) {
+        for (int k : act) S_(R, k).info.outer_iters++;
         // v = M p;  q = D-hat v with <r~, q>
-        if (int rc = inner_solve(C, C.p, C.v)) return rc;
-        if (int rc = dhat(lat, P64, C.q, C.v, C.tmp64, R_DOT, C.rt, red_target(lat, L, S_RQ), nullptr)) return rc;
-        if (int rc = launch_outer_a(lat, C.x, C.r, C.v, C.q, k, L)) return rc;
-        if (int rc = sync_scalars(lat)) return rc;
-        rr = hs(lat, L, S_RR);
-        C.info.eo_rel_residual = std::sqrt(rr) / src;
-        if (!std::isfinite(rr)) return WC_EBREAKDOWN;
-        if (std::sqrt(rr) / src < tol_eo) {
-            converged = true;
-            return WC_OK;
-        }
+        if (int rc = inner_solve(R, act, W_P, W_V)) return rc;
+        if (int rc = dhat(R, act, P64, W_Q, W_V, W_TMP64, R_DOT, W_RT, L, S_RQ, false)) return rc;
+        if (int rc = vec_over(R, act, V_OUTER_A, P64, [&](int k) {
+                VecCall v = vc(R, k, L, W(R, k, W_X), W(R, k, W_R), W(R, k, W_V), W(R, k, W_Q));
+                v.iter = it;
+                return v;
+            }))
+            return rc;
+        if (int rc = sync(R)) return rc;
+        outer_check(R, act);
+        if (act.empty()) break;
         // v = M r;  t = D-hat v with <r, t>, ||t||^2
-        if (int rc = inner_solve(C, C.r, C.v)) return rc;
-        if (int rc = dhat(lat, P64, C.t, C.v, C.tmp64, R_DOTNORM, C.r, red_target(lat, L, S_ST), nullptr)) return rc;
-        if (int rc = launch_outer_b(lat, C.x, C.r, C.v, C.t, C.rt, k, L)) return rc;
-        if (int rc = sync_scalars(lat)) return rc;
-        rr = hs(lat, L, S_RR);
-        C.info.eo_rel_residual = std::sqrt(rr) / src;
-        if (!std::isfinite(rr)) return WC_EBREAKDOWN;
-        if (std::sqrt(rr) / src < tol_eo) {
-            converged = true;
-            return WC_OK;
+        if (int rc = inner_solve(R, act, W_R, W_V)) return rc;
+        if (int rc = dhat(R, act, P64, W_T, W_V, W_TMP64, R_DOTNORM, W_R, L, S_ST, false)) return rc;
+        if (int rc = vec_over(R, act, V_OUTER_B, P64, [&](int k) {
+                VecCall v = vc(R, k, L, W(R, k, W_X), W(R, k, W_R), W(R, k, W_V), W(R, k, W_T), W(R, k, W_RT));
+                v.iter = it;
+                return v;
+            }))
+            return rc;
+        if (int rc = sync(R)) return rc;
+        outer_check(R, act);
+        for (int k : act) {
+            const int slot = ((it + 1) & 1) ? S_RHO1 : S_RHO0;
+            if (S_(R, k).st->hs(L, slot) == 0.0 && S_(R, k).st->hs(L, slot + 1) == 0.0) R.dead[k] = WC_EBREAKDOWN;
         }
-        const double r1re = hs(lat, L, (k + 1) & 1 ? S_RHO1 : S_RHO0);
-        const double r1im = hs(lat, L, ((k + 1) & 1 ? S_RHO1 : S_RHO0) + 1);
-        if (r1re == 0.0 && r1im == 0.0) return WC_EBREAKDOWN;
-        if (int rc = launch_inner_c(lat, P64, C.p, C.r, C.q, k, L, false)) return rc;
+        prune(R, act);
+        if (act.empty()) break;
+        if (int rc = vec_over(R, act, V_INNER_C, P64, [&](int k) {
+                VecCall v = vc(R, k, L, W(R, k, W_P), W(R, k, W_R), W(R, k, W_Q));
+                v.iter = it;
+                return v;
+            }))
+            return rc;
     }
     return WC_OK;
 }
 
-// plain FP64 BiCGStab on D-hat_ee (the inner machinery in FP64), x_e += solution of
-// D-hat v = r_e, repeated from the true residual until tol_eo is met
-int fp64_pass(Ctx &C, double src, double tol_eo, bool x_is_zero, bool &converged) {
-    wc_lattice *lat = C.lat;
-    converged = false;
+// plain FP64 BiCGStab on D-hat_ee (the inner machinery in FP64) for D-hat v = r_e,
+// x_e += v, for every system in act
+int fp64_pass(Run &R, std::vector<int> act, bool x_is_zero) {
     if (x_is_zero) {
-        if (int rc = launch_copy(lat, C.r, C.bhat, C.sb64)) return rc;
-        if (int rc = launch_norm2_p64(lat, C.r, red_target(lat, 1, S_RR))) return rc;
+        if (int rc = vec_over(R, act, V_COPY, P64, [&](int k) { return vc(R, k, 1, W(R, k, W_R), W(R, k, W_BHAT)); }))
+            return rc;
+        if (int rc = vec_over(R, act, V_NORM2, P64, [&](int k) {
+                VecCall v = vc(R, k, 1, W(R, k, W_R));
+                v.result = S_(R, k).st->sc(1) + S_RR;
+                return v;
+            }))
+            return rc;
     } else {
-        if (int rc = eo_residual(C)) return rc;
+        if (int rc = eo_residual(R, act)) return rc;
     }
-    if (int rc = sync_scalars(lat)) return rc;
-    const double rn = std::sqrt(hs(lat, 1, S_RR));
-    C.info.eo_rel_residual = rn / src;
-    if (rn / src < tol_eo) {
-        converged = true;
-        return WC_OK;
+    if (int rc = sync(R)) return rc;
+    std::vector<int> run;
+    for (int k : act) {
+        const double rn = std::sqrt(S_(R, k).st->hs(1, S_RR));
+        S_(R, k).info.eo_rel_residual = rn / R.src[k];
+        if (rn / R.src[k] < R.tol_eo[k]) {
+            R.conv[k] = 1;
+        } else {
+            const double t = R.tol_eo[k] * R.src[k] / rn;
+            R.tol2_in[k] = t * t;
+            S_(R, k).info.outer_iters++;
+            run.push_back(k);
+        }
     }
-    C.info.outer_iters++;
-    C.itol = tol_eo * src / rn;
-    if (int rc = inner_solve(C, C.r, C.v)) return rc;
-    if (int rc = launch_axpy_p64(lat, C.x, C.v, 1.0)) return rc;
-    if (int rc = eo_residual(C)) return rc;
-    if (int rc = sync_scalars(lat)) return rc;
-    const double rr = std::sqrt(hs(lat, 1, S_RR));
-    C.info.eo_rel_residual = rr / src;
-    converged = rr / src < tol_eo;
+    if (run.empty()) return WC_OK;
+    if (int rc = inner_solve(R, run, W_R, W_V)) return rc;
+    if (int rc = vec_over(R, run, V_AXPY, P64, [&](int k) {
+            VecCall v = vc(R, k, 1, W(R, k, W_X), W(R, k, W_V));
+            v.coef = 1.0;
+            return v;
+        }))
+        return rc;
+    if (int rc = eo_residual(R, run)) return rc;
+    if (int rc = sync(R)) return rc;
+    for (int k : run) {
+        const double rr = std::sqrt(S_(R, k).st->hs(1, S_RR));
+        S_(R, k).info.eo_rel_residual = rr / R.src[k];
+        R.conv[k] = rr / R.src[k] < R.tol_eo[k];
+    }
     return WC_OK;
 }
 
 }  // namespace
 
-extern "C" int wc_solve(wc_lattice *lat, const void *b_dev, double kappa, double csw, double tol,
-                        const wc_solve_params *pin, void *x_dev, int x0_is_guess, wc_solve_info *info) {
-    if (!lat || !b_dev || !x_dev) return wc_fail(WC_EINVAL, "null argument");
-    if (!(tol > 0.0) || !(tol < 1.0)) return wc_fail(WC_EINVAL, "tol must lie in (0, 1)");
-    wc_solve_params P;
-    wc_solve_params_default(&P);
-    if (pin) P = *pin;
-    if (P.inner_prec < 0 || P.inner_prec > 2) return wc_fail(WC_EINVAL, "bad inner precision");
-    if (P.inner_maxit < 1 || P.outer_maxit < 1 || P.check_every < 1 || P.fixed_work < 0 || P.inner_tol < 0.0 ||
-        P.inner_tol >= 1.0)
-        return wc_fail(WC_EINVAL, "bad solver parameters");
-    if (!lat->have_links) return wc_fail(WC_ENOTREADY, "wc_solve before wc_load_links");
+int solve_systems(std::vector<SolveSys> &sys, const Arena &arena, double tol, const wc_solve_params &P,
+                  int x0_is_guess) {
+    const int S = (int)sys.size();
+    if (S < 1 || S > kMaxSys) return wc_fail(WC_EINVAL, "between 1 and 16 systems per solve");
     auto t0 = std::chrono::steady_clock::now();
-    if (!lat->have_clover || lat->kappa != kappa || lat->csw != csw) {
-        if (int rc = wc_build_clover(lat, kappa, csw)) return rc;
+    Run R;
+    R.sys = &sys;
+    R.stream = sys[0].lat->stream;
+    R.tl = sys[0].lat;
+    R.arena = &arena;
+    R.iprec = P.inner_prec;
+    R.itol = P.inner_tol > 0.0 ? P.inner_tol : (P.inner_prec == WC_FP16 ? 1e-3 : 1e-6);
+    R.imaxit = P.inner_maxit;
+    R.omaxit = P.outer_maxit;
+    R.fixed_work = P.fixed_work;
+    R.check_every = P.check_every;
+    R.src.assign(S, 0.0);
+    R.tol_eo.assign(S, 0.0);
+    R.tol2_in.assign(S, R.itol * R.itol);
+    R.bnorm.assign(S, 0.0);
+    R.conv.assign(S, 0);
+    R.dead.assign(S, 0);
+    R.dslash.assign(S, 0);
+    for (auto &s : sys) {
+        std::memset(&s.info, 0, sizeof(s.info));
+        s.status = WC_ENOCONV;
     }
-    Ctx C;
-    std::memset(&C.info, 0, sizeof(C.info));
-    C.lat = lat;
-    C.iprec = P.inner_prec;
-    C.xprec = (P.inner_prec == WC_FP64) ? P64 : P32;
-    C.itol = P.inner_tol > 0.0 ? P.inner_tol : (P.inner_prec == WC_FP16 ? 1e-3 : 1e-6);
-    C.imaxit = P.inner_maxit;
-    C.omaxit = P.outer_maxit;
-    C.fixed_work = P.fixed_work;
-    C.check_every = P.check_every;
-    C.sb64 = spinor_bytes(P64, lat->Vh);
-    C.sbi = spinor_bytes(C.iprec, lat->Vh);
-    C.sbx = spinor_bytes(C.xprec, lat->Vh);
-    struct {
-        int id;
-        size_t bytes;
-        void **p;
-    } bufs[] = {
-        {W_B, 2 * C.sb64, &C.b},   {W_X, 2 * C.sb64, &C.x},  {W_BHAT, C.sb64, &C.bhat}, {W_R, C.sb64, &C.r},
-        {W_RT, C.sb64, &C.rt},     {W_P, C.sb64, &C.p},      {W_V, C.sb64, &C.v},       {W_Q, C.sb64, &C.q},
-        {W_T, C.sb64, &C.t},       {W_TMP64, C.sb64, &C.tmp64}, {W_RES, C.sb64, &C.res}, {W_IR, C.sbi, &C.ir},
-        {W_IRT, C.sbi, &C.irt},    {W_IP, C.sbi, &C.ip},     {W_IQ, C.sbi, &C.iq},      {W_IT, C.sbi, &C.it},
-        {W_ITMP, C.sbi, &C.itmp},  {W_IX, C.sbx, &C.ix},
-    };
-    for (auto &bf : bufs)
-        if (int rc = work_get(lat, bf.id, bf.bytes, bf.p)) return rc;
-    const long dslash0 = lat->dslash_count;
+    std::vector<int> all(S);
+    for (int k = 0; k < S; k++) all[k] = k;
 
-    // b -> EO FP64; ||b||.  The adjoint system D^dag x = b is solved as
+    // b -> EO FP64 and ||b||.  The adjoint system D^dag x = b is solved as
     // D y = g5 b, x = g5 y (g5 D g5 = D^dag).
-    if (int rc = launch_pack_spinor(lat, P64, C.b, b_dev)) return rc;
+    for (int k = 0; k < S; k++)
+        if (int rc = launch_pack_spinor(sys[k].lat, P64, W(R, k, W_B), sys[k].b_dev)) return rc;
     if (P.adjoint)
-        if (int rc = launch_gamma5_p64(lat, C.b, 2)) return rc;
-    char *be = (char *)C.b, *bo = (char *)C.b + C.sb64;
-    if (int rc = launch_norm2_p64(lat, be, red_target(lat, 1, S_AUX))) return rc;
-    if (int rc = sync_scalars(lat)) return rc;
-    double b2 = hs(lat, 1, S_AUX);
-    if (int rc = launch_norm2_p64(lat, bo, red_target(lat, 1, S_AUX))) return rc;
-    if (int rc = sync_scalars(lat)) return rc;
-    b2 += hs(lat, 1, S_AUX);
-    const double bnorm = std::sqrt(b2);
-    if (bnorm == 0.0 || !std::isfinite(bnorm)) {
-        if (!std::isfinite(bnorm)) return wc_fail(WC_EINVAL, "b has non-finite entries");
-        WC_HIP(hipMemsetAsync(x_dev, 0, (size_t)lat->V * 12 * 16, lat->stream));
-        WC_HIP(hipStreamSynchronize(lat->stream));
-        if (info) {
-            std::memset(info, 0, sizeof(*info));
-            info->status = WC_OK;
+        if (int rc = vec_over(R, all, V_GAMMA5, P64, [&](int k) { return vc(R, k, 1, W(R, k, W_B)); })) return rc;
+    for (int par = 0; par < 2; par++)
+        if (int rc = vec_over(R, all, V_NORM2, P64, [&](int k) {
+                VecCall v = vc(R, k, 1, par_half(R, k, W_B, par));
+                v.result = sys[k].st->sc(1) + (par ? S_NB_O : S_NB_E);
+                return v;
+            }))
+            return rc;
+    if (int rc = sync(R)) return rc;
+    std::vector<int> act;
+    for (int k = 0; k < S; k++) {
+        const double b2 = sys[k].st->hs(1, S_NB_E) + sys[k].st->hs(1, S_NB_O);
+        R.bnorm[k] = std::sqrt(b2);
+        if (!std::isfinite(b2)) return wc_fail(WC_EINVAL, "b has non-finite entries");
+        if (b2 == 0.0) {
+            // x = 0 solves D x = 0 exactly
+            if (int rc = vec_over(R, {k}, V_ZERO, P64, [&](int j) { return vc(R, j, 1, par_half(R, j, W_X, 0)); })) return rc;
+            if (int rc = vec_over(R, {k}, V_ZERO, P64, [&](int j) { return vc(R, j, 1, par_half(R, j, W_X, 1)); })) return rc;
+            sys[k].status = WC_OK;
+            R.conv[k] = 1;
+        } else {
+            act.push_back(k);
         }
-        return WC_OK;
     }
     // b-hat_e = F_ee^-1 (b_e + kappa H_eo F_oo^-1 b_o)      (eq. 6)
-    if (int rc = launch_mult(lat, [&] {
-            MultCall c = mc(P64, M_CLOV, 1, C.tmp64, nullptr, bo, 0.0);
-            c.inverse = true;
-            return c;
-        }()))
-        return rc;
-    if (int rc = launch_mult(lat, mc(P64, M_INVSRC, 0, C.bhat, C.tmp64, be, lat->kappa))) return rc;
-    if (int rc = launch_norm2_p64(lat, C.bhat, red_target(lat, 1, S_AUX))) return rc;
-    bool x_zero = true;
-    if (x0_is_guess) {
-        if (int rc = launch_pack_spinor(lat, P64, C.x, x_dev)) return rc;
-        if (P.adjoint)
-            if (int rc = launch_gamma5_p64(lat, C.x, 2)) return rc;
-        x_zero = false;
-    } else {
-        if (int rc = launch_zero(lat, C.x, 2 * C.sb64)) return rc;
+    if (!act.empty()) {
+        if (int rc = mult_over(R, act, [&](int k) {
+                MultCall c = mc(R, k, P64, M_CLOV, 1, W(R, k, W_TMP64), nullptr, par_half(R, k, W_B, 1), 0.0);
+                c.inverse = true;
+                return c;
+            }))
+            return rc;
+        if (int rc = mult_over(R, act, [&](int k) {
+                return mc(R, k, P64, M_INVSRC, 0, W(R, k, W_BHAT), W(R, k, W_TMP64), par_half(R, k, W_B, 0),
+                          sys[k].lat->kappa);
+            }))
+            return rc;
+        if (int rc = vec_over(R, act, V_NORM2, P64, [&](int k) {
+                VecCall v = vc(R, k, 1, W(R, k, W_BHAT));
+                v.result = sys[k].st->sc(1) + S_NB_E;
+                return v;
+            }))
+            return rc;
+        for (int k : act) {
+            if (x0_is_guess) {
+                if (int rc = launch_pack_spinor(sys[k].lat, P64, W(R, k, W_X), sys[k].x_dev)) return rc;
+            }
+        }
+        if (x0_is_guess && P.adjoint)
+            if (int rc = vec_over(R, act, V_GAMMA5, P64, [&](int k) { return vc(R, k, 1, W(R, k, W_X)); })) return rc;
+        if (!x0_is_guess) {
+            for (int par = 0; par < 2; par++)
+                if (int rc = vec_over(R, act, V_ZERO, P64, [&](int k) { return vc(R, k, 1, par_half(R, k, W_X, par)); }))
+                    return rc;
+        }
+        if (int rc = sync(R)) return rc;
+        for (int k : act) {
+            R.src[k] = std::sqrt(sys[k].st->hs(1, S_NB_E));
+            R.tol_eo[k] = 0.5 * tol * R.bnorm[k] / R.src[k];
+        }
     }
-    if (int rc = sync_scalars(lat)) return rc;
-    const double src = std::sqrt(hs(lat, 1, S_AUX));
-    const double tol_eo = 0.5 * tol * bnorm / src;
 
-    int status = WC_ENOCONV;
-    const int max_restarts = 6;
-    for (int pass = 0; pass < max_restarts; pass++) {
-        bool conv = false;
-        int rc = (C.iprec == WC_FP64) ? fp64_pass(C, src, tol_eo, x_zero && pass == 0, conv)
-                                      : outer_flexible(C, src, tol_eo, x_zero && pass == 0, conv);
-        if (rc == WC_EBREAKDOWN) {
-            C.info.restarts++;
-            continue;
-        }
+    const int max_passes = 6;
+    std::vector<double> res2(S, 0.0);
+    for (int pass = 0; pass < max_passes && !act.empty(); pass++) {
+        for (int k : act) R.conv[k] = 0;
+        const bool xz = (!x0_is_guess) && pass == 0;
+        int rc = (R.iprec == WC_FP64) ? fp64_pass(R, act, xz) : outer_flexible(R, act, xz);
         if (rc) return rc;
-        double res2 = 0.0;
-        if (int rc2 = reconstruct_and_check(C, res2)) return rc2;
-        C.info.true_rel_residual = std::sqrt(res2) / bnorm;
-        if (C.info.true_rel_residual <= tol) {
-            status = WC_OK;
-            break;
+        if (int rc2 = reconstruct_and_check(R, act, res2)) return rc2;
+        std::vector<int> again;
+        for (int k : act) {
+            sys[k].info.true_rel_residual = std::sqrt(res2[k]) / R.bnorm[k];
+            if (sys[k].info.true_rel_residual <= tol) {
+                sys[k].status = WC_OK;
+            } else if (R.dead[k] && pass + 1 < max_passes) {
+                R.dead[k] = 0;  // breakdown: restart from the true residual
+                sys[k].info.restarts++;
+                again.push_back(k);
+            } else if (R.conv[k] || R.iprec == WC_FP64) {
+                sys[k].info.restarts++;
+                again.push_back(k);
+            } else {
+                sys[k].status = R.dead[k] ? R.dead[k] : WC_ENOCONV;  // iteration cap
+            }
         }
-        if (!conv && C.iprec != WC_FP64) break;  // iteration cap: give up
-        C.info.restarts++;
+        act.swap(again);
     }
+    for (int k : act)
+        if (sys[k].status == WC_ENOCONV && R.dead[k]) sys[k].status = R.dead[k];
+
     if (P.adjoint)
-        if (int rc = launch_gamma5_p64(lat, C.x, 2)) return rc;
-    if (int rc = launch_unpack_spinor(lat, P64, x_dev, C.x)) return rc;
-    WC_HIP(hipStreamSynchronize(lat->stream));
-    auto t1 = std::chrono::steady_clock::now();
-    C.info.seconds = std::chrono::duration<double>(t1 - t0).count();
-    C.info.dslash_count = lat->dslash_count - dslash0;
-    C.info.status = status;
-    if (info) *info = C.info;
-    if (status != WC_OK)
-        return wc_fail(status, "solve stopped at true relative residual " + std::to_string(C.info.true_rel_residual));
+        if (int rc = vec_over(R, all, V_GAMMA5, P64, [&](int k) { return vc(R, k, 1, W(R, k, W_X)); })) return rc;
+    for (int k = 0; k < S; k++)
+        if (int rc = launch_unpack_spinor(sys[k].lat, P64, sys[k].x_dev, W(R, k, W_X))) return rc;
+    WC_HIP(hipStreamSynchronize(R.stream));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int k = 0; k < S; k++) {
+        sys[k].info.seconds = secs;
+        sys[k].info.dslash_count = R.dslash[k];
+        sys[k].info.status = sys[k].status;
+    }
     return WC_OK;
 }

@@ -1,0 +1,131 @@
+"""Batched solves on the GPU: several sources on one lattice (point sources,
+the multi-RHS case) and lattices of different sizes in one set of launches.
+
+Parity: every batched solution against the oracle's own solve at sizes the
+oracle finishes in seconds (1e-10 relative), the oracle's true residual at the
+full 32^3 x 64 size, and bit-identity with separate single solves (each
+system keeps its own reductions in the same order).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1709_08785_amd as wc  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def point_sources(dims):
+    return [synth.point_source(dims, al, a) for al in range(4) for a in range(3)]
+
+
+def test_batch_point_sources_small_vs_oracle():
+    dims = (8, 8, 8, 8)
+    kappa, csw = 0.135, 1.0
+    say("batch 12 point sources", dims)
+    U = synth.random_links(dims, 0.3, 1004)
+    lat = wc.Lattice(dims)
+    lat.load_links(dev(U))
+    bs = point_sources(dims)
+    xs, infos = lat.solve_batch([dev(b) for b in bs], kappa, csw, 1e-12)
+    F = oracle.clover_field(U, dims, kappa, csw)
+    for k in (0, 5, 11):
+        x_ref, _, _ = oracle.solve(U, F, kappa, bs[k], tol=1e-13)
+        assert rel(host(xs[k]), x_ref) < 1e-10, k
+    for k, info in enumerate(infos):
+        r, bn = oracle.residual(U, kappa, csw, bs[k], host(xs[k]))
+        assert r / bn < 1e-12 and info["true_rel_residual"] < 1e-12, (k, info)
+
+
+@pytest.mark.parametrize("inner", [wc.FP32, wc.FP16, wc.FP64])
+def test_batch_bit_identical_to_single_solves(inner):
+    dims = (8, 8, 8, 16)
+    kappa, csw = 0.13, 1.0
+    say("batch vs single", inner)
+    U = synth.random_links(dims, 0.3, 1014)
+    lat = wc.Lattice(dims)
+    lat.load_links(dev(U))
+    bs = [dev(synth.gaussian_source(dims, 2100 + k)) for k in range(3)]
+    xs, infos = lat.solve_batch(bs, kappa, csw, 1e-10, inner_prec=inner)
+    for k in range(3):
+        x1, info1 = lat.solve(bs[k], kappa, csw, 1e-10, inner_prec=inner)
+        assert torch.equal(x1, xs[k]), k
+        assert info1["inner_iters_total"] == infos[k]["inner_iters_total"]
+
+
+def test_multi_uneven_small_vs_oracle():
+    kappa, csw = 0.135, 1.0
+    dims_list = [(4, 4, 4, 4), (6, 6, 6, 12), (8, 8, 8, 16)]
+    say("multi uneven", dims_list)
+    lats, Us, bs = [], [], []
+    for i, dims in enumerate(dims_list):
+        U = synth.random_links(dims, 0.3, 1020 + i)
+        lat = wc.Lattice(dims)
+        lat.load_links(dev(U))
+        lats.append(lat)
+        Us.append(U)
+        bs.append(synth.gaussian_source(dims, 2020 + i))
+    xs, infos = wc.solve_multi(lats, [dev(b) for b in bs], [kappa] * 3, [csw] * 3, 1e-12)
+    for i, dims in enumerate(dims_list):
+        F = oracle.clover_field(Us[i], dims, kappa, csw)
+        x_ref, _, _ = oracle.solve(Us[i], F, kappa, bs[i], tol=1e-13)
+        assert rel(host(xs[i]), x_ref) < 1e-10, dims
+        assert infos[i]["true_rel_residual"] < 1e-12
+
+
+def test_multi_mixed_kappa_and_shared_lattice():
+    # two systems on one lattice plus one on another, different kappa per lattice
+    dims_a, dims_b = (8, 8, 8, 8), (4, 6, 8, 10)
+    Ua, Ub = synth.random_links(dims_a, 0.3, 1031), synth.random_links(dims_b, 0.3, 1032)
+    la, lb = wc.Lattice(dims_a), wc.Lattice(dims_b)
+    la.load_links(dev(Ua))
+    lb.load_links(dev(Ub))
+    b = [synth.gaussian_source(dims_a, 2031), synth.gaussian_source(dims_b, 2032), synth.gaussian_source(dims_a, 2033)]
+    xs, infos = wc.solve_multi([la, lb, la], [dev(v) for v in b], [0.12, 0.13, 0.12], [1.0, 1.0, 1.0], 1e-11)
+    for k, (U, dims, kap) in enumerate([(Ua, dims_a, 0.12), (Ub, dims_b, 0.13), (Ua, dims_a, 0.12)]):
+        r, bn = oracle.residual(U, kap, 1.0, b[k], host(xs[k]))
+        assert r / bn < 1e-11, k
+
+
+def test_batch_full_size_point_sources_residual():
+    # the 12 point sources on the 32^3 x 64 lattice, kappa 0.135: oracle true residual
+    dims = (32, 32, 32, 64)
+    kappa, csw = 0.135, 1.0
+    say("batch 12 point sources", dims)
+    U = synth.random_links(dims, 0.3, 1004)
+    lat = wc.Lattice(dims)
+    lat.load_links(dev(U))
+    bs = point_sources(dims)
+    xs, infos = lat.solve_batch([dev(b) for b in bs], kappa, csw, 1e-10)
+    for k, info in enumerate(infos):
+        assert info["true_rel_residual"] < 1e-10, (k, info)
+    for k in (0, 7):
+        r, bn = oracle.residual(U, kappa, csw, bs[k], host(xs[k]))
+        say("oracle residual", k, r / bn)
+        assert r / bn < 1e-10
