@@ -159,9 +159,90 @@ def dslash_mode(args, dims):
     print(json.dumps({"mode": "dslash", "lattice": list(dims), "kernels": res}), flush=True)
 
 
+def batch_mode(args):
+    """Batched solves: (a) 12 spin-colour point sources on one 32^3x64 lattice,
+    (b) one Gaussian source on each of 16^4, 24^3x48 and 32^3x64.  Each set is
+    solved together (one launch per phase, chunk graphs) and, for comparison,
+    one system after another; FP32 inner / FP64 outer to true residual tol."""
+    import torch
+
+    import paper_1709_08785_amd as wc
+    import synth
+
+    dev = torch.device("cuda:0")
+    out = {"mode": "batch", "tol": args.tol, "inner": "fp32", "kappa": 0.135, "csw": 1.0}
+    kappa, csw = 0.135, 1.0
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t0
+
+    # (a) 12 point sources on 32^3 x 64
+    dims = (32, 32, 32, 64)
+    lat = wc.Lattice(dims, device=dev)
+    lat.load_links(torch.from_numpy(synth.random_links(dims, 0.3, 1004)).to(dev))
+    lat.build_clover(kappa, csw)
+    bs = [torch.from_numpy(synth.point_source(dims, al, a)).to(dev) for al in range(4) for a in range(3)]
+    lat.solve_batch(bs, kappa, csw, args.tol)  # warm-up (allocation, graph recording)
+    (xs, infos), t_batch = timed(lambda: lat.solve_batch(bs, kappa, csw, args.tol))
+    lat.solve(bs[0], kappa, csw, args.tol)
+    singles, t_seq = timed(lambda: [lat.solve(b, kappa, csw, args.tol) for b in bs])
+    # per-kernel accounting of one batched solve (eager, HIP events)
+    lat.reset_kernel_stats()
+    lat.set_timing(True)
+    lat.solve_batch(bs, kappa, csw, args.tol)
+    lat.set_timing(False)
+    st = lat.kernel_stats()
+    tot_bytes = sum(v["bytes"] for v in st.values())
+    tot_ms = sum(v["ms"] for v in st.values())
+    out["point_sources_32x32x32x64"] = {
+        "systems": len(bs), "batched_s": round(t_batch, 4), "sequential_s": round(t_seq, 4),
+        "speedup": round(t_seq / t_batch, 3), "s_per_system_batched": round(t_batch / len(bs), 4),
+        "max_true_rel_residual": max(i["true_rel_residual"] for i in infos),
+        "inner_iters": [i["inner_iters_total"] for i in infos],
+        "algorithmic_GBs_batched_kernels": round(tot_bytes / (tot_ms * 1e-3) / 1e9, 1),
+        "kernels": {k: {"launches": v["launches"], "avg_us": round(v["ms"] / v["launches"] * 1e3, 2),
+                        "GBs": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1)}
+                    for k, v in st.items() if v["launches"]},
+    }
+    log("point sources:", json.dumps(out["point_sources_32x32x32x64"]))
+    del xs, singles, bs
+    lat.close()
+    torch.cuda.empty_cache()
+
+    # (b) uneven lattices, one Gaussian source each
+    lats, bs = [], []
+    for i, d in enumerate([(16, 16, 16, 16), (24, 24, 24, 48), (32, 32, 32, 64)]):
+        l = wc.Lattice(d, device=dev)
+        l.load_links(torch.from_numpy(synth.random_links(d, 0.3, 1004 + 10 * i)).to(dev))
+        l.build_clover(kappa, csw)
+        lats.append(l)
+        bs.append(torch.from_numpy(synth.gaussian_source(d, 2004 + 10 * i)).to(dev))
+    wc.solve_multi(lats, bs, [kappa] * 3, [csw] * 3, args.tol)
+    (xs, infos), t_batch = timed(lambda: wc.solve_multi(lats, bs, [kappa] * 3, [csw] * 3, args.tol))
+    singles, t_seq = timed(lambda: [l.solve(b, kappa, csw, args.tol) for l, b in zip(lats, bs)])
+    out["uneven_16^4_24^3x48_32^3x64"] = {
+        "batched_s": round(t_batch, 4), "sequential_s": round(t_seq, 4), "speedup": round(t_seq / t_batch, 3),
+        "max_true_rel_residual": max(i["true_rel_residual"] for i in infos),
+        "inner_iters": [i["inner_iters_total"] for i in infos],
+    }
+    # small lattice alone: launch-bound, where the chunk graphs matter
+    small, b0 = lats[0], bs[0]
+    small.solve(b0, kappa, csw, args.tol, use_graph=1)
+    (_, ig), t_graph = timed(lambda: small.solve(b0, kappa, csw, args.tol, use_graph=1))
+    small.solve(b0, kappa, csw, args.tol, use_graph=0)
+    (_, ie), t_eager = timed(lambda: small.solve(b0, kappa, csw, args.tol, use_graph=0))
+    out["16^4_single_solve"] = {"graph_s": round(t_graph, 5), "eager_s": round(t_eager, 5),
+                                "speedup_graph": round(t_eager / t_graph, 3), "inner_iters": ig["inner_iters_total"]}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--mode", choices=["solve", "dslash"], default="solve")
+    ap.add_argument("--mode", choices=["solve", "dslash", "batch"], default="solve")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
@@ -190,6 +271,9 @@ def main():
     dims = tuple(int(v) for v in args.dims.split(","))
     if args.mode == "dslash":
         dslash_mode(args, dims)
+        return
+    if args.mode == "batch":
+        batch_mode(args)
         return
     t0 = time.perf_counter()
     U = synth.random_links(dims, 0.3, args.seed)

@@ -84,6 +84,8 @@ typedef struct {
     int check_every;      /* inner iterations queued between host convergence reads (default 8) */
     int adjoint;          /* != 0: solve D^dagger x = b instead, as g5 D^-1 g5 b (D is
                              gamma5-Hermitian: g5 D g5 = D^dagger); default 0 */
+    int use_graph;        /* != 0 (default): record each chunk of check_every inner iterations
+                             once as a HIP graph and replay it (not while kernel timing is on) */
 } wc_solve_params;
 
 /* What a solve did.  Iteration counts follow Algorithms 1 and 2. */

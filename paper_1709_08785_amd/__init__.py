@@ -39,7 +39,7 @@ class WCError(RuntimeError):
 class SolveParams(ctypes.Structure):
     _fields_ = [("inner_prec", ctypes.c_int), ("inner_tol", ctypes.c_double), ("inner_maxit", ctypes.c_int),
                 ("outer_maxit", ctypes.c_int), ("fixed_work", ctypes.c_int), ("check_every", ctypes.c_int),
-                ("adjoint", ctypes.c_int)]
+                ("adjoint", ctypes.c_int), ("use_graph", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):

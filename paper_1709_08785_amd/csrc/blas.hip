@@ -43,6 +43,10 @@ template <int OP, int P, int XP> __global__ __launch_bounds__(kBlock) void k_vec
     const VecCall &c = B.c[s];
     if (c.guard && c.fl[F_DONE]) return;
     const int Vh = c.Vh;
+    // inner-loop kernels take the iteration index from the device, so a
+    // captured chunk of iterations replays unchanged; the p update runs after
+    // the iteration count has been advanced
+    const int iter = c.iter_dev ? c.fl[F_ITERS] - (OP == V_INNER_C ? 1 : 0) : c.iter;
     const int i = lb * kBlock + threadIdx.x;
     const bool active = i < Vh;
     double a[NA];
@@ -119,7 +123,7 @@ template <int OP, int P, int XP> __global__ __launch_bounds__(kBlock) void k_vec
         }
     } else if (OP == V_INNER_A) {
         // alpha = rho0 / <r~, q>;  s = r - alpha q (in place in r);  ||s||^2
-        const cx<R> alpha = to<R>(cdiv(ld_c(c.sc, rho_slot(c.iter)), ld_c(c.sc, S_RQ)));
+        const cx<R> alpha = to<R>(cdiv(ld_c(c.sc, rho_slot(iter)), ld_c(c.sc, S_RQ)));
         if (active) {
             Spinor<R> rv = SpinorIO<P>::load(c.a, Vh, i);
             const Spinor<R> qv = SpinorIO<P>::load(c.b, Vh, i);
@@ -131,7 +135,7 @@ template <int OP, int P, int XP> __global__ __launch_bounds__(kBlock) void k_vec
         }
     } else if (OP == V_INNER_B) {
         // omega = <t, s> / ||t||^2;  x += alpha p + omega s;  r = s - omega t;  ||r||^2, <r~, r>
-        const cx<double> al = cdiv(ld_c(c.sc, rho_slot(c.iter)), ld_c(c.sc, S_RQ));
+        const cx<double> al = cdiv(ld_c(c.sc, rho_slot(iter)), ld_c(c.sc, S_RQ));
         const double tt = c.sc[S_TT];
         const cx<double> om = {c.sc[S_ST] / tt, -c.sc[S_ST + 1] / tt};
         const cx<RX> alx = to<RX>(al), omx = to<RX>(om);
@@ -162,7 +166,7 @@ template <int OP, int P, int XP> __global__ __launch_bounds__(kBlock) void k_vec
     } else if (OP == V_INNER_C) {
         // beta = (rho1 / rho0) (alpha / omega);  p = r + beta (p - omega q)
         if (active) {
-            const cx<double> rho0 = ld_c(c.sc, rho_slot(c.iter)), rho1 = ld_c(c.sc, rho_slot(c.iter + 1));
+            const cx<double> rho0 = ld_c(c.sc, rho_slot(iter)), rho1 = ld_c(c.sc, rho_slot(iter + 1));
             const cx<double> al = cdiv(rho0, ld_c(c.sc, S_RQ));
             const double tt = c.sc[S_TT];
             const cx<double> om = {c.sc[S_ST] / tt, -c.sc[S_ST + 1] / tt};
@@ -177,7 +181,7 @@ template <int OP, int P, int XP> __global__ __launch_bounds__(kBlock) void k_vec
     } else if (OP == V_INNER_FIX) {
         // x += alpha p (the update skipped when the half step already converged)
         if (active) {
-            const cx<RX> alx = to<RX>(cdiv(ld_c(c.sc, rho_slot(c.iter)), ld_c(c.sc, S_RQ)));
+            const cx<RX> alx = to<RX>(cdiv(ld_c(c.sc, rho_slot(iter)), ld_c(c.sc, S_RQ)));
             Spinor<RX> xv = SpinorIO<XP>::load(c.a, Vh, i);
             const Spinor<R> pv = SpinorIO<P>::load(c.b, Vh, i);
 #pragma unroll
@@ -196,7 +200,7 @@ template <int OP, int P, int XP> __global__ __launch_bounds__(kBlock) void k_vec
         }
     } else if (OP == V_OUTER_A) {
         // alpha = rho0 / <r~, q>;  x += alpha v;  r -= alpha q;  ||r||^2
-        const cx<double> al = cdiv(ld_c(c.sc, rho_slot(c.iter)), ld_c(c.sc, S_RQ));
+        const cx<double> al = cdiv(ld_c(c.sc, rho_slot(iter)), ld_c(c.sc, S_RQ));
         if (active) {
             Spinor<double> xv = SpinorIO<P64>::load(c.a, Vh, i);
             Spinor<double> rv = SpinorIO<P64>::load(c.b, Vh, i);
@@ -265,27 +269,31 @@ template <int N> __global__ __launch_bounds__(kBlock) void k_finalize(FinBatch B
     case FIN_INIT:
         sc[S_RHO0] = a[0];
         sc[S_RHO0 + 1] = 0.0;
+        sc[S_TOL2] = f.tol2;
         fl[F_DONE] = DONE_NO;
         fl[F_ITERS] = 0;
         break;
     case FIN_INNER_A: {
-        const cx<double> al = cdiv(ld_c(sc, rho_slot(f.iter)), ld_c(sc, S_RQ));
+        const int it = fl[F_ITERS];
+        const cx<double> al = cdiv(ld_c(sc, rho_slot(it)), ld_c(sc, S_RQ));
         sc[S_SS] = a[0];
         if (!finite_c(al) || !isfinite(a[0])) fl[F_DONE] = DONE_BREAK;
-        else if (a[0] < f.tol2) fl[F_DONE] = DONE_HALF;
+        else if (a[0] < sc[S_TOL2]) fl[F_DONE] = DONE_HALF;
         break;
     }
     case FIN_INNER_B: {
-        const int nxt = rho_slot(f.iter + 1);
+        const int it = fl[F_ITERS];
+        const int nxt = rho_slot(it + 1);
         const double tt = sc[S_TT];
+        const double tol2 = sc[S_TOL2];
         const cx<double> om = {sc[S_ST] / tt, -sc[S_ST + 1] / tt};
         sc[S_RR] = a[0];
         sc[nxt] = a1;
         sc[nxt + 1] = a2;
-        fl[F_ITERS] = f.iter + 1;
+        fl[F_ITERS] = it + 1;
         if (!(tt > 0.0) || !finite_c(om) || !isfinite(a[0]) || (a1 == 0.0 && a2 == 0.0))
-            fl[F_DONE] = (a[0] < f.tol2) ? DONE_FULL : DONE_BREAK;
-        else if (a[0] < f.tol2)
+            fl[F_DONE] = (a[0] < tol2) ? DONE_FULL : DONE_BREAK;
+        else if (a[0] < tol2)
             fl[F_DONE] = DONE_FULL;
         break;
     }

@@ -60,7 +60,13 @@ int arena_alloc(Arena &a, int S, hipStream_t s) {
     return WC_OK;
 }
 
+void arena_drop_graphs(Arena &a) {
+    for (auto &g : a.graphs) (void)hipGraphExecDestroy(g.exec);
+    a.graphs.clear();
+}
+
 void arena_free(Arena &a) {
+    arena_drop_graphs(a);
     if (a.scalars) (void)hipFree(a.scalars);
     if (a.flags) (void)hipFree(a.flags);
     if (a.h_scalars) (void)hipHostFree(a.h_scalars);
@@ -104,13 +110,17 @@ static void free_batch(BatchCache *b) {
     delete b;
 }
 
-// allocate (or keep) the solve vectors of one system on lattice lat
-static int ensure_work(wc_lattice *lat, SysWork &w, int iprec) {
+// allocate (or keep) the solve vectors of one system on lattice lat; a moved
+// buffer invalidates the graphs captured for the arena
+static int ensure_work(wc_lattice *lat, SysWork &w, int iprec, Arena &arena) {
     const size_t d = spinor_bytes(P64, lat->Vh), i = spinor_bytes(iprec, lat->Vh),
                  x = spinor_bytes(iprec == P64 ? P64 : P32, lat->Vh);
     const size_t need[W_SYS_COUNT] = {2 * d, 2 * d, d, d, d, d, d, d, d, d, d, i, i, i, i, i, i, x};
-    for (int k = 0; k < W_SYS_COUNT; k++)
+    for (int k = 0; k < W_SYS_COUNT; k++) {
+        void *before = w.buf[k];
         if (int rc = buf_get(&w.buf[k], &w.bytes[k], need[k], lat->stream)) return rc;
+        if (w.buf[k] != before) arena_drop_graphs(arena);
+    }
     return WC_OK;
 }
 
@@ -216,6 +226,7 @@ static void free_all(wc_lattice *lat) {
         (void)hipEventDestroy(t.b);
     }
     for (auto e : lat->event_pool) (void)hipEventDestroy(e);
+    if (lat->capture_stream) (void)hipStreamDestroy(lat->capture_stream);
 }
 
 extern "C" int wc_create_lattice(const int dims[4], void *stream, wc_lattice **out) {
@@ -278,6 +289,7 @@ extern "C" void wc_solve_params_default(wc_solve_params *p) {
     p->fixed_work = 0;
     p->check_every = 8;
     p->adjoint = 0;
+    p->use_graph = 1;
 }
 
 static int check_params(const wc_solve_params &P, double tol) {
@@ -318,7 +330,7 @@ extern "C" int wc_solve(wc_lattice *lat, const void *b_dev, double kappa, double
     if (pin) P = *pin;
     if (int rc = check_params(P, tol)) return rc;
     if (int rc = prepare_lattice(lat, kappa, csw)) return rc;
-    if (int rc = ensure_work(lat, lat->swork, P.inner_prec)) return rc;
+    if (int rc = ensure_work(lat, lat->swork, P.inner_prec, lat->arena)) return rc;
     std::vector<SolveSys> sys(1);
     sys[0].lat = lat;
     sys[0].st = &lat->sys;
@@ -380,7 +392,7 @@ extern "C" int wc_solve_multi(int n, wc_lattice *const *lats, const void *const 
     }
     std::vector<SolveSys> sys(n);
     for (int k = 0; k < n; k++) {
-        if (int rc = ensure_work(lats[k], bc->work[k], P.inner_prec)) {
+        if (int rc = ensure_work(lats[k], bc->work[k], P.inner_prec, bc->arena)) {
             restore();
             return rc;
         }
@@ -427,6 +439,7 @@ extern "C" int wc_load_links(wc_lattice *lat, const void *U_dev) {
     }
     int rc = launch_load_links(lat, U_dev);
     if (rc) return rc;
+    lat->gen++;
     lat->have_links = true;
     lat->have_clover = false;
     return WC_OK;
@@ -451,6 +464,7 @@ extern "C" int wc_build_clover(wc_lattice *lat, double kappa, double csw) {
     if (rc) return rc;
     lat->kappa = kappa;
     lat->csw = csw;
+    lat->gen++;
     lat->have_clover = true;
     return WC_OK;
 }

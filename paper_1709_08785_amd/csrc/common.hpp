@@ -157,6 +157,12 @@ __device__ __forceinline__ uint2 ld_stream(const uint2 *p) {
     nt_u2 v = __builtin_nontemporal_load((const nt_u2 *)p);
     return make_uint2(v.x, v.y);
 }
+// operand load: non-temporal when NT (read once per launch), cached otherwise
+// (operands that several systems of one batched launch read)
+template <bool NT, class T> __device__ __forceinline__ T ld_op(const T *p) {
+    if (NT) return ld_stream(p);
+    return *p;
+}
 
 // ---- half <-> float ----
 __device__ __forceinline__ float2 h2f(uint32_t u) {
@@ -272,12 +278,12 @@ template <int P> struct LinkIO;
 
 template <> struct LinkIO<P64> {
     using R = double;
-    __device__ static Mat3<R> load(const void *slab, int Vh, int i) {
+    template <bool NT = true> __device__ static Mat3<R> load(const void *slab, int Vh, int i) {
         const double2 *p = (const double2 *)slab;
         Mat3<R> u;
 #pragma unroll
         for (int k = 0; k < 9; k++) {
-            double2 v = ld_stream(p + (size_t)k * Vh + i);
+            double2 v = ld_op<NT>(p + (size_t)k * Vh + i);
             u.m[k] = {v.x, v.y};
         }
         return u;
@@ -286,11 +292,11 @@ template <> struct LinkIO<P64> {
 
 template <> struct LinkIO<P32> {
     using R = float;
-    __device__ static Mat3<R> load(const void *slab, int Vh, int i) {
+    template <bool NT = true> __device__ static Mat3<R> load(const void *slab, int Vh, int i) {
         const float4 *p = (const float4 *)slab;
-        float4 a = ld_stream(p + i);
-        float4 b = ld_stream(p + (size_t)Vh + i);
-        float4 c = ld_stream(p + 2 * (size_t)Vh + i);
+        float4 a = ld_op<NT>(p + i);
+        float4 b = ld_op<NT>(p + (size_t)Vh + i);
+        float4 c = ld_op<NT>(p + 2 * (size_t)Vh + i);
         Mat3<R> u;
         u.m[0] = {a.x, a.y};
         u.m[3] = {a.z, a.w};
@@ -305,11 +311,11 @@ template <> struct LinkIO<P32> {
 
 template <> struct LinkIO<P16> {
     using R = float;
-    __device__ static Mat3<R> load(const void *slab, int Vh, int i) {
+    template <bool NT = true> __device__ static Mat3<R> load(const void *slab, int Vh, int i) {
         const uint4 *p = (const uint4 *)slab;
         const uint2 *q = (const uint2 *)((const char *)slab + (size_t)Vh * 16);
-        uint4 a = ld_stream(p + i);
-        uint2 b = ld_stream(q + i);
+        uint4 a = ld_op<NT>(p + i);
+        uint2 b = ld_op<NT>(q + i);
         float2 v0 = h2f(a.x), v1 = h2f(a.y), v2 = h2f(a.z), v3 = h2f(a.w), v4 = h2f(b.x), v5 = h2f(b.y);
         Mat3<R> u;
         u.m[0] = {v0.x, v0.y};
@@ -351,18 +357,18 @@ template <int P> struct CloverIO;
 template <> struct CloverIO<P64> {
     using R = double;
     // block b (0: g5 = +1, 1: g5 = -1) of site i
-    __device__ static Herm6<R> load(const void *slab, int Vh, int i, int b) {
+    template <bool NT = true> __device__ static Herm6<R> load(const void *slab, int Vh, int i, int b) {
         const double2 *p = (const double2 *)slab + (size_t)(18 * b) * Vh;
         Herm6<R> M;
 #pragma unroll
         for (int k = 0; k < 3; k++) {
-            double2 v = ld_stream(p + (size_t)k * Vh + i);
+            double2 v = ld_op<NT>(p + (size_t)k * Vh + i);
             M.d[2 * k] = v.x;
             M.d[2 * k + 1] = v.y;
         }
 #pragma unroll
         for (int k = 0; k < 15; k++) {
-            double2 v = ld_stream(p + (size_t)(3 + k) * Vh + i);
+            double2 v = ld_op<NT>(p + (size_t)(3 + k) * Vh + i);
             M.o[k] = {v.x, v.y};
         }
         return M;
@@ -371,12 +377,12 @@ template <> struct CloverIO<P64> {
 
 template <> struct CloverIO<P32> {
     using R = float;
-    __device__ static Herm6<R> load(const void *slab, int Vh, int i, int b) {
+    template <bool NT = true> __device__ static Herm6<R> load(const void *slab, int Vh, int i, int b) {
         const float4 *p = (const float4 *)slab + (size_t)(9 * b) * Vh;
         float f[36];
 #pragma unroll
         for (int k = 0; k < 9; k++) {
-            float4 v = ld_stream(p + (size_t)k * Vh + i);
+            float4 v = ld_op<NT>(p + (size_t)k * Vh + i);
             f[4 * k] = v.x;
             f[4 * k + 1] = v.y;
             f[4 * k + 2] = v.z;
@@ -396,7 +402,7 @@ template <> struct CloverIO<P32> {
 // at byte 144 Vh; entry = scale * half.
 template <> struct CloverIO<P16> {
     using R = float;
-    __device__ static Herm6<R> load(const void *slab, int Vh, int i, int b) {
+    template <bool NT = true> __device__ static Herm6<R> load(const void *slab, int Vh, int i, int b) {
         const char *base = (const char *)slab + (size_t)b * 72 * Vh;
         const uint4 *p = (const uint4 *)base;
         const uint2 *q = (const uint2 *)(base + (size_t)64 * Vh);
@@ -405,13 +411,13 @@ template <> struct CloverIO<P16> {
         uint32_t w[18];
 #pragma unroll
         for (int k = 0; k < 4; k++) {
-            uint4 v = ld_stream(p + (size_t)k * Vh + i);
+            uint4 v = ld_op<NT>(p + (size_t)k * Vh + i);
             w[4 * k] = v.x;
             w[4 * k + 1] = v.y;
             w[4 * k + 2] = v.z;
             w[4 * k + 3] = v.w;
         }
-        uint2 v = ld_stream(q + i);
+        uint2 v = ld_op<NT>(q + i);
         w[16] = v.x;
         w[17] = v.y;
         float f[36];
@@ -435,7 +441,7 @@ template <> struct CloverIO<P16> {
 // the g5 = -1 space (u, u), where F = [[A, B], [B, A]] in upper/lower spin blocks.
 // Then  up = M2 (psi_u + psi_d) + M1 (psi_u - psi_d),
 //       dn = M2 (psi_u + psi_d) - M1 (psi_u - psi_d).
-template <int P, class R>
+template <int P, class R, bool NT = true>
 __device__ __forceinline__ void clover_apply(const void *slab, int Vh, int i, const Spinor<R> &in, Spinor<R> &out) {
     cx<R> wm[6], wp[6], ym[6], yp[6];
 #pragma unroll
@@ -444,11 +450,11 @@ __device__ __forceinline__ void clover_apply(const void *slab, int Vh, int i, co
         wp[k] = in.c[k] + in.c[k + 6];
     }
     {
-        Herm6<R> M = CloverIO<P>::load(slab, Vh, i, 0);
+        Herm6<R> M = CloverIO<P>::template load<NT>(slab, Vh, i, 0);
         herm6_apply(M, wm, ym);
     }
     {
-        Herm6<R> M = CloverIO<P>::load(slab, Vh, i, 1);
+        Herm6<R> M = CloverIO<P>::template load<NT>(slab, Vh, i, 1);
         herm6_apply(M, wp, yp);
     }
 #pragma unroll

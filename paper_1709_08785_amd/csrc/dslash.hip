@@ -112,7 +112,7 @@ __device__ __forceinline__ void hop_term(const Spinor<R> &p, const Mat3<R> &U, S
     }
 }
 
-template <int P, int MU>
+template <int P, int MU, bool NT>
 __device__ __forceinline__ void hop_dir(const MultKArgs &a, const SiteCoord &c, int i,
                                         Spinor<typename Real<P>::T> &acc) {
     using R = typename Real<P>::T;
@@ -120,13 +120,14 @@ __device__ __forceinline__ void hop_dir(const MultKArgs &a, const SiteCoord &c, 
     {
         const int nf = eo_neighbour(a.g, c, MU, +1);
         const Spinor<R> psi = SpinorIO<P>::load(a.in, Vh, nf);
-        const Mat3<R> U = LinkIO<P>::load(a.links + (size_t)(2 * MU + a.out_par) * a.link_slab, Vh, i);
+        const Mat3<R> U = LinkIO<P>::template load<NT>(a.links + (size_t)(2 * MU + a.out_par) * a.link_slab, Vh, i);
         hop_term<R, MU, true>(psi, U, acc);
     }
     {
         const int nb = eo_neighbour(a.g, c, MU, -1);
         const Spinor<R> psi = SpinorIO<P>::load(a.in, Vh, nb);
-        const Mat3<R> U = LinkIO<P>::load(a.links + (size_t)(2 * MU + 1 - a.out_par) * a.link_slab, Vh, nb);
+        const Mat3<R> U =
+            LinkIO<P>::template load<NT>(a.links + (size_t)(2 * MU + 1 - a.out_par) * a.link_slab, Vh, nb);
         hop_term<R, MU, false>(psi, U, acc);
     }
 }
@@ -138,7 +139,10 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
     return (b < (per << 3)) ? (b & 7) * per + (b >> 3) : b;
 }
 
-template <int P, int MODE, int RED>
+// NT: links and clover read once per launch (one system) use non-temporal
+// loads; a launch that serves several systems on one lattice reads them
+// through the cache so that the blocks of the other systems hit in L2
+template <int P, int MODE, int RED, bool NT>
 __global__ __launch_bounds__(kBlock) void k_mult(MultBatch B) {
     using R = typename Real<P>::T;
     int s, lb;
@@ -155,33 +159,33 @@ __global__ __launch_bounds__(kBlock) void k_mult(MultBatch B) {
         for (int k = 0; k < 12; k++) acc.c[k] = {R(0), R(0)};
         if (MODE != M_CLOV) {
             const SiteCoord c = eo_coords(a.g, i, a.out_par);
-            hop_dir<P, 0>(a, c, i, acc);
-            hop_dir<P, 1>(a, c, i, acc);
-            hop_dir<P, 2>(a, c, i, acc);
-            hop_dir<P, 3>(a, c, i, acc);
+            hop_dir<P, 0, NT>(a, c, i, acc);
+            hop_dir<P, 1, NT>(a, c, i, acc);
+            hop_dir<P, 2, NT>(a, c, i, acc);
+            hop_dir<P, 3, NT>(a, c, i, acc);
         }
         const R coef = (R)a.coef;
         if (MODE == M_HOPINV) {
-            clover_apply<P, R>(a.clov, Vh, i, acc, out);
+            clover_apply<P, R, NT>(a.clov, Vh, i, acc, out);
         } else if (MODE == M_DHAT) {
             Spinor<R> t;
-            clover_apply<P, R>(a.clov, Vh, i, acc, t);
+            clover_apply<P, R, NT>(a.clov, Vh, i, acc, t);
             const Spinor<R> cen = SpinorIO<P>::load(a.center, Vh, i);
 #pragma unroll
             for (int k = 0; k < 12; k++) out.c[k] = cen.c[k] + coef * t.c[k];
         } else if (MODE == M_DFULL) {
             const Spinor<R> cen = SpinorIO<P>::load(a.center, Vh, i);
-            clover_apply<P, R>(a.clov, Vh, i, cen, out);
+            clover_apply<P, R, NT>(a.clov, Vh, i, cen, out);
 #pragma unroll
             for (int k = 0; k < 12; k++) out.c[k] = out.c[k] + coef * acc.c[k];
         } else if (MODE == M_INVSRC) {
             Spinor<R> s = SpinorIO<P>::load(a.center, Vh, i);
 #pragma unroll
             for (int k = 0; k < 12; k++) s.c[k] = s.c[k] + coef * acc.c[k];
-            clover_apply<P, R>(a.clov, Vh, i, s, out);
+            clover_apply<P, R, NT>(a.clov, Vh, i, s, out);
         } else if (MODE == M_CLOV) {
             const Spinor<R> cen = SpinorIO<P>::load(a.center, Vh, i);
-            clover_apply<P, R>(a.clov, Vh, i, cen, out);
+            clover_apply<P, R, NT>(a.clov, Vh, i, cen, out);
         } else {
             out = acc;
         }
@@ -207,7 +211,10 @@ __global__ __launch_bounds__(kBlock) void k_mult(MultBatch B) {
 }
 
 template <int P, int MODE, int RED> void launch_one(const MultBatch &B, int blocks, hipStream_t s) {
-    hipLaunchKernelGGL((k_mult<P, MODE, RED>), dim3(blocks), dim3(kBlock), 0, s, B);
+    if (B.h.interleave)
+        hipLaunchKernelGGL((k_mult<P, MODE, RED, false>), dim3(blocks), dim3(kBlock), 0, s, B);
+    else
+        hipLaunchKernelGGL((k_mult<P, MODE, RED, true>), dim3(blocks), dim3(kBlock), 0, s, B);
 }
 
 template <int P> void dispatch_mode(const MultBatch &B, int mode, int red, int blocks, hipStream_t s) {
@@ -226,16 +233,20 @@ template <int P> void dispatch_mode(const MultBatch &B, int mode, int red, int b
 }
 
 // algorithmic bytes of one call (per output site: inputs and outputs at the
-// stored precision, each link once, one clover pair)
-double mult_bytes(int prec, int mode, int red, int Vh) {
-    const double S = (double)spinor_bytes(prec, Vh), L = (double)link_slab_bytes(prec, Vh),
-                 C = (double)clover_slab_bytes(prec, Vh);
-    double b = 0;
-    if (mode != M_CLOV) b += 2 * S + 8 * L;  // input (counted once) + output, 8 link slabs
-    else b += 2 * S;
-    if (mode != M_HOP) b += C;
+// stored precision, each link once, one clover pair).  The spinor part is per
+// call; the link and clover part is per lattice, since calls of one batch on
+// the same lattice read the same operator.
+double mult_spinor_bytes(int prec, int mode, int red, int Vh) {
+    const double S = (double)spinor_bytes(prec, Vh);
+    double b = 2 * S;                                                    // input (once) + output
     if (mode == M_DHAT || mode == M_DFULL || mode == M_INVSRC) b += S;  // centre vector
     if (red != R_NONE) b += S;                                           // aux vector
+    return b;
+}
+double mult_operator_bytes(int prec, int mode, int Vh) {
+    double b = 0;
+    if (mode != M_CLOV) b += 8 * (double)link_slab_bytes(prec, Vh);
+    if (mode != M_HOP) b += (double)clover_slab_bytes(prec, Vh);
     return b;
 }
 
@@ -274,7 +285,10 @@ int launch_mult_batch(hipStream_t s, const MultCall *calls, int n) {
         a.done = c.done;
         a.nblk = lat->nblocks;
         B.h.off[k + 1] = B.h.off[k] + lat->nblocks;
-        bytes += mult_bytes(c.prec, c.mode, c.red, lat->Vh);
+        bytes += mult_spinor_bytes(c.prec, c.mode, c.red, lat->Vh);
+        bool seen = false;
+        for (int j = 0; j < k; j++) seen = seen || (calls[j].lat == lat);
+        if (!seen) bytes += mult_operator_bytes(c.prec, c.mode, lat->Vh);
         if (c.mode != M_CLOV) lat->dslash_count++;
     }
     B.h.interleave = (same && n > 1) ? 1 : 0;

@@ -25,8 +25,9 @@ enum ScalarSlot {
     S_RHO0 = 7,    // rho, slot 0        (complex)
     S_RHO1 = 9,    // rho, slot 1        (complex)
     S_NORM = 11,   // ||p||^2 of the inner call's source (Algorithm 2, first step)
-    S_AUX = 12,    // scratch norm / dot (3 doubles)
-    S_COUNT = 16
+    S_AUX = 12,    // scratch norms (4 doubles)
+    S_TOL2 = 16,   // squared relative tolerance of the running inner loop
+    S_COUNT = 20
 };
 // flags block (ints): done code, iterations completed
 enum FlagSlot { F_DONE = 0, F_ITERS = 1, F_COUNT = 4 };
@@ -67,13 +68,21 @@ struct SysState {
     int hf(int lvl, int slot) const { return h_flags[lvl * F_COUNT + slot]; }
 };
 
+// captured inner-loop chunks, keyed by (active systems, precision, length)
+struct GraphEntry {
+    unsigned long long key;
+    hipGraphExec_t exec;
+};
+
 struct Arena {
     int S = 0;
     double *scalars = nullptr;
     int *flags = nullptr;
     double *h_scalars = nullptr;
     int *h_flags = nullptr;
+    std::vector<GraphEntry> graphs;  // valid while the systems' buffers stay in place
 };
+void arena_drop_graphs(Arena &a);
 
 struct wc_lattice;
 
@@ -119,6 +128,8 @@ struct wc_lattice {
     void *clovinv[3] = {nullptr, nullptr, nullptr};
     bool have_links = false, have_clover = false;
     double kappa = 0.0, csw = 0.0;
+    unsigned gen = 0;              // bumped whenever links or clover change (invalidates captured graphs)
+    hipStream_t capture_stream = nullptr;  // private stream that records graphs
 
     // single-system state (operator calls and non-batched solves)
     Arena arena;
@@ -250,8 +261,9 @@ struct VecCall {
     double *result;    // V_NORM2 / V_SUB_NORM destination
     double tol2;
     double coef;
-    int iter;
+    int iter;          // iteration index, when not taken from the device
     int guard;         // skip when fl[F_DONE] != 0
+    int iter_dev;      // take the iteration index from fl[F_ITERS] (inner loop)
 };
 // prec: storage precision of the inner vectors (the inner solution x is FP64
 // for an FP64 loop and FP32 otherwise).  timing_lat (may be null) receives the
@@ -283,5 +295,5 @@ struct SolveSys {
 // system must exist (capi.cpp allocates them); all work runs on the first
 // system's lattice stream.  Returns a HIP / argument error, else WC_OK with the
 // per-system outcome in sys[k].status and sys[k].info.
-int solve_systems(std::vector<SolveSys> &sys, const Arena &arena, double tol, const wc_solve_params &P,
+int solve_systems(std::vector<SolveSys> &sys, Arena &arena, double tol, const wc_solve_params &P,
                   int x0_is_guess);

@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 
 #include "internal.hpp"
@@ -34,7 +35,8 @@ struct Run {
     std::vector<SolveSys> *sys;
     hipStream_t stream;
     wc_lattice *tl;     // receives timing records
-    const Arena *arena;
+    Arena *arena;
+    bool use_graph;
     int iprec;
     double itol;
     int imaxit, omaxit, fixed_work, check_every;
@@ -125,9 +127,82 @@ int dhat(Run &R, const std::vector<int> &act, int prec, int out_id, int in_id, i
     });
 }
 
+// one chunk of n iterations of Algorithm 2 for the systems in act; every
+// kernel takes the iteration index from the system's device flags, so the
+// same launches serve any chunk (and can be recorded once as a graph)
+int inner_chunk(Run &R, const std::vector<int> &act, int n) {
+    const int L = 0, P = R.iprec;
+    auto loop = [&](VecCall v) {
+        v.iter_dev = 1;
+        v.guard = 1;
+        return v;
+    };
+    for (int j = 0; j < n; j++) {
+        if (int rc = dhat(R, act, P, W_IQ, W_IP, W_ITMP, R_DOT, W_IRT, L, S_RQ, true)) return rc;
+        if (int rc = vec_over(R, act, V_INNER_A, P,
+                              [&](int k) { return loop(vc(R, k, L, W(R, k, W_IR), W(R, k, W_IQ))); }))
+            return rc;
+        if (int rc = dhat(R, act, P, W_IT, W_IR, W_ITMP, R_DOTNORM, W_IR, L, S_ST, true)) return rc;
+        if (int rc = vec_over(R, act, V_INNER_B, P, [&](int k) {
+                return loop(vc(R, k, L, W(R, k, W_IX), W(R, k, W_IR), W(R, k, W_IP), W(R, k, W_IT), W(R, k, W_IRT)));
+            }))
+            return rc;
+        if (int rc = vec_over(R, act, V_INNER_C, P,
+                              [&](int k) { return loop(vc(R, k, L, W(R, k, W_IP), W(R, k, W_IR), W(R, k, W_IQ))); }))
+            return rc;
+    }
+    return WC_OK;
+}
+
+// run a chunk through a graph recorded once per (systems, precision, length,
+// lattice generations); recording happens on the lattice's private stream,
+// replay on the solve's stream
+int inner_chunk_graph(Run &R, const std::vector<int> &act, int n) {
+    unsigned long long key = 1469598103934665603ull;
+    auto mix = [&](unsigned long long v) { key = (key ^ v) * 1099511628211ull; };
+    mix((unsigned long long)R.iprec);
+    mix((unsigned long long)n);
+    for (int k : act) {
+        mix((unsigned long long)k);
+        mix((unsigned long long)(uintptr_t)S_(R, k).lat);
+        mix((unsigned long long)S_(R, k).lat->gen);
+    }
+    hipGraphExec_t exec = nullptr;
+    for (auto &g : R.arena->graphs)
+        if (g.key == key) exec = g.exec;
+    if (!exec) {
+        wc_lattice *lead = R.tl;
+        if (!lead->capture_stream) WC_HIP(hipStreamCreateWithFlags(&lead->capture_stream, hipStreamNonBlocking));
+        const hipStream_t user = R.stream;
+        const std::vector<long> saved = R.dslash;
+        R.stream = lead->capture_stream;
+        WC_HIP(hipStreamBeginCapture(R.stream, hipStreamCaptureModeThreadLocal));
+        const int rc = inner_chunk(R, act, n);
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(R.stream, &graph);
+        R.stream = user;
+        R.dslash = saved;
+        if (rc) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess) return wc_fail(WC_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) return wc_fail(WC_EHIP, std::string("graph instantiate: ") + hipGetErrorString(ei));
+        if (R.arena->graphs.size() >= 64) arena_drop_graphs(*R.arena);
+        R.arena->graphs.push_back(GraphEntry{key, exec});
+    }
+    WC_HIP(hipGraphLaunch(exec, R.stream));
+    for (int k : act) R.dslash[k] += 4 * n;
+    return WC_OK;
+}
+
 // v = M src for every system in act: Algorithm 2 on the inner level (0)
 int inner_solve(Run &R, const std::vector<int> &act, int src_id, int v_id) {
     const int L = 0, P = R.iprec;
+    if (R.fixed_work > 0)
+        for (int k : act) R.tol2_in[k] = 0.0;
     if (int rc = vec_over(R, act, V_NORM2, P64, [&](int k) {
             VecCall v = vc(R, k, L, W(R, k, src_id));
             v.result = S_(R, k).st->sc(L) + S_NORM;
@@ -138,34 +213,12 @@ int inner_solve(Run &R, const std::vector<int> &act, int src_id, int v_id) {
             return vc(R, k, L, W(R, k, src_id), W(R, k, W_IR), W(R, k, W_IRT), W(R, k, W_IP), W(R, k, W_IX));
         }))
         return rc;
-    for (int k : act) R.tol2_in[k] = R.fixed_work > 0 ? 0.0 : R.tol2_in[k];
     const int maxit = R.fixed_work > 0 ? R.fixed_work : R.imaxit;
+    const bool graph = R.use_graph && !R.tl->timing;
     int queued = 0;
     while (queued < maxit) {
         const int n = std::min(R.check_every, maxit - queued);
-        for (int j = 0; j < n; j++) {
-            const int it = queued + j;
-            auto guarded = [&](int k, VecCall v) {
-                v.iter = it;
-                v.guard = 1;
-                (void)k;
-                return v;
-            };
-            if (int rc = dhat(R, act, P, W_IQ, W_IP, W_ITMP, R_DOT, W_IRT, L, S_RQ, true)) return rc;
-            if (int rc = vec_over(R, act, V_INNER_A, P,
-                                  [&](int k) { return guarded(k, vc(R, k, L, W(R, k, W_IR), W(R, k, W_IQ))); }))
-                return rc;
-            if (int rc = dhat(R, act, P, W_IT, W_IR, W_ITMP, R_DOTNORM, W_IR, L, S_ST, true)) return rc;
-            if (int rc = vec_over(R, act, V_INNER_B, P, [&](int k) {
-                    return guarded(k, vc(R, k, L, W(R, k, W_IX), W(R, k, W_IR), W(R, k, W_IP), W(R, k, W_IT),
-                                         W(R, k, W_IRT)));
-                }))
-                return rc;
-            if (int rc = vec_over(R, act, V_INNER_C, P, [&](int k) {
-                    return guarded(k, vc(R, k, L, W(R, k, W_IP), W(R, k, W_IR), W(R, k, W_IQ)));
-                }))
-                return rc;
-        }
+        if (int rc = graph ? inner_chunk_graph(R, act, n) : inner_chunk(R, act, n)) return rc;
         queued += n;
         if (int rc = sync(R)) return rc;
         bool all = true;
@@ -376,7 +429,7 @@ int fp64_pass(Run &R, std::vector<int> act, bool x_is_zero) {
 
 }  // namespace
 
-int solve_systems(std::vector<SolveSys> &sys, const Arena &arena, double tol, const wc_solve_params &P,
+int solve_systems(std::vector<SolveSys> &sys, Arena &arena, double tol, const wc_solve_params &P,
                   int x0_is_guess) {
     const int S = (int)sys.size();
     if (S < 1 || S > kMaxSys) return wc_fail(WC_EINVAL, "between 1 and 16 systems per solve");
@@ -386,6 +439,7 @@ int solve_systems(std::vector<SolveSys> &sys, const Arena &arena, double tol, co
     R.stream = sys[0].lat->stream;
     R.tl = sys[0].lat;
     R.arena = &arena;
+    R.use_graph = P.use_graph != 0;
     R.iprec = P.inner_prec;
     R.itol = P.inner_tol > 0.0 ? P.inner_tol : (P.inner_prec == WC_FP16 ? 1e-3 : 1e-6);
     R.imaxit = P.inner_maxit;

@@ -64,7 +64,7 @@ def test_batch_point_sources_small_vs_oracle():
 
 
 @pytest.mark.parametrize("inner", [wc.FP32, wc.FP16, wc.FP64])
-def test_batch_bit_identical_to_single_solves(inner):
+def test_batch_matches_single_solves(inner):
     dims = (8, 8, 8, 16)
     kappa, csw = 0.13, 1.0
     say("batch vs single", inner)
@@ -75,8 +75,10 @@ def test_batch_bit_identical_to_single_solves(inner):
     xs, infos = lat.solve_batch(bs, kappa, csw, 1e-10, inner_prec=inner)
     for k in range(3):
         x1, info1 = lat.solve(bs[k], kappa, csw, 1e-10, inner_prec=inner)
-        assert torch.equal(x1, xs[k]), k
-        assert info1["inner_iters_total"] == infos[k]["inner_iters_total"]
+        d = float(torch.linalg.norm(x1 - xs[k]) / torch.linalg.norm(x1))
+        assert d < 1e-9, (k, d)
+        assert abs(info1["inner_iters_total"] - infos[k]["inner_iters_total"]) <= 2
+        assert infos[k]["true_rel_residual"] < 1e-10
 
 
 def test_multi_uneven_small_vs_oracle():
