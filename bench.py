@@ -240,9 +240,61 @@ def batch_mode(args):
     print(json.dumps(out), flush=True)
 
 
+def precisions_mode(args):
+    """The three precision forms on the 48^3x96 lattice (kappa 0.1355, c_SW 1.0,
+    Z2 source), all refined in FP64 to true relative residual tol: FP16-storage
+    inner, FP32 inner, and the all-FP64 BiCGStab.  Each solution's residual is
+    also computed by the FP64 oracle on the host."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1709_08785_amd as wc
+    import synth
+
+    dims = (48, 48, 48, 96)
+    kappa, csw = 0.1355, 1.0
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    Ud = synth.random_links_torch(dims, 0.3, 1003, device=dev)
+    b = synth.z2_source(dims, 2003)
+    log("48^3x96 inputs in %.1f s" % (time.perf_counter() - t0))
+    lat = wc.Lattice(dims, device=dev)
+    lat.load_links(Ud)
+    lat.build_clover(kappa, csw)
+    U = Ud.cpu().numpy()
+    del Ud
+    bd = torch.from_numpy(b).to(dev)
+    forms = [("fp16", dict(inner_prec=wc.FP16)), ("fp32", dict(inner_prec=wc.FP32)),
+             ("fp64", dict(inner_prec=wc.FP64))]
+    res = {}
+    xs = {}
+    for name, kw in forms:
+        lat.solve(bd, kappa, csw, args.tol, **kw)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        x, info = lat.solve(bd, kappa, csw, args.tol, **kw)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t1
+        xh = x.cpu().numpy()
+        r, bn = oracle.residual(U, kappa, csw, b, xh)
+        xs[name] = xh
+        res[name] = {"seconds": round(el, 4), "inner_iters": info["inner_iters_total"],
+                     "outer_iters": info["outer_iters"], "restarts": info["restarts"],
+                     "true_rel_residual_gpu": info["true_rel_residual"], "true_rel_residual_oracle": r / bn}
+        log(name, json.dumps(res[name]))
+        del x
+    for name in ("fp16", "fp32"):
+        res[name]["solution_rel_diff_vs_fp64"] = float(np.linalg.norm(xs[name] - xs["fp64"]) /
+                                                       np.linalg.norm(xs["fp64"]))
+        res[name]["speedup_vs_fp64"] = round(res["fp64"]["seconds"] / res[name]["seconds"], 3)
+    print(json.dumps({"mode": "precisions", "lattice": list(dims), "kappa": kappa, "csw": csw, "tol": args.tol,
+                      "source": "Z2", "forms": res, "oracle_threads": oracle.num_threads()}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--mode", choices=["solve", "dslash", "batch"], default="solve")
+    ap.add_argument("--mode", choices=["solve", "dslash", "batch", "precisions"], default="solve")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
@@ -274,6 +326,9 @@ def main():
         return
     if args.mode == "batch":
         batch_mode(args)
+        return
+    if args.mode == "precisions":
+        precisions_mode(args)
         return
     t0 = time.perf_counter()
     U = synth.random_links(dims, 0.3, args.seed)
@@ -336,6 +391,7 @@ def main():
 
     # the all-FP64 arm on the same system
     fp64 = None
+    fp16 = None
     if not args.no_fp64_arm:
         x64, info64 = lat.solve(bd, args.kappa, args.csw, args.tol, inner_prec=wc.FP64)
         torch.cuda.synchronize()
@@ -347,6 +403,19 @@ def main():
         diff = float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64))
         fp64 = {"seconds": round(t64, 4), "iterations": info64["inner_iters_total"],
                 "true_rel_residual": info64["true_rel_residual"], "mixed_vs_fp64_solution_rel_diff": diff}
+        # the FP16-storage inner form on the same system (reported beside the FP32 step)
+        lat.solve(bd, args.kappa, args.csw, args.tol, inner_prec=wc.FP16)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        x16, info16 = lat.solve(bd, args.kappa, args.csw, args.tol, inner_prec=wc.FP16)
+        torch.cuda.synchronize()
+        t16 = time.perf_counter() - t1
+        log("fp16 arm: %s" % json.dumps(info16))
+        fp16 = {"seconds": round(t16, 4), "inner_iters": info16["inner_iters_total"],
+                "outer_iters": info16["outer_iters"], "true_rel_residual": info16["true_rel_residual"],
+                "solution_rel_diff_vs_fp64": float(torch.linalg.norm(x16 - x64) / torch.linalg.norm(x64)),
+                "speedup_vs_fp64": round(t64 / t16, 3)}
+        del x16
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -376,9 +445,11 @@ def main():
                    "inner": args.inner, "inner_tol": args.inner_tol},
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "time_to_solution_s": {"mixed": round(ms_per_step / 1e3, 4), "fp64": fp64["seconds"] if fp64 else None},
+        "time_to_solution_s": {"mixed": round(ms_per_step / 1e3, 4), "fp64": fp64["seconds"] if fp64 else None,
+                               "mixed_fp16_inner": fp16["seconds"] if fp16 else None},
         "speedup_mixed_vs_fp64": round(fp64["seconds"] / (ms_per_step / 1e3), 3) if fp64 else None,
         "fp64_arm": fp64,
+        "fp16_inner_arm": fp16,
         "solve": {"outer_iters": last["outer_iters"], "inner_iters": last["inner_iters_total"],
                   "inner_calls": last["inner_calls"], "restarts": last["restarts"],
                   "true_rel_residual": last["true_rel_residual"], "dslash_count": last["dslash_count"]},

@@ -1,0 +1,80 @@
+"""Parity at the full benchmark sizes: the operator on sampled output sites
+against the oracle's site-by-site D, and complete solves checked through the
+oracle's FP64 true residual on the whole lattice (a property that holds at
+any size; the oracle cannot solve these lattices in test time)."""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1709_08785_amd as wc  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def c2():
+    dims = (32, 32, 32, 64)
+    Ud = synth.random_links_torch(dims, 0.3, 1002, device="cuda")
+    lat = wc.Lattice(dims)
+    lat.load_links(Ud)
+    lat.build_clover(0.135, 1.0)
+    U = Ud.cpu().numpy()
+    return dims, lat, U, Ud
+
+
+@pytest.mark.parametrize("prec,tol", [(wc.FP64, 1e-13), (wc.FP32, 1e-5)])
+def test_apply_D_sampled_sites_32x32x32x64(c2, prec, tol):
+    dims, lat, U, Ud = c2
+    say("apply_D sampled", prec)
+    psi = synth.gaussian_source(dims, 2002)
+    out = lat.apply_D(torch.from_numpy(psi).cuda(), prec).cpu().numpy().reshape(-1, 4, 3)
+    g = synth.rng(9)
+    V = int(np.prod(dims))
+    sites = np.concatenate([g.integers(0, V, 4000), [0, 1, V - 1, V - 2, dims[0] - 1]])
+    ref = oracle.apply_D_sites(U, 0.135, 1.0, psi, sites)
+    err = np.linalg.norm(out[sites] - ref) / np.linalg.norm(ref)
+    say("rel err", err)
+    assert err < tol
+
+
+@pytest.mark.parametrize("inner", [wc.FP32, wc.FP16])
+def test_solve_32x32x32x64_oracle_residual(c2, inner):
+    dims, lat, U, Ud = c2
+    say("solve 32^3x64", inner)
+    b = synth.gaussian_source(dims, 2002)
+    x, info = lat.solve(torch.from_numpy(b).cuda(), 0.135, 1.0, 1e-10, inner_prec=inner)
+    r, bn = oracle.residual(U, 0.135, 1.0, b, x.cpu().numpy())
+    say(info, "oracle", r / bn)
+    assert r / bn < 1e-10
+    assert abs(r / bn - info["true_rel_residual"]) < 1e-12
+
+
+def test_solve_48x48x48x96_fp16_oracle_residual():
+    dims = (48, 48, 48, 96)
+    kappa, csw = 0.1355, 1.0
+    say("solve 48^3x96 fp16")
+    Ud = synth.random_links_torch(dims, 0.3, 1003, device="cuda")
+    lat = wc.Lattice(dims)
+    lat.load_links(Ud)
+    U = Ud.cpu().numpy()
+    del Ud
+    b = synth.z2_source(dims, 2003)
+    x, info = lat.solve(torch.from_numpy(b).cuda(), kappa, csw, 1e-10, inner_prec=wc.FP16)
+    r, bn = oracle.residual(U, kappa, csw, b, x.cpu().numpy())
+    say(info, "oracle", r / bn)
+    assert r / bn < 1e-10
+    lat.close()
