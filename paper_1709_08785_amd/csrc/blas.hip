@@ -92,12 +92,13 @@ template <int OP, int P, int XP> __global__ __launch_bounds__(kBlock) void k_vec
         // g5 = -[[0, 1], [1, 0]] in upper/lower spin blocks, both parity slabs
         if (active) {
             for (int par = 0; par < 2; par++) {
-                double2 *v = (double2 *)c.a + (size_t)par * 12 * Vh;
+                char *v = (char *)c.a + (size_t)par * spinor_bytes(P64, Vh);
 #pragma unroll
                 for (int k = 0; k < 6; k++) {
-                    const double2 up = v[(size_t)k * Vh + i], dn = v[(size_t)(k + 6) * Vh + i];
-                    v[(size_t)k * Vh + i] = make_double2(-dn.x, -dn.y);
-                    v[(size_t)(k + 6) * Vh + i] = make_double2(-up.x, -up.y);
+                    double2 *pu = tp<double2, 192>(v, i, 16 * k), *pd = tp<double2, 192>(v, i, 16 * (k + 6));
+                    const double2 up = *pu, dn = *pd;
+                    *pu = make_double2(-dn.x, -dn.y);
+                    *pd = make_double2(-up.x, -up.y);
                 }
             }
         }
@@ -311,8 +312,8 @@ inline int nblk(int Vh) { return (Vh + kBlock - 1) / kBlock; }
 
 // algorithmic bytes of one op on one system (vectors read and written)
 double vec_bytes(int op, int prec, int xprec, int Vh) {
-    const double S = (double)spinor_bytes(prec, Vh), X = (double)spinor_bytes(xprec, Vh),
-                 D = (double)spinor_bytes(P64, Vh);
+    const double S = (double)spinor_site_bytes(prec) * Vh, X = (double)spinor_site_bytes(xprec) * Vh,
+                 D = (double)spinor_site_bytes(P64) * Vh;
     switch (op) {
     case V_NORM2: return D;
     case V_SUB_NORM: return 3 * D;

@@ -69,7 +69,7 @@ __device__ __forceinline__ M3 m3dmul(const M3 &a, const M3 &b) {
 
 struct LinkView {
     Geom g;
-    const double2 *l64;  // [mu][parity][9][Vh]
+    const double2 *l64;  // tiled FP64 link slabs [mu][parity]
 
     __device__ M3 at(int mu, int x, int y, int z, int t) const {
         const int L0 = g.L[0], L1 = g.L[1], L2 = g.L[2], L3 = g.L[3];
@@ -80,11 +80,11 @@ struct LinkView {
         const int par = (x + y + z + t) & 1;
         const int n = x + L0 * (y + L1 * (z + L2 * t));
         const int i = n >> 1;
-        const double2 *p = l64 + (size_t)(2 * mu + par) * 9 * g.Vh;
+        const char *slab = (const char *)l64 + (size_t)(2 * mu + par) * link_slab_bytes(P64, g.Vh);
         M3 u;
 #pragma unroll
         for (int k = 0; k < 9; k++) {
-            double2 v = p[(size_t)k * g.Vh + i];
+            double2 v = *tp<double2, 144>(slab, i, 16 * k);
             u.m[k] = {v.x, v.y};
         }
         return u;
@@ -193,35 +193,34 @@ __device__ void pack_herm(const C (&M)[6][6], double scale, double (&f)[36]) {
 }
 
 struct CloverOut {
-    double2 *f64, *i64;  // [parity][36][Vh]
-    float4 *f32, *i32;   // [parity][18][Vh]
-    char *f16, *i16;     // [parity] slabs of 148 Vh bytes
+    char *f64, *i64;  // tiled slabs [parity], 576 B/site
+    char *f32, *i32;  // 288 B/site
+    char *f16, *i16;  // 148 B/site
 };
 
 __device__ void store_block_set(const CloverOut &o, bool inv, int par, int Vh, int i, const double (&f)[2][36]) {
-    double2 *d64 = (inv ? o.i64 : o.f64) + (size_t)par * 36 * Vh;
-    float4 *d32 = (inv ? o.i32 : o.f32) + (size_t)par * 18 * Vh;
-    char *d16 = (inv ? o.i16 : o.f16) + (size_t)par * 148 * Vh;
+    char *d64 = (inv ? o.i64 : o.f64) + (size_t)par * clover_slab_bytes(P64, Vh);
+    char *d32 = (inv ? o.i32 : o.f32) + (size_t)par * clover_slab_bytes(P32, Vh);
+    char *d16 = (inv ? o.i16 : o.f16) + (size_t)par * clover_slab_bytes(P16, Vh);
     double mx = 0.0;
     for (int b = 0; b < 2; b++) {
-        for (int k = 0; k < 18; k++) d64[(size_t)(18 * b + k) * Vh + i] = make_double2(f[b][2 * k], f[b][2 * k + 1]);
+        for (int k = 0; k < 18; k++)
+            *tp<double2, 576>(d64, i, 16 * (18 * b + k)) = make_double2(f[b][2 * k], f[b][2 * k + 1]);
         for (int k = 0; k < 9; k++)
-            d32[(size_t)(9 * b + k) * Vh + i] = make_float4((float)f[b][4 * k], (float)f[b][4 * k + 1],
-                                                            (float)f[b][4 * k + 2], (float)f[b][4 * k + 3]);
+            *tp<float4, 288>(d32, i, 16 * (9 * b + k)) = make_float4((float)f[b][4 * k], (float)f[b][4 * k + 1],
+                                                                     (float)f[b][4 * k + 2], (float)f[b][4 * k + 3]);
         for (int k = 0; k < 36; k++) mx = fmax(mx, fabs(f[b][k]));
     }
     const float s = (float)mx;
     const float inv_s = s > 0.f ? 1.0f / s : 0.f;
     for (int b = 0; b < 2; b++) {
-        char *base = d16 + (size_t)b * 72 * Vh;
-        uint4 *p = (uint4 *)base;
-        uint2 *q = (uint2 *)(base + (size_t)64 * Vh);
         uint32_t w[18];
         for (int k = 0; k < 18; k++) w[k] = f2h((float)f[b][2 * k] * inv_s, (float)f[b][2 * k + 1] * inv_s);
-        for (int k = 0; k < 4; k++) p[(size_t)k * Vh + i] = make_uint4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
-        q[i] = make_uint2(w[16], w[17]);
+        for (int k = 0; k < 4; k++)
+            *tp<uint4, 148>(d16, i, 72 * b + 16 * k) = make_uint4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
+        *tp<uint2, 148>(d16, i, 72 * b + 64) = make_uint2(w[16], w[17]);
     }
-    ((float *)(d16 + (size_t)144 * Vh))[i] = s;
+    *tp<float, 148>(d16, i, 144) = s;
 }
 
 __global__ __launch_bounds__(64) void k_build_clover(Geom g, const double2 *l64, CloverOut o, double kappa,
@@ -277,10 +276,10 @@ __global__ __launch_bounds__(64) void k_build_clover(Geom g, const double2 *l64,
 
 int launch_build_clover(wc_lattice *lat, double kappa, double csw) {
     CloverOut o;
-    o.f64 = (double2 *)lat->clov[P64];
-    o.i64 = (double2 *)lat->clovinv[P64];
-    o.f32 = (float4 *)lat->clov[P32];
-    o.i32 = (float4 *)lat->clovinv[P32];
+    o.f64 = (char *)lat->clov[P64];
+    o.i64 = (char *)lat->clovinv[P64];
+    o.f32 = (char *)lat->clov[P32];
+    o.i32 = (char *)lat->clovinv[P32];
     o.f16 = (char *)lat->clov[P16];
     o.i16 = (char *)lat->clovinv[P16];
     dim3 grid((lat->Vh + 63) / 64, 2);

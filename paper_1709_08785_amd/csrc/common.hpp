@@ -99,20 +99,31 @@ WC_HD int eo_neighbour(const Geom &g, const SiteCoord &c, int mu, int s) {
 // ---------------------------------------------------------------------------
 // storage precisions
 //   spinor  (12 complex per site)
-//     FP64: 12 planes of double2
-//     FP32:  6 planes of float4 (two complex per plane)
+//     FP64: 12 planes of double2                                  (192 B/site)
+//     FP32:  6 planes of float4 (two complex per plane)           ( 96 B/site)
 //     FP16:  3 planes of uint4 (eight halves = four complex per plane) plus a
-//            float scale per site; value = scale * half
-//   links (one (mu, parity) slab = Vh matrices)
-//     FP64: 9 planes of double2, row-major U[i][j]
+//            float scale plane; value = scale * half               ( 52 B/site)
+//   links (one (mu, parity) slab)
+//     FP64: 9 planes of double2, row-major U[i][j]                (144 B/site)
 //     FP32: 3 planes of float4: columns 0 and 1 (U00 U10 | U20 U01 | U11 U21);
-//           column 2 = conj(col0 x col1)
-//     FP16: the same six complex as halves: 1 uint4 + 1 uint2 plane
+//           column 2 = conj(col0 x col1)                          ( 48 B/site)
+//     FP16: the same six complex as halves: 1 uint4 + 1 uint2 plane (24 B/site)
 //   clover (two Hermitian 6x6 blocks per site, each 6 real diagonal entries
 //           then the 15 complex entries above the diagonal, row by row)
-//     FP64: 36 planes of double2
-//     FP32: 18 planes of float4
-//     FP16:  9 planes of uint4 plus a float scale per site
+//     FP64: 36 planes of double2                                  (576 B/site)
+//     FP32: 18 planes of float4                                   (288 B/site)
+//     FP16: per block 4 uint4 + 1 uint2 planes, then a float scale plane
+//                                                                 (148 B/site)
+//
+// Site tiles.  A parity slab is cut into tiles of kTile consecutive EO sites;
+// a tile holds every plane of its sites, plane after plane, each plane kTile
+// consecutive entries.  One wavefront's load of a plane is then 64 adjacent
+// entries, and all planes of its sites share a few KB of one DRAM region
+// instead of being spread over slabs hundreds of MB apart.  A plane at byte
+// offset OFF of the site record (the bytes of the planes before it) with
+// entries of E bytes lives, for site i, at
+//     slab + (i / kTile) * kTile * SB + OFF * kTile + (i % kTile) * E,
+// SB being the bytes per site.  Slabs are padded to whole tiles.
 // ---------------------------------------------------------------------------
 enum { P64 = 0, P32 = 1, P16 = 2 };
 
@@ -121,15 +132,31 @@ template <> struct Real<P64> { using T = double; };
 template <> struct Real<P32> { using T = float; };
 template <> struct Real<P16> { using T = float; };
 
-// bytes of one parity-slab of each field kind
-WC_HD size_t spinor_bytes(int prec, int Vh) {
-    return prec == P64 ? (size_t)Vh * 192 : prec == P32 ? (size_t)Vh * 96 : (size_t)Vh * 52;
+constexpr int kTile = 64;
+
+WC_HD int pad_sites(int Vh) { return (Vh + kTile - 1) / kTile * kTile; }
+
+// bytes per site of each field kind
+WC_HD size_t spinor_site_bytes(int prec) { return prec == P64 ? 192 : prec == P32 ? 96 : 52; }
+WC_HD size_t link_site_bytes(int prec) { return prec == P64 ? 144 : prec == P32 ? 48 : 24; }
+WC_HD size_t clover_site_bytes(int prec) { return prec == P64 ? 576 : prec == P32 ? 288 : 148; }
+
+// bytes of one (padded) parity slab of each field kind
+WC_HD size_t spinor_bytes(int prec, int Vh) { return (size_t)pad_sites(Vh) * spinor_site_bytes(prec); }
+WC_HD size_t link_slab_bytes(int prec, int Vh) { return (size_t)pad_sites(Vh) * link_site_bytes(prec); }
+WC_HD size_t clover_slab_bytes(int prec, int Vh) { return (size_t)pad_sites(Vh) * clover_site_bytes(prec); }
+
+// byte offset of entry i of the plane at record offset off (entries of eb bytes)
+// in a tiled slab of sb bytes per site
+WC_HD size_t tile_off(int i, size_t sb, size_t off, size_t eb) {
+    const unsigned u = (unsigned)i;
+    return (size_t)(u / kTile) * (kTile * sb) + off * kTile + (size_t)(u % kTile) * eb;
 }
-WC_HD size_t link_slab_bytes(int prec, int Vh) {
-    return prec == P64 ? (size_t)Vh * 144 : prec == P32 ? (size_t)Vh * 48 : (size_t)Vh * 24;
+template <class E, int SB> __device__ __forceinline__ const E *tp(const void *slab, int i, int off) {
+    return (const E *)((const char *)slab + tile_off(i, SB, (size_t)off, sizeof(E)));
 }
-WC_HD size_t clover_slab_bytes(int prec, int Vh) {
-    return prec == P64 ? (size_t)Vh * 576 : prec == P32 ? (size_t)Vh * 288 : (size_t)Vh * 148;
+template <class E, int SB> __device__ __forceinline__ E *tp(void *slab, int i, int off) {
+    return (E *)((char *)slab + tile_off(i, SB, (size_t)off, sizeof(E)));
 }
 
 template <class R> struct Spinor {
@@ -175,61 +202,55 @@ __device__ __forceinline__ uint32_t f2h(float a, float b) {
 }
 
 // ---------------------------------------------------------------------------
-// spinor load / store (one parity slab: base pointer, stride Vh)
+// spinor load / store (one tiled parity slab; Vh is the slab's site count)
 // ---------------------------------------------------------------------------
 template <int P> struct SpinorIO;
 
 template <> struct SpinorIO<P64> {
     using R = double;
     __device__ static Spinor<R> load(const void *base, int Vh, int i) {
-        const double2 *p = (const double2 *)base;
         Spinor<R> s;
 #pragma unroll
         for (int k = 0; k < 12; k++) {
-            double2 v = p[(size_t)k * Vh + i];
+            double2 v = *tp<double2, 192>(base, i, 16 * k);
             s.c[k] = {v.x, v.y};
         }
         return s;
     }
     __device__ static void store(void *base, int Vh, int i, const Spinor<R> &s) {
-        double2 *p = (double2 *)base;
 #pragma unroll
-        for (int k = 0; k < 12; k++) p[(size_t)k * Vh + i] = make_double2(s.c[k].re, s.c[k].im);
+        for (int k = 0; k < 12; k++) *tp<double2, 192>(base, i, 16 * k) = make_double2(s.c[k].re, s.c[k].im);
     }
 };
 
 template <> struct SpinorIO<P32> {
     using R = float;
     __device__ static Spinor<R> load(const void *base, int Vh, int i) {
-        const float4 *p = (const float4 *)base;
         Spinor<R> s;
 #pragma unroll
         for (int k = 0; k < 6; k++) {
-            float4 v = p[(size_t)k * Vh + i];
+            float4 v = *tp<float4, 96>(base, i, 16 * k);
             s.c[2 * k] = {v.x, v.y};
             s.c[2 * k + 1] = {v.z, v.w};
         }
         return s;
     }
     __device__ static void store(void *base, int Vh, int i, const Spinor<R> &s) {
-        float4 *p = (float4 *)base;
 #pragma unroll
         for (int k = 0; k < 6; k++)
-            p[(size_t)k * Vh + i] = make_float4(s.c[2 * k].re, s.c[2 * k].im, s.c[2 * k + 1].re, s.c[2 * k + 1].im);
+            *tp<float4, 96>(base, i, 16 * k) = make_float4(s.c[2 * k].re, s.c[2 * k].im, s.c[2 * k + 1].re, s.c[2 * k + 1].im);
     }
 };
 
-// FP16 storage: planes of uint4 (3 * 16 B) followed by a float scale plane
+// FP16 storage: planes of uint4 (3 * 16 B) followed by a float scale plane at 48
 template <> struct SpinorIO<P16> {
     using R = float;
     __device__ static Spinor<R> load(const void *base, int Vh, int i) {
-        const uint4 *p = (const uint4 *)base;
-        const float *sc = (const float *)((const char *)base + (size_t)Vh * 48);
-        float s = sc[i];
+        const float s = *tp<float, 52>(base, i, 48);
         Spinor<R> out;
 #pragma unroll
         for (int k = 0; k < 3; k++) {
-            uint4 v = p[(size_t)k * Vh + i];
+            uint4 v = *tp<uint4, 52>(base, i, 16 * k);
             float2 a = h2f(v.x), b = h2f(v.y), c = h2f(v.z), d = h2f(v.w);
             out.c[4 * k + 0] = {s * a.x, s * a.y};
             out.c[4 * k + 1] = {s * b.x, s * b.y};
@@ -239,8 +260,6 @@ template <> struct SpinorIO<P16> {
         return out;
     }
     __device__ static void store(void *base, int Vh, int i, const Spinor<R> &v) {
-        uint4 *p = (uint4 *)base;
-        float *sc = (float *)((char *)base + (size_t)Vh * 48);
         float m = 0.f;
 #pragma unroll
         for (int k = 0; k < 12; k++) m = fmaxf(m, fmaxf(fabsf(v.c[k].re), fabsf(v.c[k].im)));
@@ -252,9 +271,9 @@ template <> struct SpinorIO<P16> {
             u.y = f2h(v.c[4 * k + 1].re * inv, v.c[4 * k + 1].im * inv);
             u.z = f2h(v.c[4 * k + 2].re * inv, v.c[4 * k + 2].im * inv);
             u.w = f2h(v.c[4 * k + 3].re * inv, v.c[4 * k + 3].im * inv);
-            p[(size_t)k * Vh + i] = u;
+            *tp<uint4, 52>(base, i, 16 * k) = u;
         }
-        sc[i] = m;
+        *tp<float, 52>(base, i, 48) = m;
     }
 };
 
@@ -279,11 +298,10 @@ template <int P> struct LinkIO;
 template <> struct LinkIO<P64> {
     using R = double;
     template <bool NT = true> __device__ static Mat3<R> load(const void *slab, int Vh, int i) {
-        const double2 *p = (const double2 *)slab;
         Mat3<R> u;
 #pragma unroll
         for (int k = 0; k < 9; k++) {
-            double2 v = ld_op<NT>(p + (size_t)k * Vh + i);
+            double2 v = ld_op<NT>(tp<double2, 144>(slab, i, 16 * k));
             u.m[k] = {v.x, v.y};
         }
         return u;
@@ -293,10 +311,9 @@ template <> struct LinkIO<P64> {
 template <> struct LinkIO<P32> {
     using R = float;
     template <bool NT = true> __device__ static Mat3<R> load(const void *slab, int Vh, int i) {
-        const float4 *p = (const float4 *)slab;
-        float4 a = ld_op<NT>(p + i);
-        float4 b = ld_op<NT>(p + (size_t)Vh + i);
-        float4 c = ld_op<NT>(p + 2 * (size_t)Vh + i);
+        float4 a = ld_op<NT>(tp<float4, 48>(slab, i, 0));
+        float4 b = ld_op<NT>(tp<float4, 48>(slab, i, 16));
+        float4 c = ld_op<NT>(tp<float4, 48>(slab, i, 32));
         Mat3<R> u;
         u.m[0] = {a.x, a.y};
         u.m[3] = {a.z, a.w};
@@ -312,10 +329,8 @@ template <> struct LinkIO<P32> {
 template <> struct LinkIO<P16> {
     using R = float;
     template <bool NT = true> __device__ static Mat3<R> load(const void *slab, int Vh, int i) {
-        const uint4 *p = (const uint4 *)slab;
-        const uint2 *q = (const uint2 *)((const char *)slab + (size_t)Vh * 16);
-        uint4 a = ld_op<NT>(p + i);
-        uint2 b = ld_op<NT>(q + i);
+        uint4 a = ld_op<NT>(tp<uint4, 24>(slab, i, 0));
+        uint2 b = ld_op<NT>(tp<uint2, 24>(slab, i, 16));
         float2 v0 = h2f(a.x), v1 = h2f(a.y), v2 = h2f(a.z), v3 = h2f(a.w), v4 = h2f(b.x), v5 = h2f(b.y);
         Mat3<R> u;
         u.m[0] = {v0.x, v0.y};
@@ -358,17 +373,16 @@ template <> struct CloverIO<P64> {
     using R = double;
     // block b (0: g5 = +1, 1: g5 = -1) of site i
     template <bool NT = true> __device__ static Herm6<R> load(const void *slab, int Vh, int i, int b) {
-        const double2 *p = (const double2 *)slab + (size_t)(18 * b) * Vh;
         Herm6<R> M;
 #pragma unroll
         for (int k = 0; k < 3; k++) {
-            double2 v = ld_op<NT>(p + (size_t)k * Vh + i);
+            double2 v = ld_op<NT>(tp<double2, 576>(slab, i, 16 * (18 * b + k)));
             M.d[2 * k] = v.x;
             M.d[2 * k + 1] = v.y;
         }
 #pragma unroll
         for (int k = 0; k < 15; k++) {
-            double2 v = ld_op<NT>(p + (size_t)(3 + k) * Vh + i);
+            double2 v = ld_op<NT>(tp<double2, 576>(slab, i, 16 * (18 * b + 3 + k)));
             M.o[k] = {v.x, v.y};
         }
         return M;
@@ -378,11 +392,10 @@ template <> struct CloverIO<P64> {
 template <> struct CloverIO<P32> {
     using R = float;
     template <bool NT = true> __device__ static Herm6<R> load(const void *slab, int Vh, int i, int b) {
-        const float4 *p = (const float4 *)slab + (size_t)(9 * b) * Vh;
         float f[36];
 #pragma unroll
         for (int k = 0; k < 9; k++) {
-            float4 v = ld_op<NT>(p + (size_t)k * Vh + i);
+            float4 v = ld_op<NT>(tp<float4, 288>(slab, i, 16 * (9 * b + k)));
             f[4 * k] = v.x;
             f[4 * k + 1] = v.y;
             f[4 * k + 2] = v.z;
@@ -398,26 +411,22 @@ template <> struct CloverIO<P32> {
 };
 
 // FP16 clover: per block b, 4 uint4 planes then 1 uint2 plane (36 halves = 72 B per
-// site and block, block b starting at byte b * 72 Vh), then one FP32 scale per site
-// at byte 144 Vh; entry = scale * half.
+// site and block, block b at record offset 72 b), then one FP32 scale plane at
+// record offset 144; entry = scale * half.
 template <> struct CloverIO<P16> {
     using R = float;
     template <bool NT = true> __device__ static Herm6<R> load(const void *slab, int Vh, int i, int b) {
-        const char *base = (const char *)slab + (size_t)b * 72 * Vh;
-        const uint4 *p = (const uint4 *)base;
-        const uint2 *q = (const uint2 *)(base + (size_t)64 * Vh);
-        const float *sc = (const float *)((const char *)slab + (size_t)Vh * 144);
-        float s = sc[i];
+        const float s = *tp<float, 148>(slab, i, 144);
         uint32_t w[18];
 #pragma unroll
         for (int k = 0; k < 4; k++) {
-            uint4 v = ld_op<NT>(p + (size_t)k * Vh + i);
+            uint4 v = ld_op<NT>(tp<uint4, 148>(slab, i, 72 * b + 16 * k));
             w[4 * k] = v.x;
             w[4 * k + 1] = v.y;
             w[4 * k + 2] = v.z;
             w[4 * k + 3] = v.w;
         }
-        uint2 v = ld_op<NT>(q + i);
+        uint2 v = ld_op<NT>(tp<uint2, 148>(slab, i, 72 * b + 64));
         w[16] = v.x;
         w[17] = v.y;
         float f[36];
@@ -483,13 +492,13 @@ WC_HD SiteRef site_ref(const Geom &g, int x, int y, int z, int t) {
     return SiteRef{(x + y + z + t) & 1, n >> 1};
 }
 
-// U_mu at a site from the FP64 link copy ([mu][parity][9][Vh] double2)
+// U_mu at a site from the FP64 link copy (tiled slabs [mu][parity])
 __device__ __forceinline__ Mat3<double> link64(const double2 *l64, const Geom &g, int mu, SiteRef s) {
-    const double2 *p = l64 + (size_t)(2 * mu + s.par) * 9 * g.Vh;
+    const char *slab = (const char *)l64 + (size_t)(2 * mu + s.par) * link_slab_bytes(P64, g.Vh);
     Mat3<double> u;
 #pragma unroll
     for (int k = 0; k < 9; k++) {
-        double2 v = p[(size_t)k * g.Vh + s.i];
+        double2 v = *tp<double2, 144>(slab, s.i, 16 * k);
         u.m[k] = {v.x, v.y};
     }
     return u;

@@ -237,7 +237,7 @@ template <int P> void dispatch_mode(const MultBatch &B, int mode, int red, int b
 // call; the link and clover part is per lattice, since calls of one batch on
 // the same lattice read the same operator.
 double mult_spinor_bytes(int prec, int mode, int red, int Vh) {
-    const double S = (double)spinor_bytes(prec, Vh);
+    const double S = (double)spinor_site_bytes(prec) * Vh;
     double b = 2 * S;                                                    // input (once) + output
     if (mode == M_DHAT || mode == M_DFULL || mode == M_INVSRC) b += S;  // centre vector
     if (red != R_NONE) b += S;                                           // aux vector
@@ -245,8 +245,8 @@ double mult_spinor_bytes(int prec, int mode, int red, int Vh) {
 }
 double mult_operator_bytes(int prec, int mode, int Vh) {
     double b = 0;
-    if (mode != M_CLOV) b += 8 * (double)link_slab_bytes(prec, Vh);
-    if (mode != M_HOP) b += (double)clover_slab_bytes(prec, Vh);
+    if (mode != M_CLOV) b += 8 * (double)link_site_bytes(prec) * Vh;
+    if (mode != M_HOP) b += (double)clover_site_bytes(prec) * Vh;
     return b;
 }
 

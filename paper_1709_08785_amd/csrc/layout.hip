@@ -1,4 +1,4 @@
-// Layout kernels: canonical complex128 fields <-> the structure-of-arrays
+// Layout kernels: canonical complex128 fields <-> the site-tiled
 // even-odd layout, and the per-precision copies of the gauge links.
 #include "reduce.hpp"
 
@@ -17,24 +17,22 @@ __global__ __launch_bounds__(kBlock) void k_load_links(Geom g, const double2 *U,
     double2 m[9];
 #pragma unroll
     for (int k = 0; k < 9; k++) m[k] = src[k];
-    double2 *d64 = l64 + (size_t)slab * 9 * g.Vh;
+    char *d64 = (char *)l64 + (size_t)slab * link_slab_bytes(P64, g.Vh);
 #pragma unroll
-    for (int k = 0; k < 9; k++) d64[(size_t)k * g.Vh + i] = m[k];
+    for (int k = 0; k < 9; k++) *tp<double2, 144>(d64, i, 16 * k) = m[k];
     // columns 0 and 1: U00 U10 | U20 U01 | U11 U21
-    float4 *d32 = l32 + (size_t)slab * 3 * g.Vh;
-    d32[i] = make_float4((float)m[0].x, (float)m[0].y, (float)m[3].x, (float)m[3].y);
-    d32[(size_t)g.Vh + i] = make_float4((float)m[6].x, (float)m[6].y, (float)m[1].x, (float)m[1].y);
-    d32[2 * (size_t)g.Vh + i] = make_float4((float)m[4].x, (float)m[4].y, (float)m[7].x, (float)m[7].y);
-    char *b16 = l16 + (size_t)slab * 24 * g.Vh;
-    uint4 *p16 = (uint4 *)b16;
-    uint2 *q16 = (uint2 *)(b16 + (size_t)16 * g.Vh);
+    char *d32 = (char *)l32 + (size_t)slab * link_slab_bytes(P32, g.Vh);
+    *tp<float4, 48>(d32, i, 0) = make_float4((float)m[0].x, (float)m[0].y, (float)m[3].x, (float)m[3].y);
+    *tp<float4, 48>(d32, i, 16) = make_float4((float)m[6].x, (float)m[6].y, (float)m[1].x, (float)m[1].y);
+    *tp<float4, 48>(d32, i, 32) = make_float4((float)m[4].x, (float)m[4].y, (float)m[7].x, (float)m[7].y);
+    char *b16 = l16 + (size_t)slab * link_slab_bytes(P16, g.Vh);
     uint4 u;
     u.x = f2h((float)m[0].x, (float)m[0].y);
     u.y = f2h((float)m[3].x, (float)m[3].y);
     u.z = f2h((float)m[6].x, (float)m[6].y);
     u.w = f2h((float)m[1].x, (float)m[1].y);
-    p16[i] = u;
-    q16[i] = make_uint2(f2h((float)m[4].x, (float)m[4].y), f2h((float)m[7].x, (float)m[7].y));
+    *tp<uint4, 24>(b16, i, 0) = u;
+    *tp<uint2, 24>(b16, i, 16) = make_uint2(f2h((float)m[4].x, (float)m[4].y), f2h((float)m[7].x, (float)m[7].y));
 }
 
 template <int P>
