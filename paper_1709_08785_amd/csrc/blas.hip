@@ -14,6 +14,9 @@
 
 namespace {
 
+// vector operands are streamed: each is touched once per launch
+constexpr bool kVNT = true;
+
 __device__ __forceinline__ int rho_slot(int iter) { return (iter & 1) ? S_RHO1 : S_RHO0; }
 
 __device__ __forceinline__ bool finite_c(cx<double> a) { return isfinite(a.re) && isfinite(a.im); }
@@ -55,38 +58,38 @@ template <int OP, int P, int XP> __global__ __launch_bounds__(kBlock) void k_vec
 
     if (OP == V_NORM2) {
         if (active) {
-            const Spinor<double> v = SpinorIO<P64>::load(c.a, Vh, i);
+            const Spinor<double> v = SpinorIO<P64>::template load<kVNT>(c.a, Vh, i);
 #pragma unroll
             for (int k = 0; k < 12; k++) a[0] += norm2(v.c[k]);
         }
     } else if (OP == V_SUB_NORM) {
         if (active) {
-            const Spinor<double> x = SpinorIO<P64>::load(c.b, Vh, i);
-            const Spinor<double> y = SpinorIO<P64>::load(c.c, Vh, i);
+            const Spinor<double> x = SpinorIO<P64>::template load<kVNT>(c.b, Vh, i);
+            const Spinor<double> y = SpinorIO<P64>::template load<kVNT>(c.c, Vh, i);
             Spinor<double> o;
 #pragma unroll
             for (int k = 0; k < 12; k++) {
                 o.c[k] = x.c[k] - y.c[k];
                 a[0] += norm2(o.c[k]);
             }
-            SpinorIO<P64>::store(c.a, Vh, i, o);
+            SpinorIO<P64>::template store<kVNT>(c.a, Vh, i, o);
         }
     } else if (OP == V_AXPY) {
         if (active) {
-            Spinor<double> y = SpinorIO<P64>::load(c.a, Vh, i);
-            const Spinor<double> x = SpinorIO<P64>::load(c.b, Vh, i);
+            Spinor<double> y = SpinorIO<P64>::template load<kVNT>(c.a, Vh, i);
+            const Spinor<double> x = SpinorIO<P64>::template load<kVNT>(c.b, Vh, i);
 #pragma unroll
             for (int k = 0; k < 12; k++) y.c[k] = y.c[k] + c.coef * x.c[k];
-            SpinorIO<P64>::store(c.a, Vh, i, y);
+            SpinorIO<P64>::template store<kVNT>(c.a, Vh, i, y);
         }
     } else if (OP == V_COPY) {
-        if (active) SpinorIO<P64>::store(c.a, Vh, i, SpinorIO<P64>::load(c.b, Vh, i));
+        if (active) SpinorIO<P64>::template store<kVNT>(c.a, Vh, i, SpinorIO<P64>::template load<kVNT>(c.b, Vh, i));
     } else if (OP == V_ZERO) {
         if (active) {
             Spinor<double> z;
 #pragma unroll
             for (int k = 0; k < 12; k++) z.c[k] = {0.0, 0.0};
-            SpinorIO<P64>::store(c.a, Vh, i, z);
+            SpinorIO<P64>::template store<kVNT>(c.a, Vh, i, z);
         }
     } else if (OP == V_GAMMA5) {
         // g5 = -[[0, 1], [1, 0]] in upper/lower spin blocks, both parity slabs
@@ -107,18 +110,18 @@ template <int OP, int P, int XP> __global__ __launch_bounds__(kBlock) void k_vec
         if (active) {
             const double nrm2 = c.sc[S_NORM];
             const double inv = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
-            const Spinor<double> v = SpinorIO<P64>::load(c.a, Vh, i);
+            const Spinor<double> v = SpinorIO<P64>::template load<kVNT>(c.a, Vh, i);
             Spinor<R> b;
 #pragma unroll
             for (int k = 0; k < 12; k++) b.c[k] = {(R)(inv * v.c[k].re), (R)(inv * v.c[k].im)};
-            SpinorIO<P>::store(c.b, Vh, i, b);
-            SpinorIO<P>::store(c.c, Vh, i, b);
-            SpinorIO<P>::store(c.d, Vh, i, b);
+            SpinorIO<P>::template store<kVNT>(c.b, Vh, i, b);
+            SpinorIO<P>::template store<kVNT>(c.c, Vh, i, b);
+            SpinorIO<P>::template store<kVNT>(c.d, Vh, i, b);
             Spinor<RX> z;
 #pragma unroll
             for (int k = 0; k < 12; k++) z.c[k] = {RX(0), RX(0)};
-            SpinorIO<XP>::store(c.e, Vh, i, z);
-            const Spinor<R> bs = SpinorIO<P>::load(c.b, Vh, i);
+            SpinorIO<XP>::template store<kVNT>(c.e, Vh, i, z);
+            const Spinor<R> bs = SpinorIO<P>::template load<kVNT>(c.b, Vh, i);
 #pragma unroll
             for (int k = 0; k < 12; k++) a[0] += norm2(bs.c[k]);
         }
@@ -126,11 +129,11 @@ template <int OP, int P, int XP> __global__ __launch_bounds__(kBlock) void k_vec
         // alpha = rho0 / <r~, q>;  s = r - alpha q (in place in r);  ||s||^2
         const cx<R> alpha = to<R>(cdiv(ld_c(c.sc, rho_slot(iter)), ld_c(c.sc, S_RQ)));
         if (active) {
-            Spinor<R> rv = SpinorIO<P>::load(c.a, Vh, i);
-            const Spinor<R> qv = SpinorIO<P>::load(c.b, Vh, i);
+            Spinor<R> rv = SpinorIO<P>::template load<kVNT>(c.a, Vh, i);
+            const Spinor<R> qv = SpinorIO<P>::template load<kVNT>(c.b, Vh, i);
 #pragma unroll
             for (int k = 0; k < 12; k++) rv.c[k] = rv.c[k] - alpha * qv.c[k];
-            SpinorIO<P>::store(c.a, Vh, i, rv);
+            SpinorIO<P>::template store<kVNT>(c.a, Vh, i, rv);
 #pragma unroll
             for (int k = 0; k < 12; k++) a[0] += norm2(rv.c[k]);
         }
@@ -142,20 +145,20 @@ template <int OP, int P, int XP> __global__ __launch_bounds__(kBlock) void k_vec
         const cx<RX> alx = to<RX>(al), omx = to<RX>(om);
         const cx<R> omega = to<R>(om);
         if (active) {
-            Spinor<R> sv = SpinorIO<P>::load(c.b, Vh, i);
-            const Spinor<R> pv = SpinorIO<P>::load(c.c, Vh, i);
-            Spinor<RX> xv = SpinorIO<XP>::load(c.a, Vh, i);
+            Spinor<R> sv = SpinorIO<P>::template load<kVNT>(c.b, Vh, i);
+            const Spinor<R> pv = SpinorIO<P>::template load<kVNT>(c.c, Vh, i);
+            Spinor<RX> xv = SpinorIO<XP>::template load<kVNT>(c.a, Vh, i);
 #pragma unroll
             for (int k = 0; k < 12; k++) {
                 const cx<RX> pk = {(RX)pv.c[k].re, (RX)pv.c[k].im}, sk = {(RX)sv.c[k].re, (RX)sv.c[k].im};
                 xv.c[k] = xv.c[k] + alx * pk + omx * sk;
             }
-            SpinorIO<XP>::store(c.a, Vh, i, xv);
-            const Spinor<R> tv = SpinorIO<P>::load(c.d, Vh, i);
+            SpinorIO<XP>::template store<kVNT>(c.a, Vh, i, xv);
+            const Spinor<R> tv = SpinorIO<P>::template load<kVNT>(c.d, Vh, i);
 #pragma unroll
             for (int k = 0; k < 12; k++) sv.c[k] = sv.c[k] - omega * tv.c[k];
-            SpinorIO<P>::store(c.b, Vh, i, sv);
-            const Spinor<R> rtv = SpinorIO<P>::load(c.e, Vh, i);
+            SpinorIO<P>::template store<kVNT>(c.b, Vh, i, sv);
+            const Spinor<R> rtv = SpinorIO<P>::template load<kVNT>(c.e, Vh, i);
 #pragma unroll
             for (int k = 0; k < 12; k++) {
                 a[0] += norm2(sv.c[k]);
@@ -172,60 +175,60 @@ template <int OP, int P, int XP> __global__ __launch_bounds__(kBlock) void k_vec
             const double tt = c.sc[S_TT];
             const cx<double> om = {c.sc[S_ST] / tt, -c.sc[S_ST + 1] / tt};
             const cx<R> beta = to<R>(cdiv(rho1, rho0) * cdiv(al, om)), omega = to<R>(om);
-            Spinor<R> pv = SpinorIO<P>::load(c.a, Vh, i);
-            const Spinor<R> rv = SpinorIO<P>::load(c.b, Vh, i);
-            const Spinor<R> qv = SpinorIO<P>::load(c.c, Vh, i);
+            Spinor<R> pv = SpinorIO<P>::template load<kVNT>(c.a, Vh, i);
+            const Spinor<R> rv = SpinorIO<P>::template load<kVNT>(c.b, Vh, i);
+            const Spinor<R> qv = SpinorIO<P>::template load<kVNT>(c.c, Vh, i);
 #pragma unroll
             for (int k = 0; k < 12; k++) pv.c[k] = rv.c[k] + beta * (pv.c[k] - omega * qv.c[k]);
-            SpinorIO<P>::store(c.a, Vh, i, pv);
+            SpinorIO<P>::template store<kVNT>(c.a, Vh, i, pv);
         }
     } else if (OP == V_INNER_FIX) {
         // x += alpha p (the update skipped when the half step already converged)
         if (active) {
             const cx<RX> alx = to<RX>(cdiv(ld_c(c.sc, rho_slot(iter)), ld_c(c.sc, S_RQ)));
-            Spinor<RX> xv = SpinorIO<XP>::load(c.a, Vh, i);
-            const Spinor<R> pv = SpinorIO<P>::load(c.b, Vh, i);
+            Spinor<RX> xv = SpinorIO<XP>::template load<kVNT>(c.a, Vh, i);
+            const Spinor<R> pv = SpinorIO<P>::template load<kVNT>(c.b, Vh, i);
 #pragma unroll
             for (int k = 0; k < 12; k++) xv.c[k] = xv.c[k] + alx * cx<RX>{(RX)pv.c[k].re, (RX)pv.c[k].im};
-            SpinorIO<XP>::store(c.a, Vh, i, xv);
+            SpinorIO<XP>::template store<kVNT>(c.a, Vh, i, xv);
         }
     } else if (OP == V_INNER_FINAL) {
         // v = ||src|| x into FP64 (Algorithm 2, last step)
         if (active) {
             const double nrm = sqrt(c.sc[S_NORM]);
-            const Spinor<RX> xv = SpinorIO<XP>::load(c.b, Vh, i);
+            const Spinor<RX> xv = SpinorIO<XP>::template load<kVNT>(c.b, Vh, i);
             Spinor<double> o;
 #pragma unroll
             for (int k = 0; k < 12; k++) o.c[k] = {nrm * (double)xv.c[k].re, nrm * (double)xv.c[k].im};
-            SpinorIO<P64>::store(c.a, Vh, i, o);
+            SpinorIO<P64>::template store<kVNT>(c.a, Vh, i, o);
         }
     } else if (OP == V_OUTER_A) {
         // alpha = rho0 / <r~, q>;  x += alpha v;  r -= alpha q;  ||r||^2
         const cx<double> al = cdiv(ld_c(c.sc, rho_slot(iter)), ld_c(c.sc, S_RQ));
         if (active) {
-            Spinor<double> xv = SpinorIO<P64>::load(c.a, Vh, i);
-            Spinor<double> rv = SpinorIO<P64>::load(c.b, Vh, i);
-            const Spinor<double> vv = SpinorIO<P64>::load(c.c, Vh, i);
-            const Spinor<double> qv = SpinorIO<P64>::load(c.d, Vh, i);
+            Spinor<double> xv = SpinorIO<P64>::template load<kVNT>(c.a, Vh, i);
+            Spinor<double> rv = SpinorIO<P64>::template load<kVNT>(c.b, Vh, i);
+            const Spinor<double> vv = SpinorIO<P64>::template load<kVNT>(c.c, Vh, i);
+            const Spinor<double> qv = SpinorIO<P64>::template load<kVNT>(c.d, Vh, i);
 #pragma unroll
             for (int k = 0; k < 12; k++) {
                 xv.c[k] = xv.c[k] + al * vv.c[k];
                 rv.c[k] = rv.c[k] - al * qv.c[k];
                 a[0] += norm2(rv.c[k]);
             }
-            SpinorIO<P64>::store(c.a, Vh, i, xv);
-            SpinorIO<P64>::store(c.b, Vh, i, rv);
+            SpinorIO<P64>::template store<kVNT>(c.a, Vh, i, xv);
+            SpinorIO<P64>::template store<kVNT>(c.b, Vh, i, rv);
         }
     } else if (OP == V_OUTER_B) {
         // omega = <t, r> / ||t||^2;  x += omega v;  r -= omega t;  ||r||^2, <r~, r>
         const double tt = c.sc[S_TT];
         const cx<double> om = {c.sc[S_ST] / tt, -c.sc[S_ST + 1] / tt};
         if (active) {
-            Spinor<double> xv = SpinorIO<P64>::load(c.a, Vh, i);
-            Spinor<double> rv = SpinorIO<P64>::load(c.b, Vh, i);
-            const Spinor<double> vv = SpinorIO<P64>::load(c.c, Vh, i);
-            const Spinor<double> tv = SpinorIO<P64>::load(c.d, Vh, i);
-            const Spinor<double> rtv = SpinorIO<P64>::load(c.e, Vh, i);
+            Spinor<double> xv = SpinorIO<P64>::template load<kVNT>(c.a, Vh, i);
+            Spinor<double> rv = SpinorIO<P64>::template load<kVNT>(c.b, Vh, i);
+            const Spinor<double> vv = SpinorIO<P64>::template load<kVNT>(c.c, Vh, i);
+            const Spinor<double> tv = SpinorIO<P64>::template load<kVNT>(c.d, Vh, i);
+            const Spinor<double> rtv = SpinorIO<P64>::template load<kVNT>(c.e, Vh, i);
 #pragma unroll
             for (int k = 0; k < 12; k++) {
                 xv.c[k] = xv.c[k] + om * vv.c[k];
@@ -235,8 +238,8 @@ template <int OP, int P, int XP> __global__ __launch_bounds__(kBlock) void k_vec
                 a[1 % NA] += ar * br + ai * bi;
                 a[2 % NA] += ar * bi - ai * br;
             }
-            SpinorIO<P64>::store(c.a, Vh, i, xv);
-            SpinorIO<P64>::store(c.b, Vh, i, rv);
+            SpinorIO<P64>::template store<kVNT>(c.a, Vh, i, xv);
+            SpinorIO<P64>::template store<kVNT>(c.b, Vh, i, rv);
         }
     }
     if (N > 0) block_partials<NA>(a, c.partials, (Vh + kBlock - 1) / kBlock, lb);

@@ -184,6 +184,21 @@ __device__ __forceinline__ uint2 ld_stream(const uint2 *p) {
     nt_u2 v = __builtin_nontemporal_load((const nt_u2 *)p);
     return make_uint2(v.x, v.y);
 }
+__device__ __forceinline__ float ld_stream(const float *p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ void st_stream(float4 *p, float4 v) {
+    __builtin_nontemporal_store(nt_f4{v.x, v.y, v.z, v.w}, (nt_f4 *)p);
+}
+__device__ __forceinline__ void st_stream(double2 *p, double2 v) {
+    __builtin_nontemporal_store(nt_d2{v.x, v.y}, (nt_d2 *)p);
+}
+__device__ __forceinline__ void st_stream(uint4 *p, uint4 v) {
+    __builtin_nontemporal_store(nt_u4{v.x, v.y, v.z, v.w}, (nt_u4 *)p);
+}
+__device__ __forceinline__ void st_stream(float *p, float v) { __builtin_nontemporal_store(v, p); }
+template <bool NT, class T> __device__ __forceinline__ void st_op(T *p, T v) {
+    if (NT) st_stream(p, v);
+    else *p = v;
+}
 // operand load: non-temporal when NT (read once per launch), cached otherwise
 // (operands that several systems of one batched launch read)
 template <bool NT, class T> __device__ __forceinline__ T ld_op(const T *p) {
@@ -208,49 +223,50 @@ template <int P> struct SpinorIO;
 
 template <> struct SpinorIO<P64> {
     using R = double;
-    __device__ static Spinor<R> load(const void *base, int Vh, int i) {
+    template <bool NT = false> __device__ static Spinor<R> load(const void *base, int Vh, int i) {
         Spinor<R> s;
 #pragma unroll
         for (int k = 0; k < 12; k++) {
-            double2 v = *tp<double2, 192>(base, i, 16 * k);
+            double2 v = ld_op<NT>(tp<double2, 192>(base, i, 16 * k));
             s.c[k] = {v.x, v.y};
         }
         return s;
     }
-    __device__ static void store(void *base, int Vh, int i, const Spinor<R> &s) {
+    template <bool NT = false> __device__ static void store(void *base, int Vh, int i, const Spinor<R> &s) {
 #pragma unroll
-        for (int k = 0; k < 12; k++) *tp<double2, 192>(base, i, 16 * k) = make_double2(s.c[k].re, s.c[k].im);
+        for (int k = 0; k < 12; k++) st_op<NT>(tp<double2, 192>(base, i, 16 * k), make_double2(s.c[k].re, s.c[k].im));
     }
 };
 
 template <> struct SpinorIO<P32> {
     using R = float;
-    __device__ static Spinor<R> load(const void *base, int Vh, int i) {
+    template <bool NT = false> __device__ static Spinor<R> load(const void *base, int Vh, int i) {
         Spinor<R> s;
 #pragma unroll
         for (int k = 0; k < 6; k++) {
-            float4 v = *tp<float4, 96>(base, i, 16 * k);
+            float4 v = ld_op<NT>(tp<float4, 96>(base, i, 16 * k));
             s.c[2 * k] = {v.x, v.y};
             s.c[2 * k + 1] = {v.z, v.w};
         }
         return s;
     }
-    __device__ static void store(void *base, int Vh, int i, const Spinor<R> &s) {
+    template <bool NT = false> __device__ static void store(void *base, int Vh, int i, const Spinor<R> &s) {
 #pragma unroll
         for (int k = 0; k < 6; k++)
-            *tp<float4, 96>(base, i, 16 * k) = make_float4(s.c[2 * k].re, s.c[2 * k].im, s.c[2 * k + 1].re, s.c[2 * k + 1].im);
+            st_op<NT>(tp<float4, 96>(base, i, 16 * k),
+                      make_float4(s.c[2 * k].re, s.c[2 * k].im, s.c[2 * k + 1].re, s.c[2 * k + 1].im));
     }
 };
 
 // FP16 storage: planes of uint4 (3 * 16 B) followed by a float scale plane at 48
 template <> struct SpinorIO<P16> {
     using R = float;
-    __device__ static Spinor<R> load(const void *base, int Vh, int i) {
-        const float s = *tp<float, 52>(base, i, 48);
+    template <bool NT = false> __device__ static Spinor<R> load(const void *base, int Vh, int i) {
+        const float s = ld_op<NT>(tp<float, 52>(base, i, 48));
         Spinor<R> out;
 #pragma unroll
         for (int k = 0; k < 3; k++) {
-            uint4 v = *tp<uint4, 52>(base, i, 16 * k);
+            uint4 v = ld_op<NT>(tp<uint4, 52>(base, i, 16 * k));
             float2 a = h2f(v.x), b = h2f(v.y), c = h2f(v.z), d = h2f(v.w);
             out.c[4 * k + 0] = {s * a.x, s * a.y};
             out.c[4 * k + 1] = {s * b.x, s * b.y};
@@ -259,7 +275,7 @@ template <> struct SpinorIO<P16> {
         }
         return out;
     }
-    __device__ static void store(void *base, int Vh, int i, const Spinor<R> &v) {
+    template <bool NT = false> __device__ static void store(void *base, int Vh, int i, const Spinor<R> &v) {
         float m = 0.f;
 #pragma unroll
         for (int k = 0; k < 12; k++) m = fmaxf(m, fmaxf(fabsf(v.c[k].re), fabsf(v.c[k].im)));
@@ -271,9 +287,9 @@ template <> struct SpinorIO<P16> {
             u.y = f2h(v.c[4 * k + 1].re * inv, v.c[4 * k + 1].im * inv);
             u.z = f2h(v.c[4 * k + 2].re * inv, v.c[4 * k + 2].im * inv);
             u.w = f2h(v.c[4 * k + 3].re * inv, v.c[4 * k + 3].im * inv);
-            *tp<uint4, 52>(base, i, 16 * k) = u;
+            st_op<NT>(tp<uint4, 52>(base, i, 16 * k), u);
         }
-        *tp<float, 52>(base, i, 48) = m;
+        st_op<NT>(tp<float, 52>(base, i, 48), m);
     }
 };
 

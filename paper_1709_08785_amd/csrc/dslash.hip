@@ -170,26 +170,26 @@ __global__ __launch_bounds__(kBlock) void k_mult(MultBatch B) {
         } else if (MODE == M_DHAT) {
             Spinor<R> t;
             clover_apply<P, R, NT>(a.clov, Vh, i, acc, t);
-            const Spinor<R> cen = SpinorIO<P>::load(a.center, Vh, i);
+            const Spinor<R> cen = SpinorIO<P>::template load<true>(a.center, Vh, i);
 #pragma unroll
             for (int k = 0; k < 12; k++) out.c[k] = cen.c[k] + coef * t.c[k];
         } else if (MODE == M_DFULL) {
-            const Spinor<R> cen = SpinorIO<P>::load(a.center, Vh, i);
+            const Spinor<R> cen = SpinorIO<P>::template load<true>(a.center, Vh, i);
             clover_apply<P, R, NT>(a.clov, Vh, i, cen, out);
 #pragma unroll
             for (int k = 0; k < 12; k++) out.c[k] = out.c[k] + coef * acc.c[k];
         } else if (MODE == M_INVSRC) {
-            Spinor<R> s = SpinorIO<P>::load(a.center, Vh, i);
+            Spinor<R> s = SpinorIO<P>::template load<true>(a.center, Vh, i);
 #pragma unroll
             for (int k = 0; k < 12; k++) s.c[k] = s.c[k] + coef * acc.c[k];
             clover_apply<P, R, NT>(a.clov, Vh, i, s, out);
         } else if (MODE == M_CLOV) {
-            const Spinor<R> cen = SpinorIO<P>::load(a.center, Vh, i);
+            const Spinor<R> cen = SpinorIO<P>::template load<true>(a.center, Vh, i);
             clover_apply<P, R, NT>(a.clov, Vh, i, cen, out);
         } else {
             out = acc;
         }
-        SpinorIO<P>::store(a.out, Vh, i, out);
+        SpinorIO<P>::template store<P == P64>(a.out, Vh, i, out);
     }
     if (RED != R_NONE) {
         constexpr int N = (RED == R_DOT) ? 2 : 3;
@@ -197,7 +197,7 @@ __global__ __launch_bounds__(kBlock) void k_mult(MultBatch B) {
 #pragma unroll
         for (int k = 0; k < N; k++) v[k] = 0.0;
         if (active) {
-            const Spinor<R> ax = SpinorIO<P>::load(a.aux, Vh, i);
+            const Spinor<R> ax = SpinorIO<P>::template load<true>(a.aux, Vh, i);
 #pragma unroll
             for (int k = 0; k < 12; k++) {
                 const double ar = ax.c[k].re, ai = ax.c[k].im, orr = out.c[k].re, oi = out.c[k].im;
