@@ -115,7 +115,9 @@ def dslash_mode(args, dims):
     lat.build_clover(args.kappa, args.csw)
     psid = torch.from_numpy(psi).to(dev)
     res = {}
-    for name, prec in [("fp32", wc.FP32), ("fp16", wc.FP16), ("fp64", wc.FP64)]:
+    for name, prec, recon in [("fp32", wc.FP32, 12), ("fp16", wc.FP16, 12), ("fp64", wc.FP64, 12),
+                              ("fp32", wc.FP32, 8)]:
+        lat.set_link_recon(recon)
         eo = lat.pack(psid, prec)
         out = lat.new_eo(prec, 1)
         e_in = lat.parity_view(eo, 0, prec)
@@ -134,7 +136,8 @@ def dslash_mode(args, dims):
         st = lat.kernel_stats()
         for kname, v in st.items():
             if v["launches"]:
-                res[kname] = {"launches": v["launches"], "avg_us": round(v["ms"] / v["launches"] * 1e3, 2),
+                res[kname + ("_recon8" if recon == 8 else "")] = {
+                              "launches": v["launches"], "avg_us": round(v["ms"] / v["launches"] * 1e3, 2),
                               "algorithmic_GBs": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1),
                               "frac_hbm": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                               "bytes_per_launch": v["bytes"] / v["launches"]}
@@ -304,6 +307,7 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--inner-tol", type=float, default=1e-6)
     ap.add_argument("--inner", type=str, default="fp32")
+    ap.add_argument("--recon", type=int, default=12, choices=[12, 8])
     ap.add_argument("--no-fp64-arm", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=1002)
@@ -341,6 +345,7 @@ def main():
     bd = torch.from_numpy(b).to(dev)
     lat.load_links(Ud)
     lat.build_clover(args.kappa, args.csw)
+    lat.set_link_recon(args.recon)
     del Ud
     torch.cuda.synchronize()
     inner = wc._prec(args.inner)
@@ -392,6 +397,7 @@ def main():
     # the all-FP64 arm on the same system
     fp64 = None
     fp16 = None
+    recon8 = None
     if not args.no_fp64_arm:
         x64, info64 = lat.solve(bd, args.kappa, args.csw, args.tol, inner_prec=wc.FP64)
         torch.cuda.synchronize()
@@ -416,6 +422,26 @@ def main():
                 "solution_rel_diff_vs_fp64": float(torch.linalg.norm(x16 - x64) / torch.linalg.norm(x64)),
                 "speedup_vs_fp64": round(t64 / t16, 3)}
         del x16
+        # the FP32-inner form with reconstruct-8 links in the inner stencils
+        if args.recon == 12:
+            recon8 = {}
+            lat.set_link_recon(8)
+            for name, prec in [("fp32_inner", wc.FP32)]:
+                lat.solve(bd, args.kappa, args.csw, args.tol, inner_prec=prec)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                x8, info8 = lat.solve(bd, args.kappa, args.csw, args.tol, inner_prec=prec)
+                torch.cuda.synchronize()
+                t8 = time.perf_counter() - t1
+                log("recon8 %s arm: %s" % (name, json.dumps(info8)))
+                recon8[name] = {"seconds": round(t8, 4), "inner_iters": info8["inner_iters_total"],
+                                "outer_iters": info8["outer_iters"],
+                                "true_rel_residual": info8["true_rel_residual"],
+                                "solution_rel_diff_vs_fp64": float(torch.linalg.norm(x8 - x64) /
+                                                                   torch.linalg.norm(x64)),
+                                "speedup_vs_fp64": round(t64 / t8, 3)}
+                del x8
+            lat.set_link_recon(args.recon)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -442,14 +468,16 @@ def main():
                                % ("x".join(map(str, dims)), args.kappa, args.csw, args.inner.upper(),
                                   args.inner_tol, args.tol),
                    "lattice": list(dims), "kappa": args.kappa, "csw": args.csw, "tol": args.tol,
-                   "inner": args.inner, "inner_tol": args.inner_tol},
+                   "inner": args.inner, "inner_tol": args.inner_tol, "link_recon": args.recon},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "time_to_solution_s": {"mixed": round(ms_per_step / 1e3, 4), "fp64": fp64["seconds"] if fp64 else None,
-                               "mixed_fp16_inner": fp16["seconds"] if fp16 else None},
+                               "mixed_fp16_inner": fp16["seconds"] if fp16 else None,
+                               "mixed_recon8": recon8["fp32_inner"]["seconds"] if recon8 else None},
         "speedup_mixed_vs_fp64": round(fp64["seconds"] / (ms_per_step / 1e3), 3) if fp64 else None,
         "fp64_arm": fp64,
         "fp16_inner_arm": fp16,
+        "recon8_arms": recon8,
         "solve": {"outer_iters": last["outer_iters"], "inner_iters": last["inner_iters_total"],
                   "inner_calls": last["inner_calls"], "restarts": last["restarts"],
                   "true_rel_residual": last["true_rel_residual"], "dslash_count": last["dslash_count"]},

@@ -118,6 +118,24 @@ int wc_set_stream(wc_lattice *lat, void *stream);
    clover term. */
 int wc_load_links(wc_lattice *lat, const void *U_dev);
 
+/* Choose how the FP32 stencil stores links (Sec. III-A: each MULT reads every
+   link once, so links are 44% of its bytes): recon = 12 (default, two columns,
+   48 B) or 8 (eight reals, 32 B: U01, U02, the smaller in modulus of U10 and
+   U20, and the phases of U00 and of the other one; the remaining entries follow
+   from unitarity and det U = 1, exact up to a few FP32 rounding steps).  FP64
+   always keeps full matrices; FP16 always keeps two columns (rebuilding from
+   eight half-precision reals loses too many of its bits).  recon = 8 builds the
+   extra copy from the loaded links and returns WC_EINVAL, leaving the setting
+   unchanged, if some link has |U01|^2 + |U02|^2 < 1e-6 (unit links, for
+   instance); WC_ENOTREADY before wc_load_links.  A later wc_load_links rebuilds
+   the copy; if the new links fail the same check it returns WC_EINVAL and the
+   lattice falls back to 12 (the links themselves are loaded).  Applies to every
+   later FP32 apply and solve on this lattice; one batched solve needs the same
+   setting on all its lattices. */
+int wc_set_link_recon(wc_lattice *lat, int recon);
+/* The current setting (12 or 8); 0 for a null lattice. */
+int wc_link_recon(const wc_lattice *lat);
+
 /* Build the clover term F (Sec. II-A) from the loaded links in FP64, split into
    its two 6x6 Hermitian chiral blocks (Sec. III-A), invert them in FP64, and keep
    FP64, FP32 and FP16 copies of F and F^-1.  WC_ENOTREADY before wc_load_links. */

@@ -73,6 +73,8 @@ def load_library():
         "wc_set_stream": (I, [P, P]),
         "wc_load_links": (I, [P, P]),
         "wc_build_clover": (I, [P, D, D]),
+        "wc_set_link_recon": (I, [P, I]),
+        "wc_link_recon": (I, [P]),
         "wc_spinor_bytes": (ctypes.c_size_t, [P, I]),
         "wc_pack_spinor": (I, [P, P, P, I]),
         "wc_unpack_spinor": (I, [P, P, P, I]),
@@ -167,6 +169,15 @@ class Lattice:
         if getattr(self, "_links_key", None) != key:
             self.load_links(U.detach().contiguous())
             self._links_key = key
+
+    def set_link_recon(self, recon: int):
+        """Link storage of the FP32/FP16 stencils: 12 (two columns) or 8 (eight reals)."""
+        self._sync_stream()
+        _check(self.lib.wc_set_link_recon(self.h, int(recon)))
+
+    @property
+    def link_recon(self) -> int:
+        return int(self.lib.wc_link_recon(self.h))
 
     def build_clover(self, kappa: float, csw: float):
         self._sync_stream()

@@ -214,6 +214,8 @@ static void free_all(wc_lattice *lat) {
         if (lat->clov[p]) (void)hipFree(lat->clov[p]);
         if (lat->clovinv[p]) (void)hipFree(lat->clovinv[p]);
     }
+    if (lat->links8) (void)hipFree(lat->links8);
+    if (lat->recon_min) (void)hipFree(lat->recon_min);
     for (int k = 0; k < LW_COUNT; k++)
         if (lat->lwork[k]) (void)hipFree(lat->lwork[k]);
     free_work(lat->swork);
@@ -358,6 +360,8 @@ extern "C" int wc_solve_multi(int n, wc_lattice *const *lats, const void *const 
         for (int j = 0; j < k; j++)
             if (lats[j] == lats[k] && (kappa[j] != kappa[k] || csw[j] != csw[k]))
                 return wc_fail(WC_EINVAL, "systems on one lattice must share kappa and csw");
+        if (lats[k]->recon != lats[0]->recon)
+            return wc_fail(WC_EINVAL, "lattices of one batched solve must share the link reconstruction");
         if (int rc = prepare_lattice(lats[k], kappa[k], csw[k])) return rc;
     }
     wc_lattice *lead = lats[0];
@@ -429,6 +433,31 @@ extern "C" size_t wc_spinor_bytes(const wc_lattice *lat, int prec) {
     return spinor_bytes(prec, lat->Vh);
 }
 
+// reconstruct-8 copies of the current links; refuses links whose first row
+// puts (almost) all its weight on U00, where the parametrisation breaks down
+static int build_recon8(wc_lattice *lat) {
+    if (!lat->links8) {
+        int rc = dev_alloc(&lat->links8, 8 * link8_slab_bytes(lat->Vh));
+        if (rc) return rc;
+    }
+    if (!lat->recon_min) {
+        int rc = dev_alloc((void **)&lat->recon_min, sizeof(unsigned));
+        if (rc) return rc;
+    }
+    const unsigned init = 0x7f7fffffu;  // FLT_MAX
+    WC_HIP(hipMemcpyAsync(lat->recon_min, &init, sizeof(init), hipMemcpyHostToDevice, lat->stream));
+    if (int rc = launch_links_recon8(lat, lat->recon_min)) return rc;
+    unsigned bits = 0;
+    WC_HIP(hipMemcpyAsync(&bits, lat->recon_min, sizeof(bits), hipMemcpyDeviceToHost, lat->stream));
+    WC_HIP(hipStreamSynchronize(lat->stream));
+    float nmin;
+    std::memcpy(&nmin, &bits, sizeof(nmin));
+    if (!(nmin >= kRecon8MinN))
+        return wc_fail(WC_EINVAL, "reconstruct-8 needs |U01|^2 + |U02|^2 >= " + std::to_string(kRecon8MinN) +
+                                      " on every link; smallest found: " + std::to_string(nmin));
+    return WC_OK;
+}
+
 extern "C" int wc_load_links(wc_lattice *lat, const void *U_dev) {
     if (!lat || !U_dev) return wc_fail(WC_EINVAL, "null lattice or link pointer");
     for (int p = 0; p < 3; p++) {
@@ -442,8 +471,29 @@ extern "C" int wc_load_links(wc_lattice *lat, const void *U_dev) {
     lat->gen++;
     lat->have_links = true;
     lat->have_clover = false;
+    if (lat->recon == 8) {
+        // keep the reconstruct-8 copies in step; links they cannot hold switch it off
+        rc = build_recon8(lat);
+        if (rc) lat->recon = 12;
+        return rc;
+    }
     return WC_OK;
 }
+
+extern "C" int wc_set_link_recon(wc_lattice *lat, int recon) {
+    if (!lat) return wc_fail(WC_EINVAL, "null lattice");
+    if (recon != 12 && recon != 8) return wc_fail(WC_EINVAL, "link reconstruction must be 12 or 8");
+    if (recon == lat->recon) return WC_OK;
+    if (recon == 8) {
+        if (!lat->have_links) return wc_fail(WC_ENOTREADY, "wc_set_link_recon(8) before wc_load_links");
+        if (int rc = build_recon8(lat)) return rc;
+    }
+    lat->recon = recon;
+    lat->gen++;
+    return WC_OK;
+}
+
+extern "C" int wc_link_recon(const wc_lattice *lat) { return lat ? lat->recon : 0; }
 
 extern "C" int wc_build_clover(wc_lattice *lat, double kappa, double csw) {
     if (!lat) return wc_fail(WC_EINVAL, "null lattice");

@@ -361,6 +361,71 @@ template <> struct LinkIO<P16> {
 };
 
 // ---------------------------------------------------------------------------
+// links from 8 real parameters (reconstruct-8), FP32 storage
+//   Stored per link: a2 = U01, a3 = U02, y, t_a = arg(U00)/pi and t_z.
+//   With N = |U01|^2 + |U02|^2 = |U10|^2 + |U20|^2 (unit first row and first
+//   column), y is whichever of U10, U20 has the smaller modulus and the other,
+//   z, is rebuilt from |z|^2 = N - |y|^2 >= N/2, a subtraction that cannot
+//   cancel; t_z = arg(z)/pi, plus 3 when y holds U20.  |U00|^2 = 1 - N.
+//   Writing a1 = U00, b1 = U10, c1 = U20, orthogonality of the rows to the
+//   first row and det U = 1 fix the remaining 2x2 block:
+//     U11 = -(b1 a1* a2 + c1* a3*) / N      U12 = (c1* a2* - b1 a1* a3) / N
+//     U21 = (b1* a3* - c1 a1* a2) / N       U22 = -(c1 a1* a3 + b1* a2*) / N
+//   Two float4 planes: (a2 | a3), (y | t_a, t_z)                  (32 B/site)
+//   The rebuilt entries carry a few FP32 rounding steps (every numerator
+//   term is O(N), so dividing by N does not amplify them); N must not vanish,
+//   and the library checks its minimum before use.
+// ---------------------------------------------------------------------------
+WC_HD size_t link8_slab_bytes(int Vh) { return (size_t)pad_sites(Vh) * 32; }
+
+__device__ __forceinline__ Mat3<float> recon8(cx<float> a2, cx<float> a3, cx<float> y, float ta, float tz) {
+    const float N = norm2(a2) + norm2(a3);
+    const bool swap = tz > 2.0f;
+    const float t = swap ? tz - 3.0f : tz;
+    float sa, ca, sz, cz;
+    sincospif(ta, &sa, &ca);
+    sincospif(t, &sz, &cz);
+    const float ma = sqrtf(fmaxf(1.0f - N, 0.0f));
+    const float mz = sqrtf(fmaxf(N - norm2(y), 0.0f));
+    const cx<float> a1 = {ma * ca, ma * sa}, z = {mz * cz, mz * sz};
+    const cx<float> b1 = swap ? z : y, c1 = swap ? y : z;
+    const float inv = 1.0f / N;
+    const cx<float> ba = cmulc(a1, b1), ca1 = cmulc(a1, c1);  // b1 a1*, c1 a1*
+    const cx<float> c1a3 = conjx(c1 * a3), c1a2 = conjx(c1 * a2), b1a3 = conjx(b1 * a3), b1a2 = conjx(b1 * a2);
+    Mat3<float> u;
+    u.m[0] = a1;
+    u.m[1] = a2;
+    u.m[2] = a3;
+    u.m[3] = b1;
+    u.m[6] = c1;
+    u.m[4] = -inv * (ba * a2 + c1a3);
+    u.m[5] = inv * (c1a2 - ba * a3);
+    u.m[7] = inv * (b1a3 - ca1 * a2);
+    u.m[8] = -inv * (ca1 * a3 + b1a2);
+    return u;
+}
+
+struct Link8IO {
+    template <bool NT = true> __device__ static Mat3<float> load(const void *slab, int Vh, int i) {
+        const float4 a = ld_op<NT>(tp<float4, 32>(slab, i, 0));
+        const float4 b = ld_op<NT>(tp<float4, 32>(slab, i, 16));
+        return recon8({a.x, a.y}, {a.z, a.w}, {b.x, b.y}, b.z, b.w);
+    }
+};
+
+// the link accessor a stencil instance uses: R8 selects reconstruct-8 (FP32 only)
+template <int P, bool R8> struct LinkLoad {
+    template <bool NT> __device__ static Mat3<typename Real<P>::T> load(const void *slab, int Vh, int i) {
+        return LinkIO<P>::template load<NT>(slab, Vh, i);
+    }
+};
+template <> struct LinkLoad<P32, true> {
+    template <bool NT> __device__ static Mat3<float> load(const void *slab, int Vh, int i) {
+        return Link8IO::template load<NT>(slab, Vh, i);
+    }
+};
+
+// ---------------------------------------------------------------------------
 // clover blocks: y = M w for a packed Hermitian 6x6 M
 // ---------------------------------------------------------------------------
 template <class R> struct Herm6 {

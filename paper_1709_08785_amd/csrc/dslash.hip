@@ -112,7 +112,7 @@ __device__ __forceinline__ void hop_term(const Spinor<R> &p, const Mat3<R> &U, S
     }
 }
 
-template <int P, int MU, bool NT>
+template <int P, int MU, bool NT, bool R8>
 __device__ __forceinline__ void hop_dir(const MultKArgs &a, const SiteCoord &c, int i,
                                         Spinor<typename Real<P>::T> &acc) {
     using R = typename Real<P>::T;
@@ -120,14 +120,14 @@ __device__ __forceinline__ void hop_dir(const MultKArgs &a, const SiteCoord &c, 
     {
         const int nf = eo_neighbour(a.g, c, MU, +1);
         const Spinor<R> psi = SpinorIO<P>::load(a.in, Vh, nf);
-        const Mat3<R> U = LinkIO<P>::template load<NT>(a.links + (size_t)(2 * MU + a.out_par) * a.link_slab, Vh, i);
+        const Mat3<R> U = LinkLoad<P, R8>::template load<NT>(a.links + (size_t)(2 * MU + a.out_par) * a.link_slab, Vh, i);
         hop_term<R, MU, true>(psi, U, acc);
     }
     {
         const int nb = eo_neighbour(a.g, c, MU, -1);
         const Spinor<R> psi = SpinorIO<P>::load(a.in, Vh, nb);
         const Mat3<R> U =
-            LinkIO<P>::template load<NT>(a.links + (size_t)(2 * MU + 1 - a.out_par) * a.link_slab, Vh, nb);
+            LinkLoad<P, R8>::template load<NT>(a.links + (size_t)(2 * MU + 1 - a.out_par) * a.link_slab, Vh, nb);
         hop_term<R, MU, false>(psi, U, acc);
     }
 }
@@ -142,7 +142,7 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 // NT: links and clover read once per launch (one system) use non-temporal
 // loads; a launch that serves several systems on one lattice reads them
 // through the cache so that the blocks of the other systems hit in L2
-template <int P, int MODE, int RED, bool NT>
+template <int P, int MODE, int RED, bool NT, bool R8>
 __global__ __launch_bounds__(kBlock) void k_mult(MultBatch B) {
     using R = typename Real<P>::T;
     int s, lb;
@@ -159,10 +159,10 @@ __global__ __launch_bounds__(kBlock) void k_mult(MultBatch B) {
         for (int k = 0; k < 12; k++) acc.c[k] = {R(0), R(0)};
         if (MODE != M_CLOV) {
             const SiteCoord c = eo_coords(a.g, i, a.out_par);
-            hop_dir<P, 0, NT>(a, c, i, acc);
-            hop_dir<P, 1, NT>(a, c, i, acc);
-            hop_dir<P, 2, NT>(a, c, i, acc);
-            hop_dir<P, 3, NT>(a, c, i, acc);
+            hop_dir<P, 0, NT, R8>(a, c, i, acc);
+            hop_dir<P, 1, NT, R8>(a, c, i, acc);
+            hop_dir<P, 2, NT, R8>(a, c, i, acc);
+            hop_dir<P, 3, NT, R8>(a, c, i, acc);
         }
         const R coef = (R)a.coef;
         if (MODE == M_HOPINV) {
@@ -210,25 +210,36 @@ __global__ __launch_bounds__(kBlock) void k_mult(MultBatch B) {
     }
 }
 
-template <int P, int MODE, int RED> void launch_one(const MultBatch &B, int blocks, hipStream_t s) {
+template <int P, int MODE, int RED, bool R8> void launch_nt(const MultBatch &B, int blocks, hipStream_t s) {
     if (B.h.interleave)
-        hipLaunchKernelGGL((k_mult<P, MODE, RED, false>), dim3(blocks), dim3(kBlock), 0, s, B);
+        hipLaunchKernelGGL((k_mult<P, MODE, RED, false, R8>), dim3(blocks), dim3(kBlock), 0, s, B);
     else
-        hipLaunchKernelGGL((k_mult<P, MODE, RED, true>), dim3(blocks), dim3(kBlock), 0, s, B);
+        hipLaunchKernelGGL((k_mult<P, MODE, RED, true, R8>), dim3(blocks), dim3(kBlock), 0, s, B);
 }
 
-template <int P> void dispatch_mode(const MultBatch &B, int mode, int red, int blocks, hipStream_t s) {
+// reconstruct-8 instances exist for the FP32 stencil only
+template <int P, int MODE, int RED> void launch_one(const MultBatch &B, int blocks, hipStream_t s, bool r8) {
+    if constexpr (P == P32) {
+        if (r8) {
+            launch_nt<P, MODE, RED, true>(B, blocks, s);
+            return;
+        }
+    }
+    launch_nt<P, MODE, RED, false>(B, blocks, s);
+}
+
+template <int P> void dispatch_mode(const MultBatch &B, int mode, int red, int blocks, hipStream_t s, bool r8) {
     switch (mode) {
-    case M_HOPINV: launch_one<P, M_HOPINV, R_NONE>(B, blocks, s); break;
+    case M_HOPINV: launch_one<P, M_HOPINV, R_NONE>(B, blocks, s, r8); break;
     case M_DHAT:
-        if (red == R_DOT) launch_one<P, M_DHAT, R_DOT>(B, blocks, s);
-        else if (red == R_DOTNORM) launch_one<P, M_DHAT, R_DOTNORM>(B, blocks, s);
-        else launch_one<P, M_DHAT, R_NONE>(B, blocks, s);
+        if (red == R_DOT) launch_one<P, M_DHAT, R_DOT>(B, blocks, s, r8);
+        else if (red == R_DOTNORM) launch_one<P, M_DHAT, R_DOTNORM>(B, blocks, s, r8);
+        else launch_one<P, M_DHAT, R_NONE>(B, blocks, s, r8);
         break;
-    case M_DFULL: launch_one<P, M_DFULL, R_NONE>(B, blocks, s); break;
-    case M_INVSRC: launch_one<P, M_INVSRC, R_NONE>(B, blocks, s); break;
-    case M_HOP: launch_one<P, M_HOP, R_NONE>(B, blocks, s); break;
-    case M_CLOV: launch_one<P, M_CLOV, R_NONE>(B, blocks, s); break;
+    case M_DFULL: launch_one<P, M_DFULL, R_NONE>(B, blocks, s, r8); break;
+    case M_INVSRC: launch_one<P, M_INVSRC, R_NONE>(B, blocks, s, r8); break;
+    case M_HOP: launch_one<P, M_HOP, R_NONE>(B, blocks, s, r8); break;
+    case M_CLOV: launch_one<P, M_CLOV, R_NONE>(B, blocks, s, r8); break;
     }
 }
 
@@ -243,9 +254,9 @@ double mult_spinor_bytes(int prec, int mode, int red, int Vh) {
     if (red != R_NONE) b += S;                                           // aux vector
     return b;
 }
-double mult_operator_bytes(int prec, int mode, int Vh) {
+double mult_operator_bytes(int prec, int mode, bool r8, int Vh) {
     double b = 0;
-    if (mode != M_CLOV) b += 8 * (double)link_site_bytes(prec) * Vh;
+    if (mode != M_CLOV) b += 8 * (double)(r8 ? 32 : link_site_bytes(prec)) * Vh;
     if (mode != M_HOP) b += (double)clover_site_bytes(prec) * Vh;
     return b;
 }
@@ -261,6 +272,7 @@ int launch_mult_batch(hipStream_t s, const MultCall *calls, int n) {
     B.h.off[0] = 0;
     bool same = true;
     double bytes = 0;
+    const bool r8 = c0.prec == P32 && c0.lat->recon == 8;
     for (int k = 0; k < n; k++) {
         const MultCall &c = calls[k];
         wc_lattice *lat = c.lat;
@@ -274,8 +286,10 @@ int launch_mult_batch(hipStream_t s, const MultCall *calls, int n) {
         a.in = c.in;
         a.center = c.center;
         a.aux = c.aux;
-        a.links = (const char *)lat->links[c.prec];
-        a.link_slab = link_slab_bytes(c.prec, lat->Vh);
+        if ((c.prec == P32 && lat->recon == 8) != r8)
+            return wc_fail(WC_EINVAL, "batched stencil calls must share the link reconstruction");
+        a.links = (const char *)(r8 ? lat->links8 : lat->links[c.prec]);
+        a.link_slab = r8 ? link8_slab_bytes(lat->Vh) : link_slab_bytes(c.prec, lat->Vh);
         const bool use_inv = (c.mode == M_HOPINV || c.mode == M_DHAT || c.mode == M_INVSRC ||
                               (c.mode == M_CLOV && c.inverse));
         const char *cb = (const char *)(use_inv ? lat->clovinv[c.prec] : lat->clov[c.prec]);
@@ -288,7 +302,7 @@ int launch_mult_batch(hipStream_t s, const MultCall *calls, int n) {
         bytes += mult_spinor_bytes(c.prec, c.mode, c.red, lat->Vh);
         bool seen = false;
         for (int j = 0; j < k; j++) seen = seen || (calls[j].lat == lat);
-        if (!seen) bytes += mult_operator_bytes(c.prec, c.mode, lat->Vh);
+        if (!seen) bytes += mult_operator_bytes(c.prec, c.mode, r8, lat->Vh);
         if (c.mode != M_CLOV) lat->dslash_count++;
     }
     B.h.interleave = (same && n > 1) ? 1 : 0;
@@ -299,9 +313,9 @@ int launch_mult_batch(hipStream_t s, const MultCall *calls, int n) {
     if (c0.mode == M_DHAT) slot = KS_MULT_DHAT_P64 + c0.prec;
     TimedLaunch t;
     if (tl->timing) timing_begin(tl, slot, bytes, t);
-    if (c0.prec == P64) dispatch_mode<P64>(B, c0.mode, c0.red, blocks, s);
-    else if (c0.prec == P32) dispatch_mode<P32>(B, c0.mode, c0.red, blocks, s);
-    else dispatch_mode<P16>(B, c0.mode, c0.red, blocks, s);
+    if (c0.prec == P64) dispatch_mode<P64>(B, c0.mode, c0.red, blocks, s, false);
+    else if (c0.prec == P32) dispatch_mode<P32>(B, c0.mode, c0.red, blocks, s, r8);
+    else dispatch_mode<P16>(B, c0.mode, c0.red, blocks, s, r8);
     WC_HIP(hipGetLastError());
     if (tl->timing) timing_end(tl, t);
     if (c0.red != R_NONE && c0.mode == M_DHAT) {

@@ -35,6 +35,7 @@ enum DoneCode { DONE_NO = 0, DONE_FULL = 1, DONE_HALF = 2, DONE_BREAK = 4 };
 
 enum { NUM_LEVELS = 2 };  // 0 = inner loop, 1 = outer / FP64 loop
 constexpr int kMaxSys = 16;  // systems per batched launch
+constexpr float kRecon8MinN = 1e-6f;  // smallest |U01|^2 + |U02|^2 reconstruct-8 accepts
 
 // kinds of timed kernel launches
 enum KernelSlot {
@@ -123,6 +124,11 @@ struct wc_lattice {
 
     // gauge links per precision: 8 slabs ([mu][parity]) of link_slab_bytes
     void *links[3] = {nullptr, nullptr, nullptr};
+    // reconstruct-8 FP32 copy (8 slabs of link8_slab_bytes), built on request;
+    // recon = 8 makes the FP32 stencils read it
+    void *links8 = nullptr;
+    int recon = 12;
+    unsigned *recon_min = nullptr;  // device word: smallest N as FP32 bits
     // clover F and F^-1 per precision: 2 slabs ([parity]) of clover_slab_bytes
     void *clov[3] = {nullptr, nullptr, nullptr};
     void *clovinv[3] = {nullptr, nullptr, nullptr};
@@ -276,6 +282,7 @@ int launch_vec_batch(hipStream_t s, wc_lattice *timing_lat, int op, int prec, co
 int launch_pack_spinor(wc_lattice *lat, int prec, void *eo_out, const void *canon_in);
 int launch_unpack_spinor(wc_lattice *lat, int prec, void *canon_out, const void *eo_in);
 int launch_load_links(wc_lattice *lat, const void *U);
+int launch_links_recon8(wc_lattice *lat, unsigned *min_bits);
 int launch_build_clover(wc_lattice *lat, double kappa, double csw);
 int launch_link_grad(wc_lattice *lat, const void *lam_eo, const void *x_eo, void *G, void *Nbuf, double kappa,
                      double csw, bool clover);

@@ -35,6 +35,32 @@ __global__ __launch_bounds__(kBlock) void k_load_links(Geom g, const double2 *U,
     *tp<uint2, 24>(b16, i, 16) = make_uint2(f2h((float)m[4].x, (float)m[4].y), f2h((float)m[7].x, (float)m[7].y));
 }
 
+// reconstruct-8 copy of the FP64 links and the smallest N = |U01|^2 + |U02|^2
+// (as FP32 bits, which order like the non-negative values they encode)
+__global__ __launch_bounds__(kBlock) void k_links_recon8(Geom g, const char *l64, char *l8, unsigned *min_bits) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const int slab = blockIdx.y;  // 2 mu + parity
+    float n32 = 3.0e38f;
+    if (i < g.Vh) {
+        const char *src = l64 + (size_t)slab * link_slab_bytes(P64, g.Vh);
+        double2 m[9];
+#pragma unroll
+        for (int k = 0; k < 9; k++) m[k] = *tp<double2, 144>(src, i, 16 * k);
+        const double2 a2 = m[1], a3 = m[2], b1 = m[3], c1 = m[6];
+        const bool swap = (b1.x * b1.x + b1.y * b1.y) > (c1.x * c1.x + c1.y * c1.y);
+        const double2 y = swap ? c1 : b1, z = swap ? b1 : c1;
+        const double ta = atan2(m[0].y, m[0].x) / M_PI, tz = atan2(z.y, z.x) / M_PI;
+        char *d = l8 + (size_t)slab * link8_slab_bytes(g.Vh);
+        const float4 p0 = make_float4((float)a2.x, (float)a2.y, (float)a3.x, (float)a3.y);
+        *tp<float4, 32>(d, i, 0) = p0;
+        *tp<float4, 32>(d, i, 16) = make_float4((float)y.x, (float)y.y, (float)ta, (float)(swap ? tz + 3.0 : tz));
+        n32 = p0.x * p0.x + p0.y * p0.y + p0.z * p0.z + p0.w * p0.w;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) n32 = fminf(n32, __shfl_xor(n32, off));
+    if ((threadIdx.x & 63) == 0) atomicMin(min_bits, __float_as_uint(n32));
+}
+
 template <int P>
 __global__ __launch_bounds__(kBlock) void k_pack(Geom g, char *eo, const double2 *canon, size_t slab_bytes) {
     using R = typename Real<P>::T;
@@ -73,6 +99,14 @@ int launch_load_links(wc_lattice *lat, const void *U) {
     dim3 grid((lat->Vh + kBlock - 1) / kBlock, 8);
     hipLaunchKernelGGL(k_load_links, grid, dim3(kBlock), 0, lat->stream, lat->g, (const double2 *)U,
                        (double2 *)lat->links[P64], (float4 *)lat->links[P32], (char *)lat->links[P16]);
+    WC_HIP(hipGetLastError());
+    return WC_OK;
+}
+
+int launch_links_recon8(wc_lattice *lat, unsigned *min_bits) {
+    dim3 grid((lat->Vh + kBlock - 1) / kBlock, 8);
+    hipLaunchKernelGGL(k_links_recon8, grid, dim3(kBlock), 0, lat->stream, lat->g, (const char *)lat->links[P64],
+                       (char *)lat->links8, min_bits);
     WC_HIP(hipGetLastError());
     return WC_OK;
 }

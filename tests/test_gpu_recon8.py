@@ -1,0 +1,146 @@
+"""GPU parity of the reconstruct-8 link storage of the FP32 stencil.
+
+Each link keeps U01, U02, the smaller of U10 and U20, and two phases; the
+other entries are rebuilt from unitarity and det U = 1.  The rebuilt FP32
+links differ from the exact ones by a few FP32 rounding steps (below 1e-6 per
+entry over the random fields used here), so the operator keeps the FP32
+tolerance of the recon-12 tests (1e-5 relative).  FP16 stencils ignore the
+setting and keep two columns (checked against the oracle at 2e-3).  Solves
+stay FP64-refined and match the oracle to 1e-10.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # collected on CPU but never run there
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1709_08785_amd as wc  # noqa: E402
+
+TOL = {wc.FP32: 1e-5, wc.FP16: 2e-3}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def make(dims, seed, kappa, csw=1.0, recon=8):
+    U = synth.random_links(dims, 0.3, seed)
+    lat = wc.Lattice(dims)
+    lat.load_links(dev(U))
+    lat.build_clover(kappa, csw)
+    lat.set_link_recon(recon)
+    return lat, U
+
+
+@pytest.mark.parametrize("prec", [wc.FP32, wc.FP16])
+@pytest.mark.parametrize("dims", [(4, 6, 8, 10), (2, 2, 2, 2), (6, 4, 2, 8)])
+def test_recon8_mult_and_dhat(dims, prec):
+    say("recon8 mult/dhat", dims, prec)
+    kappa = 0.13
+    lat, U = make(dims, 1100, kappa)
+    assert lat.link_recon == 8
+    F = oracle.clover_field(U, dims, kappa, 1.0)
+    Finv = oracle.site_invert(F)
+    psi = synth.gaussian_source(dims, 12)
+    eo_in = lat.pack(dev(psi), prec)
+    for out_par in (0, 1):
+        eo_out = lat.new_eo(prec, 2)
+        lat.apply_mult(lat.parity_view(eo_out, out_par, prec), lat.parity_view(eo_in, 1 - out_par, prec), out_par,
+                       prec)
+        assert rel(host(lat.unpack(eo_out, prec)), oracle.htilde(U, Finv, psi, out_par)) < TOL[prec]
+    pe = oracle.restrict(psi, 0)
+    eo_in = lat.pack(dev(pe), prec)
+    eo_out = lat.new_eo(prec, 2)
+    lat.apply_Dee_oo(lat.parity_view(eo_out, 0, prec), lat.parity_view(eo_in, 0, prec), prec)
+    assert rel(host(lat.unpack(eo_out, prec)), oracle.dhat_ee(U, Finv, kappa, pe)) < TOL[prec]
+
+
+def test_recon8_matches_recon12_closely():
+    # same FP32 stencil, only the link storage differs: the gap stays near FP32 rounding
+    dims = (8, 8, 8, 8)
+    lat, U = make(dims, 1101, 0.13, recon=12)
+    pe = oracle.restrict(synth.gaussian_source(dims, 13), 0)
+    eo_in = lat.pack(dev(pe), wc.FP32)
+    outs = []
+    for recon in (12, 8):
+        lat.set_link_recon(recon)
+        eo_out = lat.new_eo(wc.FP32, 2)
+        lat.apply_Dee_oo(lat.parity_view(eo_out, 0, wc.FP32), lat.parity_view(eo_in, 0, wc.FP32), wc.FP32)
+        outs.append(host(lat.unpack(eo_out, wc.FP32)))
+    assert rel(outs[1], outs[0]) < 2e-6
+
+
+@pytest.mark.parametrize("inner", [wc.FP32, wc.FP16, wc.FP64])
+def test_recon8_solve_matches_oracle(inner):
+    dims = (8, 8, 8, 8)
+    kappa = 0.12
+    say("recon8 solve", inner)
+    lat, U = make(dims, 1001, kappa)
+    b = synth.gaussian_source(dims, 2001)
+    F = oracle.clover_field(U, dims, kappa, 1.0)
+    x_ref, _, _ = oracle.solve(U, F, kappa, b, tol=1e-13)
+    x, info = lat.solve(dev(b), kappa, 1.0, 1e-12, inner_prec=inner)
+    say(info)
+    r, bn = oracle.residual(U, kappa, 1.0, b, host(x))
+    assert r / bn < 1e-12
+    assert rel(host(x), x_ref) < 1e-10
+
+
+def test_recon8_refuses_unit_links_and_reload_falls_back():
+    dims = (4, 4, 4, 4)
+    lat = wc.Lattice(dims)
+    with pytest.raises(wc.WCError) as e:
+        lat.set_link_recon(8)  # no links yet
+    assert e.value.code == -4
+    lat.load_links(dev(synth.unit_links(dims)))
+    with pytest.raises(wc.WCError) as e:
+        lat.set_link_recon(8)
+    assert e.value.code == -1
+    assert lat.link_recon == 12
+    with pytest.raises(wc.WCError):
+        lat.set_link_recon(10)
+    # accepted on random links; a reload with unrepresentable links falls back to 12
+    U = synth.random_links(dims, 0.3, 1102)
+    lat.load_links(dev(U))
+    lat.set_link_recon(8)
+    assert lat.link_recon == 8
+    with pytest.raises(wc.WCError):
+        lat.load_links(dev(synth.unit_links(dims)))
+    assert lat.link_recon == 12
+    # the unit links themselves were loaded and work with recon 12
+    lat.build_clover(0.12, 1.0)
+    b = synth.gaussian_source(dims, 14)
+    x, info = lat.solve(dev(b), 0.12, 1.0, 1e-10)
+    r, bn = oracle.residual(synth.unit_links(dims), 0.12, 1.0, b, host(x))
+    assert r / bn < 1e-10
+
+
+def test_recon8_batch_needs_one_setting():
+    dims = (4, 4, 4, 8)
+    a, _ = make(dims, 1103, 0.12, recon=8)
+    c, _ = make(dims, 1104, 0.12, recon=12)
+    b = dev(synth.gaussian_source(dims, 15))
+    with pytest.raises(wc.WCError):
+        wc.solve_multi([a, c], [b, b], [0.12, 0.12], [1.0, 1.0], 1e-10)
