@@ -247,11 +247,11 @@ template <int P> void dispatch_mode(const MultBatch &B, int mode, int red, int b
 // stored precision, each link once, one clover pair).  The spinor part is per
 // call; the link and clover part is per lattice, since calls of one batch on
 // the same lattice read the same operator.
-double mult_spinor_bytes(int prec, int mode, int red, int Vh) {
+double mult_spinor_bytes(int prec, int mode, int red, bool aux_is_centre, int Vh) {
     const double S = (double)spinor_site_bytes(prec) * Vh;
     double b = 2 * S;                                                    // input (once) + output
     if (mode == M_DHAT || mode == M_DFULL || mode == M_INVSRC) b += S;  // centre vector
-    if (red != R_NONE) b += S;                                           // aux vector
+    if (red != R_NONE && !aux_is_centre) b += S;                         // aux vector, unless the centre
     return b;
 }
 double mult_operator_bytes(int prec, int mode, bool r8, int Vh) {
@@ -299,7 +299,7 @@ int launch_mult_batch(hipStream_t s, const MultCall *calls, int n) {
         a.done = c.done;
         a.nblk = lat->nblocks;
         B.h.off[k + 1] = B.h.off[k] + lat->nblocks;
-        bytes += mult_spinor_bytes(c.prec, c.mode, c.red, lat->Vh);
+        bytes += mult_spinor_bytes(c.prec, c.mode, c.red, c.aux == c.center, lat->Vh);
         bool seen = false;
         for (int j = 0; j < k; j++) seen = seen || (calls[j].lat == lat);
         if (!seen) bytes += mult_operator_bytes(c.prec, c.mode, r8, lat->Vh);

@@ -77,8 +77,34 @@ def test_batch_matches_single_solves(inner):
         x1, info1 = lat.solve(bs[k], kappa, csw, 1e-10, inner_prec=inner)
         d = float(torch.linalg.norm(x1 - xs[k]) / torch.linalg.norm(x1))
         assert d < 1e-9, (k, d)
-        assert abs(info1["inner_iters_total"] - infos[k]["inner_iters_total"]) <= 2
+        # the batched stencil rounds differently (another kernel, other FMA
+        # contractions); at FP16 storage that moves the iteration count by a few
+        assert abs(info1["inner_iters_total"] - infos[k]["inner_iters_total"]) <= max(2, 0.1 * info1["inner_iters_total"])
         assert infos[k]["true_rel_residual"] < 1e-10
+
+
+@pytest.mark.parametrize("inner,recon", [(wc.FP32, 12), (wc.FP32, 8), (wc.FP16, 12)])
+def test_batch_five_sources_two_groups(inner, recon):
+    # five systems on one lattice: the multi-system stencil takes them four at a
+    # time, so the second group has one live slot; the sources differ in size
+    # so the systems converge at different iterations and drop out one by one
+    dims = (8, 8, 8, 16)
+    kappa, csw = 0.13, 1.0
+    say("batch of 5", inner, recon)
+    U = synth.random_links(dims, 0.3, 1015)
+    lat = wc.Lattice(dims)
+    lat.load_links(dev(U))
+    lat.build_clover(kappa, csw)
+    lat.set_link_recon(recon)
+    bs = [dev(synth.gaussian_source(dims, 2200 + k) * (10.0 ** (k - 2))) for k in range(5)]
+    bs[3] = dev(synth.point_source(dims, 1, 2))
+    xs, infos = lat.solve_batch(bs, kappa, csw, 1e-10, inner_prec=inner)
+    for k in range(5):
+        r, bn = oracle.residual(U, kappa, csw, host(bs[k]), host(xs[k]))
+        assert r / bn < 1e-10 and infos[k]["true_rel_residual"] < 1e-10, (k, infos[k])
+        x1, info1 = lat.solve(bs[k], kappa, csw, 1e-10, inner_prec=inner)
+        d = float(torch.linalg.norm(x1 - xs[k]) / torch.linalg.norm(x1))
+        assert d < 1e-9, (k, d)
 
 
 def test_multi_uneven_small_vs_oracle():
