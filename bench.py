@@ -398,6 +398,7 @@ def main():
     fp64 = None
     fp16 = None
     recon8 = None
+    dc = None
     if not args.no_fp64_arm:
         x64, info64 = lat.solve(bd, args.kappa, args.csw, args.tol, inner_prec=wc.FP64)
         torch.cuda.synchronize()
@@ -422,26 +423,27 @@ def main():
                 "solution_rel_diff_vs_fp64": float(torch.linalg.norm(x16 - x64) / torch.linalg.norm(x64)),
                 "speedup_vs_fp64": round(t64 / t16, 3)}
         del x16
-        # the FP32-inner form with reconstruct-8 links in the inner stencils
+        # further forms of the same solve: reconstruct-8 links in the FP32 inner
+        # stencil, and the defect-correction outer iteration
         if args.recon == 12:
-            recon8 = {}
-            lat.set_link_recon(8)
-            for name, prec in [("fp32_inner", wc.FP32)]:
-                lat.solve(bd, args.kappa, args.csw, args.tol, inner_prec=prec)
+            def arm(prec, recon, outer):
+                lat.set_link_recon(recon)
+                lat.solve(bd, args.kappa, args.csw, args.tol, inner_prec=prec, outer=outer)
                 torch.cuda.synchronize()
                 t1 = time.perf_counter()
-                x8, info8 = lat.solve(bd, args.kappa, args.csw, args.tol, inner_prec=prec)
+                xa, ia = lat.solve(bd, args.kappa, args.csw, args.tol, inner_prec=prec, outer=outer)
                 torch.cuda.synchronize()
-                t8 = time.perf_counter() - t1
-                log("recon8 %s arm: %s" % (name, json.dumps(info8)))
-                recon8[name] = {"seconds": round(t8, 4), "inner_iters": info8["inner_iters_total"],
-                                "outer_iters": info8["outer_iters"],
-                                "true_rel_residual": info8["true_rel_residual"],
-                                "solution_rel_diff_vs_fp64": float(torch.linalg.norm(x8 - x64) /
-                                                                   torch.linalg.norm(x64)),
-                                "speedup_vs_fp64": round(t64 / t8, 3)}
-                del x8
-            lat.set_link_recon(args.recon)
+                ta = time.perf_counter() - t1
+                lat.set_link_recon(args.recon)
+                log("arm %s recon %d %s: %s" % (prec, recon, outer, json.dumps(ia)))
+                return {"seconds": round(ta, 4), "inner_iters": ia["inner_iters_total"],
+                        "inner_calls": ia["inner_calls"], "outer_iters": ia["outer_iters"],
+                        "true_rel_residual": ia["true_rel_residual"],
+                        "solution_rel_diff_vs_fp64": float(torch.linalg.norm(xa - x64) / torch.linalg.norm(x64)),
+                        "speedup_vs_fp64": round(t64 / ta, 3)}
+            recon8 = {"fp32_inner": arm(wc.FP32, 8, "bicgstab")}
+            dc = {"fp32_inner": arm(wc.FP32, 12, "dc"), "fp32_inner_recon8": arm(wc.FP32, 8, "dc"),
+                  "fp16_inner": arm(wc.FP16, 12, "dc")}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -473,11 +475,15 @@ def main():
         "cpu_baseline": cpu,
         "time_to_solution_s": {"mixed": round(ms_per_step / 1e3, 4), "fp64": fp64["seconds"] if fp64 else None,
                                "mixed_fp16_inner": fp16["seconds"] if fp16 else None,
-                               "mixed_recon8": recon8["fp32_inner"]["seconds"] if recon8 else None},
+                               "mixed_recon8": recon8["fp32_inner"]["seconds"] if recon8 else None,
+                               "dc_fp32_inner": dc["fp32_inner"]["seconds"] if dc else None,
+                               "dc_fp32_inner_recon8": dc["fp32_inner_recon8"]["seconds"] if dc else None,
+                               "dc_fp16_inner": dc["fp16_inner"]["seconds"] if dc else None},
         "speedup_mixed_vs_fp64": round(fp64["seconds"] / (ms_per_step / 1e3), 3) if fp64 else None,
         "fp64_arm": fp64,
         "fp16_inner_arm": fp16,
         "recon8_arms": recon8,
+        "defect_correction_arms": dc,
         "solve": {"outer_iters": last["outer_iters"], "inner_iters": last["inner_iters_total"],
                   "inner_calls": last["inner_calls"], "restarts": last["restarts"],
                   "true_rel_residual": last["true_rel_residual"], "dslash_count": last["dslash_count"]},

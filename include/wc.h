@@ -86,7 +86,12 @@ typedef struct {
                              gamma5-Hermitian: g5 D g5 = D^dagger); default 0 */
     int use_graph;        /* != 0 (default): record each chunk of check_every inner iterations
                              once as a HIP graph and replay it (not while kernel timing is on) */
+    int outer;            /* outer iteration around the inner solver: WC_OUTER_BICGSTAB (default,
+                             the flexible BiCGStab of Algorithm 1) or WC_OUTER_DC (defect
+                             correction: x_e += M r_e, r_e recomputed in FP64 each step) */
 } wc_solve_params;
+
+enum wc_outer { WC_OUTER_BICGSTAB = 0, WC_OUTER_DC = 1 };
 
 /* What a solve did.  Iteration counts follow Algorithms 1 and 2. */
 typedef struct {

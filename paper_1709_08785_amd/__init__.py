@@ -39,7 +39,10 @@ class WCError(RuntimeError):
 class SolveParams(ctypes.Structure):
     _fields_ = [("inner_prec", ctypes.c_int), ("inner_tol", ctypes.c_double), ("inner_maxit", ctypes.c_int),
                 ("outer_maxit", ctypes.c_int), ("fixed_work", ctypes.c_int), ("check_every", ctypes.c_int),
-                ("adjoint", ctypes.c_int), ("use_graph", ctypes.c_int)]
+                ("adjoint", ctypes.c_int), ("use_graph", ctypes.c_int), ("outer", ctypes.c_int)]
+
+
+OUTER = {"bicgstab": 0, "dc": 1}
 
 
 class SolveInfo(ctypes.Structure):
@@ -234,9 +237,14 @@ class Lattice:
     def default_params(**kw) -> SolveParams:
         p = SolveParams()
         load_library().wc_solve_params_default(ctypes.byref(p))
+        names = {f for f, _ in SolveParams._fields_}
         for k, v in kw.items():
+            if k not in names:
+                raise TypeError("unknown solver parameter %r" % k)
             if k == "inner_prec":
                 v = _prec(v)
+            if k == "outer" and isinstance(v, str):
+                v = OUTER[v]
             setattr(p, k, v)
         return p
 

@@ -292,6 +292,7 @@ extern "C" void wc_solve_params_default(wc_solve_params *p) {
     p->check_every = 8;
     p->adjoint = 0;
     p->use_graph = 1;
+    p->outer = WC_OUTER_BICGSTAB;
 }
 
 static int check_params(const wc_solve_params &P, double tol) {
@@ -300,6 +301,7 @@ static int check_params(const wc_solve_params &P, double tol) {
     if (P.inner_maxit < 1 || P.outer_maxit < 1 || P.check_every < 1 || P.fixed_work < 0 || P.inner_tol < 0.0 ||
         P.inner_tol >= 1.0)
         return wc_fail(WC_EINVAL, "bad solver parameters");
+    if (P.outer != WC_OUTER_BICGSTAB && P.outer != WC_OUTER_DC) return wc_fail(WC_EINVAL, "bad outer method");
     return WC_OK;
 }
 

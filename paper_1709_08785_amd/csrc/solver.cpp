@@ -380,6 +380,61 @@ int outer_flexible(Run &R, std::vector<int> act, bool x_is_zero) {
     return WC_OK;
 }
 
+// Defect correction from the current x_e of every system in act: each step
+// solves D-hat v = r_e with the low-precision inner solver (Algorithm 2),
+// adds v to x_e and recomputes r_e = b-hat - D-hat x_e in FP64.  Each inner
+// solve aims at the inner tolerance, or at half the reduction still needed
+// when that is looser, so the last step does not over-solve.  A step that
+// does not lower ||r_e|| ends the system's iteration (reported as no
+// convergence unless the tolerance is met).
+int outer_dc(Run &R, std::vector<int> act, bool x_is_zero) {
+    if (x_is_zero) {
+        if (int rc = vec_over(R, act, V_COPY, P64, [&](int k) { return vc(R, k, 1, W(R, k, W_R), W(R, k, W_BHAT)); }))
+            return rc;
+        if (int rc = vec_over(R, act, V_NORM2, P64, [&](int k) {
+                VecCall v = vc(R, k, 1, W(R, k, W_R));
+                v.result = S_(R, k).st->sc(1) + S_RR;
+                return v;
+            }))
+            return rc;
+    } else {
+        if (int rc = eo_residual(R, act)) return rc;
+    }
+    if (int rc = sync(R)) return rc;
+    std::vector<double> last(R.src.size(), 0.0);
+    for (int it = 0; !act.empty(); it++) {
+        std::vector<int> run;
+        for (int k : act) {
+            const double rn = std::sqrt(S_(R, k).st->hs(1, S_RR));
+            S_(R, k).info.eo_rel_residual = rn / R.src[k];
+            if (!std::isfinite(rn)) {
+                R.dead[k] = WC_EBREAKDOWN;
+            } else if (rn / R.src[k] < R.tol_eo[k]) {
+                R.conv[k] = 1;
+            } else if (it < R.omaxit && (it == 0 || rn < last[k])) {
+                const double t = std::max(R.itol, 0.5 * R.tol_eo[k] * R.src[k] / rn);
+                R.tol2_in[k] = t * t;
+                last[k] = rn;
+                S_(R, k).info.outer_iters++;
+                run.push_back(k);
+            }
+        }
+        act.swap(run);
+        if (act.empty()) break;
+        if (int rc = inner_solve(R, act, W_R, W_V)) return rc;
+        if (int rc = vec_over(R, act, V_AXPY, P64, [&](int k) {
+                VecCall v = vc(R, k, 1, W(R, k, W_X), W(R, k, W_V));
+                v.coef = 1.0;
+                return v;
+            }))
+            return rc;
+        if (int rc = eo_residual(R, act)) return rc;
+        if (int rc = sync(R)) return rc;
+    }
+    for (auto &t : R.tol2_in) t = R.itol * R.itol;
+    return WC_OK;
+}
+
 // plain FP64 BiCGStab on D-hat_ee (the inner machinery in FP64) for D-hat v = r_e,
 // x_e += v, for every system in act
 int fp64_pass(Run &R, std::vector<int> act, bool x_is_zero) {
@@ -532,7 +587,9 @@ int solve_systems(std::vector<SolveSys> &sys, Arena &arena, double tol, const wc
     for (int pass = 0; pass < max_passes && !act.empty(); pass++) {
         for (int k : act) R.conv[k] = 0;
         const bool xz = (!x0_is_guess) && pass == 0;
-        int rc = (R.iprec == WC_FP64) ? fp64_pass(R, act, xz) : outer_flexible(R, act, xz);
+        int rc = (R.iprec == WC_FP64)       ? fp64_pass(R, act, xz)
+                 : (P.outer == WC_OUTER_DC) ? outer_dc(R, act, xz)
+                                            : outer_flexible(R, act, xz);
         if (rc) return rc;
         if (int rc2 = reconstruct_and_check(R, act, res2)) return rc2;
         std::vector<int> again;

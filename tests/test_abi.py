@@ -67,3 +67,33 @@ def test_default_params(lib):
     lib.wc_solve_params_default(ctypes.byref(p))
     assert p.inner_prec == wc.FP32 and p.inner_maxit > 0 and p.outer_maxit > 0 and p.check_every > 0
     assert p.fixed_work == 0
+
+
+def test_params_and_info_layout_match_header(tmp_path):
+    # the binding's ctypes mirrors must agree with the C structs field by field
+    import subprocess
+
+    import paper_1709_08785_amd as wc
+    here = os.path.dirname(os.path.abspath(__file__))
+    inc = os.path.join(os.path.dirname(here), "include")
+    fields = {"wc_solve_params": wc.SolveParams, "wc_solve_info": wc.SolveInfo}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "wc.h"', "int main(void) {"]
+    for cname, cls in fields.items():
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in cls._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {" ".join(l.split()[:-1]): int(l.split()[-1]) for l in out if l.strip()}
+    for cname, cls in fields.items():
+        assert got[cname + " size"] == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got["%s %s" % (cname, f)] == getattr(cls, f).offset, (cname, f)
+    p = wc.Lattice.default_params(outer="dc")
+    assert p.outer == 1
+    with pytest.raises(TypeError):
+        wc.Lattice.default_params(not_a_parameter=1)
