@@ -246,8 +246,10 @@ def batch_mode(args):
 def precisions_mode(args):
     """The three precision forms on the 48^3x96 lattice (kappa 0.1355, c_SW 1.0,
     Z2 source), all refined in FP64 to true relative residual tol: FP16-storage
-    inner, FP32 inner, and the all-FP64 BiCGStab.  Each solution's residual is
-    also computed by the FP64 oracle on the host."""
+    inner, FP32 inner, and the all-FP64 BiCGStab; then FP32 inner with
+    reconstruct-8 links, and the defect-correction outer with FP16 and with
+    reconstruct-8 FP32 inner solves.  Each solution's residual is also computed
+    by the FP64 oracle on the host."""
     import numpy as np
     import torch
 
@@ -268,11 +270,16 @@ def precisions_mode(args):
     U = Ud.cpu().numpy()
     del Ud
     bd = torch.from_numpy(b).to(dev)
-    forms = [("fp16", dict(inner_prec=wc.FP16)), ("fp32", dict(inner_prec=wc.FP32)),
-             ("fp64", dict(inner_prec=wc.FP64))]
+    # the three forms of the paper's method (flexible BiCGStab outer), then the
+    # same with reconstruct-8 FP32 links and with the defect-correction outer
+    forms = [("fp16", 12, dict(inner_prec=wc.FP16)), ("fp32", 12, dict(inner_prec=wc.FP32)),
+             ("fp64", 12, dict(inner_prec=wc.FP64)), ("fp32_recon8", 8, dict(inner_prec=wc.FP32)),
+             ("fp16_dc", 12, dict(inner_prec=wc.FP16, outer="dc")),
+             ("fp32_recon8_dc", 8, dict(inner_prec=wc.FP32, outer="dc"))]
     res = {}
     xs = {}
-    for name, kw in forms:
+    for name, recon, kw in forms:
+        lat.set_link_recon(recon)
         lat.solve(bd, kappa, csw, args.tol, **kw)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -287,7 +294,8 @@ def precisions_mode(args):
                      "true_rel_residual_gpu": info["true_rel_residual"], "true_rel_residual_oracle": r / bn}
         log(name, json.dumps(res[name]))
         del x
-    for name in ("fp16", "fp32"):
+    lat.set_link_recon(12)
+    for name in [f[0] for f in forms if f[0] != "fp64"]:
         res[name]["solution_rel_diff_vs_fp64"] = float(np.linalg.norm(xs[name] - xs["fp64"]) /
                                                        np.linalg.norm(xs["fp64"]))
         res[name]["speedup_vs_fp64"] = round(res["fp64"]["seconds"] / res[name]["seconds"], 3)
