@@ -366,7 +366,9 @@ template <> struct LinkIO<P16> {
 //   With N = |U01|^2 + |U02|^2 = |U10|^2 + |U20|^2 (unit first row and first
 //   column), y is whichever of U10, U20 has the smaller modulus and the other,
 //   z, is rebuilt from |z|^2 = N - |y|^2 >= N/2, a subtraction that cannot
-//   cancel; t_z = arg(z)/pi, plus 3 when y holds U20.  |U00|^2 = 1 - N.
+//   cancel; t_z = arg(z)/pi taken in [0, 2), its sign bit set when y holds U20
+//   (a sign bit, unlike an offset, cannot be lost to rounding and costs no
+//   precision).  |U00|^2 = 1 - N.
 //   Writing a1 = U00, b1 = U10, c1 = U20, orthogonality of the rows to the
 //   first row and det U = 1 fix the remaining 2x2 block:
 //     U11 = -(b1 a1* a2 + c1* a3*) / N      U12 = (c1* a2* - b1 a1* a3) / N
@@ -380,8 +382,8 @@ WC_HD size_t link8_slab_bytes(int Vh) { return (size_t)pad_sites(Vh) * 32; }
 
 __device__ __forceinline__ Mat3<float> recon8(cx<float> a2, cx<float> a3, cx<float> y, float ta, float tz) {
     const float N = norm2(a2) + norm2(a3);
-    const bool swap = tz > 2.0f;
-    const float t = swap ? tz - 3.0f : tz;
+    const bool swap = signbit(tz);
+    const float t = fabsf(tz);
     float sa, ca, sz, cz;
     sincospif(ta, &sa, &ca);
     sincospif(t, &sz, &cz);

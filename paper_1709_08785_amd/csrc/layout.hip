@@ -49,11 +49,14 @@ __global__ __launch_bounds__(kBlock) void k_links_recon8(Geom g, const char *l64
         const double2 a2 = m[1], a3 = m[2], b1 = m[3], c1 = m[6];
         const bool swap = (b1.x * b1.x + b1.y * b1.y) > (c1.x * c1.x + c1.y * c1.y);
         const double2 y = swap ? c1 : b1, z = swap ? b1 : c1;
-        const double ta = atan2(m[0].y, m[0].x) / M_PI, tz = atan2(z.y, z.x) / M_PI;
+        const double ta = atan2(m[0].y, m[0].x) / M_PI;
+        double tz = atan2(z.y, z.x) / M_PI;
+        if (tz < 0.0) tz += 2.0;  // [0, 2]: the sign bit is free for the flag
         char *d = l8 + (size_t)slab * link8_slab_bytes(g.Vh);
         const float4 p0 = make_float4((float)a2.x, (float)a2.y, (float)a3.x, (float)a3.y);
         *tp<float4, 32>(d, i, 0) = p0;
-        *tp<float4, 32>(d, i, 16) = make_float4((float)y.x, (float)y.y, (float)ta, (float)(swap ? tz + 3.0 : tz));
+        const float tzf = (float)tz;
+        *tp<float4, 32>(d, i, 16) = make_float4((float)y.x, (float)y.y, (float)ta, swap ? -tzf : tzf);
         n32 = p0.x * p0.x + p0.y * p0.y + p0.z * p0.z + p0.w * p0.w;
     }
 #pragma unroll

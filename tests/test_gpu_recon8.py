@@ -77,6 +77,40 @@ def test_recon8_mult_and_dhat(dims, prec):
     assert rel(host(lat.unpack(eo_out, prec)), oracle.dhat_ee(U, Finv, kappa, pe)) < TOL[prec]
 
 
+def _phase_rotated_links(dims, seed):
+    """Random links whose larger of U10, U20 sits just below the negative real
+    axis (argument -pi + 1e-9): the phase that reconstruct-8 stores for it is
+    then at the end of its range, where a flag kept as an offset of the phase
+    would be lost to FP32 rounding.  Rows are rotated by diagonal SU(3)
+    phases, so the links stay special unitary."""
+    U = synth.random_links(dims, 0.3, seed)
+    V = U.reshape(-1, 3, 3)
+    big = np.where(np.abs(V[:, 1, 0]) > np.abs(V[:, 2, 0]), 1, 2)
+    z = V[np.arange(len(V)), big, 0]
+    ph = np.exp(1j * (np.pi + 1e-9 - np.angle(z)))
+    D = np.ones((len(V), 3), dtype=np.complex128)
+    D[np.arange(len(V)), big] = ph
+    D[np.arange(len(V)), 3 - big] = np.conj(ph)
+    return (D[:, :, None] * V).reshape(U.shape)
+
+
+def test_recon8_phase_at_range_end():
+    dims, kappa = (4, 6, 8, 10), 0.13
+    U = _phase_rotated_links(dims, 1105)
+    lat = wc.Lattice(dims)
+    lat.load_links(dev(U))
+    lat.build_clover(kappa, 1.0)
+    lat.set_link_recon(8)
+    Finv = oracle.site_invert(oracle.clover_field(U, dims, kappa, 1.0))
+    psi = synth.gaussian_source(dims, 16)
+    eo_in = lat.pack(dev(psi), wc.FP32)
+    for out_par in (0, 1):
+        eo_out = lat.new_eo(wc.FP32, 2)
+        lat.apply_mult(lat.parity_view(eo_out, out_par, wc.FP32), lat.parity_view(eo_in, 1 - out_par, wc.FP32),
+                       out_par, wc.FP32)
+        assert rel(host(lat.unpack(eo_out, wc.FP32)), oracle.htilde(U, Finv, psi, out_par)) < 1e-5
+
+
 def test_recon8_matches_recon12_closely():
     # same FP32 stencil, only the link storage differs: the gap stays near FP32 rounding
     dims = (8, 8, 8, 8)
