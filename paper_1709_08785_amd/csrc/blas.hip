@@ -276,6 +276,7 @@ template <int N> __global__ __launch_bounds__(kBlock) void k_finalize(FinBatch B
         sc[S_TOL2] = f.tol2;
         fl[F_DONE] = DONE_NO;
         fl[F_ITERS] = 0;
+        fl[F_STOPPH] = 0;
         break;
     case FIN_INNER_A: {
         const int it = fl[F_ITERS];
@@ -283,6 +284,7 @@ template <int N> __global__ __launch_bounds__(kBlock) void k_finalize(FinBatch B
         sc[S_SS] = a[0];
         if (!finite_c(al) || !isfinite(a[0])) fl[F_DONE] = DONE_BREAK;
         else if (a[0] < sc[S_TOL2]) fl[F_DONE] = DONE_HALF;
+        if (fl[F_DONE] != DONE_NO) fl[F_STOPPH] = 1;
         break;
     }
     case FIN_INNER_B: {
@@ -299,6 +301,7 @@ template <int N> __global__ __launch_bounds__(kBlock) void k_finalize(FinBatch B
             fl[F_DONE] = (a[0] < tol2) ? DONE_FULL : DONE_BREAK;
         else if (a[0] < tol2)
             fl[F_DONE] = DONE_FULL;
+        if (fl[F_DONE] != DONE_NO) fl[F_STOPPH] = 2;
         break;
     }
     case FIN_OUTER_B: {
@@ -379,7 +382,14 @@ int launch_vec_batch(hipStream_t s, wc_lattice *tlat, int op, int prec, const Ve
     }
     const int blocks = B.h.off[n];
     TimedLaunch t;
-    if (tlat && tlat->timing) timing_begin(tlat, KS_BLAS, bytes, t);
+    if (tlat && tlat->timing) {
+        timing_begin(tlat, KS_BLAS, bytes, t);
+        t.iter = tlat->tag_iter;
+        t.phase = tlat->tag_phase;
+        for (int k = 0; k < n; k++)
+            t.parts.push_back(TimedPart{{calls[k].guard ? calls[k].fl : nullptr},
+                                        vec_bytes(op, prec, xprec, calls[k].Vh)});
+    }
     switch (op) {
     case V_NORM2: launch_op<V_NORM2, P64, P64>(s, B, blocks); break;
     case V_SUB_NORM: launch_op<V_SUB_NORM, P64, P64>(s, B, blocks); break;

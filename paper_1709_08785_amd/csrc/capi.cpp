@@ -151,6 +151,26 @@ void timing_end(wc_lattice *lat, TimedLaunch &t) {
     if (t.a && t.b) lat->launches.push_back(t);
 }
 
+void timing_settle(wc_lattice *lat, size_t from, const std::vector<StopPoint> &stops) {
+    auto stopped = [&](const int *fl, int iter, int phase) {
+        for (const auto &sp : stops)
+            if (sp.fl == fl) return iter > sp.iter || (iter == sp.iter && phase >= sp.phase);
+        return false;
+    };
+    for (size_t k = from; k < lat->launches.size(); k++) {
+        TimedLaunch &t = lat->launches[k];
+        if (t.iter < 0 || t.parts.empty()) continue;
+        double live = 0.0;
+        for (const auto &part : t.parts) {
+            bool any = false;
+            for (const int *o : part.owners) any = any || !stopped(o, t.iter, t.phase);
+            if (any) live += part.bytes;
+        }
+        t.bytes = live;
+        t.skipped = live == 0.0;
+    }
+}
+
 static const char *kSlotNames[KS_COUNT] = {
     "mult_hopinv_fp64", "mult_hopinv_fp32", "mult_hopinv_fp16", "mult_dhat_fp64",
     "mult_dhat_fp32",   "mult_dhat_fp16",   "mult_other",       "blas",
@@ -164,6 +184,7 @@ struct SlotStats {
 static int collect_stats(wc_lattice *lat, SlotStats *st) {
     WC_HIP(hipStreamSynchronize(lat->stream));
     for (auto &t : lat->launches) {
+        if (t.skipped) continue;  // converged systems only: the kernel returned at once
         float ms = 0.f;
         WC_HIP(hipEventElapsedTime(&ms, t.a, t.b));
         st[t.slot].n++;

@@ -261,6 +261,21 @@ template <> struct SpinorIO<P32> {
 // FP16 storage: planes of uint4 (3 * 16 B) followed by a float scale plane at 48
 template <> struct SpinorIO<P16> {
     using R = float;
+    // stored values without their site scale, and the scale
+    __device__ static Spinor<R> load_raw(const void *base, int Vh, int i, float &s) {
+        s = *tp<float, 52>(base, i, 48);
+        Spinor<R> out;
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            const uint4 v = *tp<uint4, 52>(base, i, 16 * k);
+            const float2 a = h2f(v.x), b = h2f(v.y), c = h2f(v.z), d = h2f(v.w);
+            out.c[4 * k + 0] = {a.x, a.y};
+            out.c[4 * k + 1] = {b.x, b.y};
+            out.c[4 * k + 2] = {c.x, c.y};
+            out.c[4 * k + 3] = {d.x, d.y};
+        }
+        return out;
+    }
     template <bool NT = false> __device__ static Spinor<R> load(const void *base, int Vh, int i) {
         const float s = ld_op<NT>(tp<float, 52>(base, i, 48));
         Spinor<R> out;
@@ -498,8 +513,12 @@ template <> struct CloverIO<P32> {
 // record offset 144; entry = scale * half.
 template <> struct CloverIO<P16> {
     using R = float;
+    __device__ static float scale(const void *slab, int i) { return *tp<float, 148>(slab, i, 144); }
     template <bool NT = true> __device__ static Herm6<R> load(const void *slab, int Vh, int i, int b) {
-        const float s = *tp<float, 148>(slab, i, 144);
+        return load_scaled<NT>(slab, Vh, i, b, scale(slab, i));
+    }
+    // block b with its entries multiplied by s (s = 1: the stored values)
+    template <bool NT = true> __device__ static Herm6<R> load_scaled(const void *slab, int Vh, int i, int b, float s) {
         uint32_t w[18];
 #pragma unroll
         for (int k = 0; k < 4; k++) {
@@ -541,18 +560,36 @@ __device__ __forceinline__ void clover_apply(const void *slab, int Vh, int i, co
         wm[k] = in.c[k] - in.c[k + 6];
         wp[k] = in.c[k] + in.c[k + 6];
     }
-    {
-        Herm6<R> M = CloverIO<P>::template load<NT>(slab, Vh, i, 0);
-        herm6_apply(M, wm, ym);
-    }
-    {
-        Herm6<R> M = CloverIO<P>::template load<NT>(slab, Vh, i, 1);
-        herm6_apply(M, wp, yp);
-    }
+    if constexpr (P == P16) {
+        // one scale per site for both blocks: apply it once to the result
+        const float s = CloverIO<P16>::scale(slab, i);
+        {
+            Herm6<R> M = CloverIO<P16>::template load_scaled<NT>(slab, Vh, i, 0, 1.0f);
+            herm6_apply(M, wm, ym);
+        }
+        {
+            Herm6<R> M = CloverIO<P16>::template load_scaled<NT>(slab, Vh, i, 1, 1.0f);
+            herm6_apply(M, wp, yp);
+        }
 #pragma unroll
-    for (int k = 0; k < 6; k++) {
-        out.c[k] = yp[k] + ym[k];
-        out.c[k + 6] = yp[k] - ym[k];
+        for (int k = 0; k < 6; k++) {
+            out.c[k] = s * (yp[k] + ym[k]);
+            out.c[k + 6] = s * (yp[k] - ym[k]);
+        }
+    } else {
+        {
+            Herm6<R> M = CloverIO<P>::template load<NT>(slab, Vh, i, 0);
+            herm6_apply(M, wm, ym);
+        }
+        {
+            Herm6<R> M = CloverIO<P>::template load<NT>(slab, Vh, i, 1);
+            herm6_apply(M, wp, yp);
+        }
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            out.c[k] = yp[k] + ym[k];
+            out.c[k + 6] = yp[k] - ym[k];
+        }
     }
 }
 

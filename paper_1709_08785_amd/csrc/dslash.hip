@@ -62,9 +62,11 @@ __device__ __forceinline__ void su3_mul2(const Mat3<R> &U, const cx<R> (&h)[2][3
     }
 }
 
-// accumulate (1 -+ g_mu) U psi for direction mu; FWD selects the forward hop
-template <class R, int MU, bool FWD>
-__device__ __forceinline__ void hop_term(const Spinor<R> &p, const Mat3<R> &U, Spinor<R> &acc) {
+// accumulate (1 -+ g_mu) U psi for direction mu; FWD selects the forward hop.
+// SC: psi holds stored values whose site scale is sc (FP16 storage); the
+// scale then rides on the accumulation, where every update is an FMA anyway.
+template <class R, int MU, bool FWD, bool SC>
+__device__ __forceinline__ void hop_term(const Spinor<R> &p, const Mat3<R> &U, Spinor<R> &acc, R sc) {
     cx<R> h[2][3], g[2][3];
 #pragma unroll
     for (int a = 0; a < 3; a++) {
@@ -84,31 +86,47 @@ __device__ __forceinline__ void hop_term(const Spinor<R> &p, const Mat3<R> &U, S
         }
     }
     su3_mul2<R, !FWD>(U, h, g);
+    auto S = [&](cx<R> v) { return SC ? sc * v : v; };
 #pragma unroll
     for (int a = 0; a < 3; a++) {
         const cx<R> g0 = g[0][a], g1 = g[1][a];
         if (MU == 3) {
             if (FWD) {
-                acc.c[6 + a] = acc.c[6 + a] + g0;
-                acc.c[9 + a] = acc.c[9 + a] + g1;
+                acc.c[6 + a] = acc.c[6 + a] + S(g0);
+                acc.c[9 + a] = acc.c[9 + a] + S(g1);
             } else {
-                acc.c[a] = acc.c[a] + g0;
-                acc.c[3 + a] = acc.c[3 + a] + g1;
+                acc.c[a] = acc.c[a] + S(g0);
+                acc.c[3 + a] = acc.c[3 + a] + S(g1);
             }
             continue;
         }
-        acc.c[a] = acc.c[a] + g0;
-        acc.c[3 + a] = acc.c[3 + a] + g1;
+        acc.c[a] = acc.c[a] + S(g0);
+        acc.c[3 + a] = acc.c[3 + a] + S(g1);
         if (MU == 0) {
-            acc.c[6 + a] = acc.c[6 + a] + (FWD ? mul_mi(g1) : mul_i(g1));
-            acc.c[9 + a] = acc.c[9 + a] + (FWD ? mul_mi(g0) : mul_i(g0));
+            acc.c[6 + a] = acc.c[6 + a] + S(FWD ? mul_mi(g1) : mul_i(g1));
+            acc.c[9 + a] = acc.c[9 + a] + S(FWD ? mul_mi(g0) : mul_i(g0));
         } else if (MU == 1) {
-            acc.c[6 + a] = FWD ? acc.c[6 + a] - g1 : acc.c[6 + a] + g1;
-            acc.c[9 + a] = FWD ? acc.c[9 + a] + g0 : acc.c[9 + a] - g0;
+            acc.c[6 + a] = FWD ? acc.c[6 + a] - S(g1) : acc.c[6 + a] + S(g1);
+            acc.c[9 + a] = FWD ? acc.c[9 + a] + S(g0) : acc.c[9 + a] - S(g0);
         } else {
-            acc.c[6 + a] = acc.c[6 + a] + (FWD ? mul_mi(g0) : mul_i(g0));
-            acc.c[9 + a] = acc.c[9 + a] + (FWD ? mul_i(g1) : mul_mi(g1));
+            acc.c[6 + a] = acc.c[6 + a] + S(FWD ? mul_mi(g0) : mul_i(g0));
+            acc.c[9 + a] = acc.c[9 + a] + S(FWD ? mul_i(g1) : mul_mi(g1));
         }
+    }
+}
+
+// one neighbour: load its spinor and add its hop; FP16 storage leaves the
+// site scale to the accumulation (hop_term, SC)
+template <int P, int MU, bool FWD>
+__device__ __forceinline__ void hop_one(const void *in, int Vh, int n, const Mat3<typename Real<P>::T> &U,
+                                        Spinor<typename Real<P>::T> &acc) {
+    using R = typename Real<P>::T;
+    if constexpr (P == P16) {
+        float sc;
+        const Spinor<R> psi = SpinorIO<P16>::load_raw(in, Vh, n, sc);
+        hop_term<R, MU, FWD, true>(psi, U, acc, sc);
+    } else {
+        hop_term<R, MU, FWD, false>(SpinorIO<P>::load(in, Vh, n), U, acc, R(1));
     }
 }
 
@@ -119,16 +137,14 @@ __device__ __forceinline__ void hop_dir(const MultKArgs &a, const SiteCoord &c, 
     const int Vh = a.g.Vh;
     {
         const int nf = eo_neighbour(a.g, c, MU, +1);
-        const Spinor<R> psi = SpinorIO<P>::load(a.in, Vh, nf);
         const Mat3<R> U = LinkLoad<P, R8>::template load<NT>(a.links + (size_t)(2 * MU + a.out_par) * a.link_slab, Vh, i);
-        hop_term<R, MU, true>(psi, U, acc);
+        hop_one<P, MU, true>(a.in, Vh, nf, U, acc);
     }
     {
         const int nb = eo_neighbour(a.g, c, MU, -1);
-        const Spinor<R> psi = SpinorIO<P>::load(a.in, Vh, nb);
         const Mat3<R> U =
             LinkLoad<P, R8>::template load<NT>(a.links + (size_t)(2 * MU + 1 - a.out_par) * a.link_slab, Vh, nb);
-        hop_term<R, MU, false>(psi, U, acc);
+        hop_one<P, MU, false>(a.in, Vh, nb, U, acc);
     }
 }
 
@@ -263,7 +279,7 @@ double mult_operator_bytes(int prec, int mode, bool r8, int Vh) {
 
 }  // namespace
 
-int launch_mult_batch(hipStream_t s, const MultCall *calls, int n) {
+int launch_mult_batch(hipStream_t s, const MultCall *calls, int n, wc_lattice *timing_lat) {
     if (n <= 0) return WC_OK;
     if (n > kMaxSys) return wc_fail(WC_EINVAL, "too many systems in one batch");
     const MultCall &c0 = calls[0];
@@ -307,12 +323,29 @@ int launch_mult_batch(hipStream_t s, const MultCall *calls, int n) {
     }
     B.h.interleave = (same && n > 1) ? 1 : 0;
     const int blocks = B.h.off[n];
-    wc_lattice *tl = c0.lat;
+    wc_lattice *tl = timing_lat ? timing_lat : c0.lat;
     int slot = KS_MULT_OTHER;
     if (c0.mode == M_HOPINV) slot = KS_MULT_HOPINV_P64 + c0.prec;
     if (c0.mode == M_DHAT) slot = KS_MULT_DHAT_P64 + c0.prec;
     TimedLaunch t;
-    if (tl->timing) timing_begin(tl, slot, bytes, t);
+    if (tl->timing) {
+        timing_begin(tl, slot, bytes, t);
+        // split by system, and the operator by the systems that share it
+        t.iter = tl->tag_iter;
+        t.phase = tl->tag_phase;
+        for (int k = 0; k < n; k++) {
+            const MultCall &c = calls[k];
+            t.parts.push_back(TimedPart{{c.done}, mult_spinor_bytes(c.prec, c.mode, c.red, c.aux == c.center,
+                                                                      c.lat->Vh)});
+            bool seen = false;
+            for (int j = 0; j < k; j++) seen = seen || (calls[j].lat == c.lat);
+            if (seen) continue;
+            TimedPart op{{}, mult_operator_bytes(c.prec, c.mode, r8, c.lat->Vh)};
+            for (int j = k; j < n; j++)
+                if (calls[j].lat == c.lat) op.owners.push_back(calls[j].done);
+            t.parts.push_back(op);
+        }
+    }
     if (c0.prec == P64) dispatch_mode<P64>(B, c0.mode, c0.red, blocks, s, false);
     else if (c0.prec == P32) dispatch_mode<P32>(B, c0.mode, c0.red, blocks, s, r8);
     else dispatch_mode<P16>(B, c0.mode, c0.red, blocks, s, r8);

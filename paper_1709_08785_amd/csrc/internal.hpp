@@ -30,7 +30,9 @@ enum ScalarSlot {
     S_COUNT = 20
 };
 // flags block (ints): done code, iterations completed
-enum FlagSlot { F_DONE = 0, F_ITERS = 1, F_COUNT = 4 };
+// F_STOPPH: where the inner loop stopped: 1 at the half-step check (after the
+// first D-hat), 2 at the full-step check (after the second)
+enum FlagSlot { F_DONE = 0, F_ITERS = 1, F_STOPPH = 2, F_COUNT = 4 };
 enum DoneCode { DONE_NO = 0, DONE_FULL = 1, DONE_HALF = 2, DONE_BREAK = 4 };
 
 enum { NUM_LEVELS = 2 };  // 0 = inner loop, 1 = outer / FP64 loop
@@ -46,10 +48,24 @@ enum KernelSlot {
     KS_COUNT
 };
 
+// One timed launch.  Inner-loop launches carry the iteration and phase they
+// belong to (phase 0: first D-hat and the s update, 1: second D-hat and the
+// x, r update, 2: the p update) and their algorithmic bytes split by system
+// (keyed by the system's flag block) and by lattice operator (keyed by the
+// flag blocks of the systems that share it), so that the work of systems
+// that had already converged -- those kernels return at once -- can be taken
+// out afterwards.
+struct TimedPart {
+    std::vector<const int *> owners;  // the part counts while any owner still runs
+    double bytes;
+};
 struct TimedLaunch {
     int slot;
     double bytes;
     hipEvent_t a, b;
+    int iter = -1, phase = 0;
+    std::vector<TimedPart> parts;
+    bool skipped = false;  // every system of the launch had stopped: no work done
 };
 
 // One linear system's device-side solver state: scalar and flag blocks per
@@ -147,6 +163,7 @@ struct wc_lattice {
 
     // timing
     bool timing = false;
+    int tag_iter = -1, tag_phase = 0;  // inner-loop position of the launches being queued
     std::vector<TimedLaunch> launches;
     std::vector<hipEvent_t> event_pool;
     long dslash_count = 0;
@@ -176,6 +193,14 @@ int sync_arena(const Arena &a, hipStream_t s);
 // ---------------------------------------------------------------------------
 void timing_begin(wc_lattice *lat, int slot, double bytes, TimedLaunch &t);
 void timing_end(wc_lattice *lat, TimedLaunch &t);
+// after an inner solve: take out the bytes of systems that had stopped before
+// each tagged launch of lat->launches[from..]; stop = (iteration, phase) per
+// flag block
+struct StopPoint {
+    const int *fl;
+    int iter, phase;
+};
+void timing_settle(wc_lattice *lat, size_t from, const std::vector<StopPoint> &stops);
 
 // ---------------------------------------------------------------------------
 // reductions: target of stage 1, and stage 2 (blas.hip)
@@ -232,7 +257,8 @@ struct MultCall {
     RedTarget red_to;
     const int *done;     // skip this call when *done != 0
 };
-int launch_mult_batch(hipStream_t s, const MultCall *calls, int n);
+// timing_lat (default: the first call's lattice) receives the timing record
+int launch_mult_batch(hipStream_t s, const MultCall *calls, int n, wc_lattice *timing_lat = nullptr);
 inline int launch_mult(wc_lattice *lat, MultCall c) {
     c.lat = lat;
     return launch_mult_batch(lat->stream, &c, 1);

@@ -95,7 +95,7 @@ template <class F> int mult_over(Run &R, const std::vector<int> &act, F &&make) 
         calls[n++] = make(k);
         R.dslash[k]++;
     }
-    return launch_mult_batch(R.stream, calls, n);
+    return launch_mult_batch(R.stream, calls, n, R.tl);
 }
 
 template <class F> int vec_over(Run &R, const std::vector<int> &act, int op, int prec, F &&make) {
@@ -130,27 +130,37 @@ int dhat(Run &R, const std::vector<int> &act, int prec, int out_id, int in_id, i
 // one chunk of n iterations of Algorithm 2 for the systems in act; every
 // kernel takes the iteration index from the system's device flags, so the
 // same launches serve any chunk (and can be recorded once as a graph)
-int inner_chunk(Run &R, const std::vector<int> &act, int n) {
+int inner_chunk(Run &R, const std::vector<int> &act, int n, int base = 0) {
     const int L = 0, P = R.iprec;
     auto loop = [&](VecCall v) {
         v.iter_dev = 1;
         v.guard = 1;
         return v;
     };
+    // tags for the timing records: iteration and phase (0: first D-hat and the
+    // s update, 1: second D-hat and the x, r update, 2: the p update)
+    auto tag = [&](int it, int ph) {
+        R.tl->tag_iter = it;
+        R.tl->tag_phase = ph;
+    };
     for (int j = 0; j < n; j++) {
+        tag(base + j, 0);
         if (int rc = dhat(R, act, P, W_IQ, W_IP, W_ITMP, R_DOT, W_IRT, L, S_RQ, true)) return rc;
         if (int rc = vec_over(R, act, V_INNER_A, P,
                               [&](int k) { return loop(vc(R, k, L, W(R, k, W_IR), W(R, k, W_IQ))); }))
             return rc;
+        tag(base + j, 1);
         if (int rc = dhat(R, act, P, W_IT, W_IR, W_ITMP, R_DOTNORM, W_IR, L, S_ST, true)) return rc;
         if (int rc = vec_over(R, act, V_INNER_B, P, [&](int k) {
                 return loop(vc(R, k, L, W(R, k, W_IX), W(R, k, W_IR), W(R, k, W_IP), W(R, k, W_IT), W(R, k, W_IRT)));
             }))
             return rc;
+        tag(base + j, 2);
         if (int rc = vec_over(R, act, V_INNER_C, P,
                               [&](int k) { return loop(vc(R, k, L, W(R, k, W_IP), W(R, k, W_IR), W(R, k, W_IQ))); }))
             return rc;
     }
+    tag(-1, 0);
     return WC_OK;
 }
 
@@ -215,15 +225,29 @@ int inner_solve(Run &R, const std::vector<int> &act, int src_id, int v_id) {
         return rc;
     const int maxit = R.fixed_work > 0 ? R.fixed_work : R.imaxit;
     const bool graph = R.use_graph && !R.tl->timing;
+    const size_t timed_from = R.tl->launches.size();
+    const std::vector<long> dslash_before = R.dslash;
     int queued = 0;
     while (queued < maxit) {
         const int n = std::min(R.check_every, maxit - queued);
-        if (int rc = graph ? inner_chunk_graph(R, act, n) : inner_chunk(R, act, n)) return rc;
+        if (int rc = graph ? inner_chunk_graph(R, act, n) : inner_chunk(R, act, n, queued)) return rc;
         queued += n;
         if (int rc = sync(R)) return rc;
         bool all = true;
         for (int k : act) all = all && S_(R, k).st->hf(L, F_DONE) != DONE_NO;
         if (all) break;
+    }
+    if (R.tl->timing) {
+        // launches queued after a system stopped did no work for it
+        std::vector<StopPoint> stops;
+        for (int k : act) {
+            const SysState &st = *S_(R, k).st;
+            const int ph = st.hf(L, F_STOPPH);
+            if (st.hf(L, F_DONE) == DONE_NO || ph == 0) continue;
+            const int it = st.hf(L, F_ITERS);
+            stops.push_back(StopPoint{st.fl(L), ph == 1 ? it : it - 1, ph});
+        }
+        timing_settle(R.tl, timed_from, stops);
     }
     std::vector<int> fix;
     for (int k : act) {
@@ -236,6 +260,11 @@ int inner_solve(Run &R, const std::vector<int> &act, int src_id, int v_id) {
         }
         s.info.inner_iters_total += iters;
         s.info.inner_calls += 1;
+        // MULTs done: four per full iteration, two for a half-step exit (the
+        // launches queued after the stop returned at once)
+        const int stopph = s.st->hf(L, F_STOPPH);
+        const long full = s.st->hf(L, F_ITERS);
+        R.dslash[k] = dslash_before[k] + 4 * full + ((code != DONE_NO && stopph == 1) ? 2 : 0);
     }
     if (!fix.empty())
         if (int rc = vec_over(R, fix, V_INNER_FIX, P, [&](int k) {
