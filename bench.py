@@ -97,6 +97,42 @@ def cpu_baseline(U, b, dims, kappa, csw, budget_s=20.0):
     }
 
 
+def small_config():
+    """The 8^4, kappa 0.12, c_SW 1.0 system (links seed 1001, Gaussian source seed
+    2001) solved to 1e-10 by the GPU (FP32 inner, Algorithm 1 outer) and by the
+    FP64 oracle's plain BiCGStab on the full D, on the host cores: context for
+    the oracle's cost at the size its parity tests use."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1709_08785_amd as wc
+    import synth
+
+    dims, kappa, csw = (8, 8, 8, 8), 0.12, 1.0
+    U = synth.random_links(dims, 0.3, 1001)
+    b = synth.gaussian_source(dims, 2001)
+    lat = wc.Lattice(dims)
+    lat.load_links(torch.from_numpy(U).cuda())
+    bd = torch.from_numpy(b).cuda()
+    lat.solve(bd, kappa, csw, 1e-10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, info = lat.solve(bd, kappa, csw, 1e-10)
+    torch.cuda.synchronize()
+    t_gpu = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    F = oracle.clover_field(U, dims, kappa, csw)
+    x_ref, its, _ = oracle.solve(U, F, kappa, b, tol=1e-10)
+    t_cpu = time.perf_counter() - t0
+    xh = x.cpu().numpy()
+    lat.close()
+    return {"lattice": list(dims), "kappa": kappa, "tol": 1e-10, "gpu_s": round(t_gpu, 5),
+            "gpu_inner_iters": info["inner_iters_total"], "oracle_s": round(t_cpu, 3), "oracle_iters": its,
+            "oracle_threads": oracle.num_threads(),
+            "solution_rel_diff": float(np.linalg.norm(xh - x_ref) / np.linalg.norm(x_ref))}
+
+
 def dslash_mode(args, dims):
     """Operator micro-benchmark: MULT and D-hat_ee in each precision, K launches each,
     timed with HIP events on the library stream; plus a device copy of known size
@@ -461,10 +497,12 @@ def main():
                   "fp16_inner": arm(wc.FP16, 12, "dc")}
 
     cpu = None
+    small = None
     if not args.no_cpu_baseline:
         del x
         torch.cuda.synchronize()
         cpu = cpu_baseline(U, b, dims, args.kappa, args.csw)
+        small = small_config()
 
     last = infos[-1]
     out = {
@@ -488,6 +526,7 @@ def main():
                    "inner": args.inner, "inner_tol": args.inner_tol, "link_recon": args.recon},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "small_config_8x8x8x8": small,
         "time_to_solution_s": {"mixed": round(ms_per_step / 1e3, 4), "fp64": fp64["seconds"] if fp64 else None,
                                "mixed_fp16_inner": fp16["seconds"] if fp16 else None,
                                "mixed_recon8": recon8["fp32_inner"]["seconds"] if recon8 else None,

@@ -63,18 +63,74 @@ def test_solve_32x32x32x64_oracle_residual(c2, inner):
     assert abs(r / bn - info["true_rel_residual"]) < 1e-12
 
 
-def test_solve_48x48x48x96_fp16_oracle_residual():
+def test_apply_D_recon8_sampled_sites_32x32x32x64(c2):
+    dims, lat, U, Ud = c2
+    say("apply_D sampled, reconstruct-8")
+    psi = synth.gaussian_source(dims, 2002)
+    lat.set_link_recon(8)
+    try:
+        out = lat.apply_D(torch.from_numpy(psi).cuda(), wc.FP32).cpu().numpy().reshape(-1, 4, 3)
+    finally:
+        lat.set_link_recon(12)
+    g = synth.rng(10)
+    V = int(np.prod(dims))
+    sites = np.concatenate([g.integers(0, V, 4000), [0, 1, V - 1, V - 2, dims[0] - 1]])
+    ref = oracle.apply_D_sites(U, 0.135, 1.0, psi, sites)
+    err = np.linalg.norm(out[sites] - ref) / np.linalg.norm(ref)
+    say("rel err", err)
+    assert err < 1e-5
+
+
+@pytest.mark.parametrize("inner,recon,outer", [(wc.FP32, 8, "bicgstab"), (wc.FP16, 12, "dc")])
+def test_solve_32x32x32x64_variants_oracle_residual(c2, inner, recon, outer):
+    dims, lat, U, Ud = c2
+    say("solve 32^3x64", inner, recon, outer)
+    b = synth.gaussian_source(dims, 2002)
+    lat.set_link_recon(recon)
+    try:
+        x, info = lat.solve(torch.from_numpy(b).cuda(), 0.135, 1.0, 1e-10, inner_prec=inner, outer=outer)
+    finally:
+        lat.set_link_recon(12)
+    r, bn = oracle.residual(U, 0.135, 1.0, b, x.cpu().numpy())
+    say(info, "oracle", r / bn)
+    assert r / bn < 1e-10
+
+
+@pytest.fixture(scope="module")
+def c3():
     dims = (48, 48, 48, 96)
-    kappa, csw = 0.1355, 1.0
-    say("solve 48^3x96 fp16")
     Ud = synth.random_links_torch(dims, 0.3, 1003, device="cuda")
     lat = wc.Lattice(dims)
     lat.load_links(Ud)
     U = Ud.cpu().numpy()
     del Ud
     b = synth.z2_source(dims, 2003)
+    yield dims, lat, U, b
+    lat.close()
+
+
+def test_solve_48x48x48x96_fp16_oracle_residual(c3):
+    dims, lat, U, b = c3
+    kappa, csw = 0.1355, 1.0
+    say("solve 48^3x96 fp16")
     x, info = lat.solve(torch.from_numpy(b).cuda(), kappa, csw, 1e-10, inner_prec=wc.FP16)
     r, bn = oracle.residual(U, kappa, csw, b, x.cpu().numpy())
     say(info, "oracle", r / bn)
     assert r / bn < 1e-10
-    lat.close()
+
+
+def test_solve_48x48x48x96_recon8_converges_like_recon12(c3):
+    # 42M links: a link rebuilt from the wrong entries anywhere would slow the
+    # FP32 inner solve well beyond the two-column form's 198 iterations
+    dims, lat, U, b = c3
+    kappa, csw = 0.1355, 1.0
+    say("solve 48^3x96 fp32 reconstruct-8")
+    lat.set_link_recon(8)
+    try:
+        x, info = lat.solve(torch.from_numpy(b).cuda(), kappa, csw, 1e-10, inner_prec=wc.FP32)
+    finally:
+        lat.set_link_recon(12)
+    r, bn = oracle.residual(U, kappa, csw, b, x.cpu().numpy())
+    say(info, "oracle", r / bn)
+    assert r / bn < 1e-10
+    assert info["outer_iters"] == 1 and info["inner_iters_total"] < 230
