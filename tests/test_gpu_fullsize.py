@@ -134,3 +134,27 @@ def test_solve_48x48x48x96_recon8_converges_like_recon12(c3):
     say(info, "oracle", r / bn)
     assert r / bn < 1e-10
     assert info["outer_iters"] == 1 and info["inner_iters_total"] < 230
+
+
+def test_solve_pure_gauge_fft_32x32x32x64():
+    # full-size solve with no oracle solver: for U_mu(n) = Om(n) Om(n+mu)^dagger,
+    # D[U] = Om D_free Om^dagger, so x = Om FFT-solve(Om^dagger b) (closed form
+    # in momentum space); Haar Om makes every link a generic SU(3) matrix
+    dims = (32, 32, 32, 64)
+    kappa = 0.12
+    lx, ly, lz, lt = dims
+    say("pure gauge FFT solve 32^3x64")
+    om = synth.haar_su3((lt, lz, ly, lx), synth.rng(78))
+    U = synth.pure_gauge_links(om, dims)
+    lat = wc.Lattice(dims)
+    lat.load_links(torch.from_numpy(U).cuda())
+    del U
+    b = synth.gaussian_source(dims, 79)
+    x, info = lat.solve(torch.from_numpy(b).cuda(), kappa, 1.0, 1e-12)
+    say(info)
+    omd_b = np.einsum("...ji,...aj->...ai", np.conj(om), b)
+    x_ref = np.einsum("...ij,...aj->...ai", om, oracle.free_solve_fft(omd_b, kappa))
+    err = np.linalg.norm(x.cpu().numpy() - x_ref) / np.linalg.norm(x_ref)
+    say("rel err", err)
+    assert err < 1e-10
+    lat.close()

@@ -212,6 +212,27 @@ def test_solve_pure_gauge_fft_closed_form():
     assert rel(host(x), x_ref) < 1e-10
 
 
+def test_solve_gauge_covariance():
+    # x[U^Om, Om b] = Om x[U, b] for U^Om_mu(n) = Om(n) U_mu(n) Om(n+mu)^dagger
+    dims = (8, 8, 8, 16)
+    kappa = 0.13
+    lx, ly, lz, lt = dims
+    U = synth.random_links(dims, 0.3, 1020)
+    om = synth.haar_su3((lt, lz, ly, lx), synth.rng(1021))
+    Uo = synth.gauge_transform_links(U, om, dims)
+    b = synth.gaussian_source(dims, 1022)
+    bo = np.einsum("...ij,...aj->...ai", om, b)
+    xs = []
+    for links, src in ((U, b), (Uo, bo)):
+        lat = wc.Lattice(dims)
+        lat.load_links(dev(links))
+        x, info = lat.solve(dev(src), kappa, 1.0, 1e-12)
+        assert info["true_rel_residual"] < 1e-12
+        xs.append(host(x))
+        lat.close()
+    assert rel(xs[1], np.einsum("...ij,...aj->...ai", om, xs[0])) < 1e-10
+
+
 def test_solve_zero_source_and_guess():
     dims = (4, 4, 4, 4)
     lat, U, F, Finv = setup_case(dims, seed=5)
