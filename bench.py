@@ -279,6 +279,46 @@ def batch_mode(args):
     print(json.dumps(out), flush=True)
 
 
+def inner_mode(args):
+    """Algorithm 2 against the pipelined inner BiCGStab (two reduction phases per
+    iteration instead of four, more vector traffic) from the launch-bound 8^4 to
+    the bandwidth-bound 32^3x64: FP32 inner, Algorithm 1 outer, kappa 0.13,
+    c_SW 1.0, Gaussian source, tol on the true residual; chunk graphs on."""
+    import torch
+
+    import paper_1709_08785_amd as wc
+    import synth
+
+    dev = torch.device("cuda:0")
+    kappa, csw = 0.13, 1.0
+    rows = {}
+    for i, d in enumerate([(8, 8, 8, 8), (16, 16, 16, 16), (24, 24, 24, 48), (32, 32, 32, 64)]):
+        lat = wc.Lattice(d, device=dev)
+        lat.load_links(torch.from_numpy(synth.random_links(d, 0.3, 1100 + i)).to(dev))
+        lat.build_clover(kappa, csw)
+        b = torch.from_numpy(synth.gaussian_source(d, 2100 + i)).to(dev)
+        row = {}
+        for name in ("bicgstab", "pipelined"):
+            lat.solve(b, kappa, csw, args.tol, inner_method=name)
+            reps = 20 if d[0] <= 16 else 3
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for r in range(reps):
+                x, info = lat.solve(b, kappa, csw, args.tol, inner_method=name)
+            torch.cuda.synchronize()
+            el = (time.perf_counter() - t0) / reps
+            row[name] = {"ms": round(el * 1e3, 3), "inner_iters": info["inner_iters_total"],
+                         "inner_calls": info["inner_calls"], "outer_iters": info["outer_iters"],
+                         "us_per_inner_iter": round(el * 1e6 / info["inner_iters_total"], 2),
+                         "true_rel_residual": info["true_rel_residual"]}
+            log("inner %s %s %s" % ("x".join(map(str, d)), name, json.dumps(row[name])))
+        row["pipelined_speedup"] = round(row["bicgstab"]["ms"] / row["pipelined"]["ms"], 3)
+        rows["x".join(map(str, d))] = row
+        lat.close()
+    print(json.dumps({"mode": "inner", "kappa": kappa, "csw": csw, "tol": args.tol, "inner": "fp32",
+                      "lattices": rows}), flush=True)
+
+
 def precisions_mode(args):
     """The three precision forms on the 48^3x96 lattice (kappa 0.1355, c_SW 1.0,
     Z2 source), all refined in FP64 to true relative residual tol: FP16-storage
@@ -341,7 +381,7 @@ def precisions_mode(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--mode", choices=["solve", "dslash", "batch", "precisions"], default="solve")
+    ap.add_argument("--mode", choices=["solve", "dslash", "batch", "precisions", "inner"], default="solve")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
@@ -377,6 +417,9 @@ def main():
         return
     if args.mode == "precisions":
         precisions_mode(args)
+        return
+    if args.mode == "inner":
+        inner_mode(args)
         return
     t0 = time.perf_counter()
     U = synth.random_links(dims, 0.3, args.seed)

@@ -89,9 +89,15 @@ typedef struct {
     int outer;            /* outer iteration around the inner solver: WC_OUTER_BICGSTAB (default,
                              the flexible BiCGStab of Algorithm 1) or WC_OUTER_DC (defect
                              correction: x_e += M r_e, r_e recomputed in FP64 each step) */
+    int inner_method;     /* WC_INNER_BICGSTAB (default, Algorithm 2) or WC_INNER_PIPELINED: the
+                             pipelined BiCGStab of Cools and Vanroose (2017), the same iterates
+                             with two reduction phases per iteration instead of four and
+                             about 9 more vector passes; it also needs 4 more inner-precision
+                             work vectors per system */
 } wc_solve_params;
 
 enum wc_outer { WC_OUTER_BICGSTAB = 0, WC_OUTER_DC = 1 };
+enum wc_inner_method { WC_INNER_BICGSTAB = 0, WC_INNER_PIPELINED = 1 };
 
 /* What a solve did.  Iteration counts follow Algorithms 1 and 2. */
 typedef struct {

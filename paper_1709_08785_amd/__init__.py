@@ -39,10 +39,12 @@ class WCError(RuntimeError):
 class SolveParams(ctypes.Structure):
     _fields_ = [("inner_prec", ctypes.c_int), ("inner_tol", ctypes.c_double), ("inner_maxit", ctypes.c_int),
                 ("outer_maxit", ctypes.c_int), ("fixed_work", ctypes.c_int), ("check_every", ctypes.c_int),
-                ("adjoint", ctypes.c_int), ("use_graph", ctypes.c_int), ("outer", ctypes.c_int)]
+                ("adjoint", ctypes.c_int), ("use_graph", ctypes.c_int), ("outer", ctypes.c_int),
+                ("inner_method", ctypes.c_int)]
 
 
 OUTER = {"bicgstab": 0, "dc": 1}
+INNER_METHOD = {"bicgstab": 0, "pipelined": 1}
 
 
 class SolveInfo(ctypes.Structure):
@@ -245,6 +247,8 @@ class Lattice:
                 v = _prec(v)
             if k == "outer" and isinstance(v, str):
                 v = OUTER[v]
+            if k == "inner_method" and isinstance(v, str):
+                v = INNER_METHOD[v]
             setattr(p, k, v)
         return p
 

@@ -31,9 +31,18 @@ template <class R> __device__ __forceinline__ cx<R> to(cx<double> a) { return {(
 // number of reduced values of each op (0: no reduction)
 __host__ __device__ constexpr int red_count(int op) {
     return op == V_NORM2 ? 2
-         : (op == V_SUB_NORM || op == V_INNER_INIT || op == V_INNER_A || op == V_OUTER_A) ? 1
+         : (op == V_SUB_NORM || op == V_INNER_INIT || op == V_INNER_A || op == V_OUTER_A || op == V_PIPE_INIT) ? 1
          : (op == V_INNER_B || op == V_OUTER_B) ? 3
+         : op == V_PIPE_A ? 8
+         : op == V_PIPE_B ? 5
          : 0;
+}
+
+// a += conj(x) y as (re, im) into two accumulators
+template <class T> __device__ __forceinline__ void dot_acc(double &re, double &im, cx<T> x, cx<T> y) {
+    const double xr = x.re, xi = x.im, yr = y.re, yi = y.im;
+    re += xr * yr + xi * yi;
+    im += xr * yi - xi * yr;
 }
 
 template <int OP, int P, int XP> __global__ __launch_bounds__(kBlock) void k_vec(VecBatch B) {
@@ -242,6 +251,132 @@ template <int OP, int P, int XP> __global__ __launch_bounds__(kBlock) void k_vec
             SpinorIO<P64>::template store<kVNT>(c.b, Vh, i, rv);
         }
     }
+    if (OP == V_PIPE_INIT) {
+        // b = src / ||src||; r = r~ = b; x = 0; p = s = z = v = 0 (the recurrences
+        // start with beta = 0, so the zeros only keep them finite); rho = <r~, r>
+        if (active) {
+            const double nrm2 = c.sc[S_NORM];
+            const double inv = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
+            const Spinor<double> v = SpinorIO<P64>::template load<kVNT>(c.a, Vh, i);
+            Spinor<R> b, z;
+#pragma unroll
+            for (int k = 0; k < 12; k++) {
+                b.c[k] = {(R)(inv * v.c[k].re), (R)(inv * v.c[k].im)};
+                z.c[k] = {R(0), R(0)};
+            }
+            SpinorIO<P>::template store<kVNT>(c.b, Vh, i, b);
+            SpinorIO<P>::template store<kVNT>(c.c, Vh, i, b);
+            SpinorIO<P>::template store<kVNT>(c.e, Vh, i, z);
+            SpinorIO<P>::template store<kVNT>(c.f, Vh, i, z);
+            SpinorIO<P>::template store<kVNT>(c.g, Vh, i, z);
+            SpinorIO<P>::template store<kVNT>(c.h, Vh, i, z);
+            Spinor<RX> zx;
+#pragma unroll
+            for (int k = 0; k < 12; k++) zx.c[k] = {RX(0), RX(0)};
+            SpinorIO<XP>::template store<kVNT>(c.d, Vh, i, zx);
+            const Spinor<R> bs = SpinorIO<P>::load(c.b, Vh, i);
+#pragma unroll
+            for (int k = 0; k < 12; k++) a[0] += norm2(bs.c[k]);
+        }
+    } else if (OP == V_PIPE_A) {
+        // p = r + beta (p - omega s); s = w + beta (s - omega z); z = t + beta (z - omega v)
+        // with the new s, z: q = r - alpha s, y = w - alpha z, and the sums
+        // <y, q>, ||y||^2, ||q||^2, <r~, s>, <r~, z> (q and y are not stored)
+        const cx<R> al = to<R>(ld_c(c.sc, S_RQ)), om = to<R>(ld_c(c.sc, S_ST)), be = to<R>(ld_c(c.sc, S_RHO1));
+        if (active) {
+            const Spinor<R> s0 = SpinorIO<P>::template load<kVNT>(c.e, Vh, i);
+            const Spinor<R> r = SpinorIO<P>::template load<kVNT>(c.a, Vh, i);
+            {
+                Spinor<R> pv = SpinorIO<P>::template load<kVNT>(c.d, Vh, i);
+#pragma unroll
+                for (int k = 0; k < 12; k++) pv.c[k] = r.c[k] + be * (pv.c[k] - om * s0.c[k]);
+                SpinorIO<P>::template store<kVNT>(c.d, Vh, i, pv);
+            }
+            const Spinor<R> z0 = SpinorIO<P>::template load<kVNT>(c.f, Vh, i);
+            const Spinor<R> w = SpinorIO<P>::template load<kVNT>(c.b, Vh, i);
+            Spinor<R> sn;
+#pragma unroll
+            for (int k = 0; k < 12; k++) sn.c[k] = w.c[k] + be * (s0.c[k] - om * z0.c[k]);
+            SpinorIO<P>::template store<kVNT>(c.e, Vh, i, sn);
+            Spinor<R> zn;
+            {
+                const Spinor<R> t = SpinorIO<P>::template load<kVNT>(c.c, Vh, i);
+                const Spinor<R> v = SpinorIO<P>::template load<kVNT>(c.g, Vh, i);
+#pragma unroll
+                for (int k = 0; k < 12; k++) zn.c[k] = t.c[k] + be * (z0.c[k] - om * v.c[k]);
+            }
+            SpinorIO<P>::template store<kVNT>(c.f, Vh, i, zn);
+            const Spinor<R> rt = SpinorIO<P>::template load<kVNT>(c.h, Vh, i);
+#pragma unroll
+            for (int k = 0; k < 12; k++) {
+                const cx<R> q = r.c[k] - al * sn.c[k], y = w.c[k] - al * zn.c[k];
+                dot_acc(a[0 % NA], a[1 % NA], y, q);
+                a[2 % NA] += norm2(y);
+                a[3 % NA] += norm2(q);
+                dot_acc(a[4 % NA], a[5 % NA], rt.c[k], sn.c[k]);
+                dot_acc(a[6 % NA], a[7 % NA], rt.c[k], zn.c[k]);
+            }
+        }
+    } else if (OP == V_PIPE_B) {
+        // q = r - alpha s, y = w - alpha z; x += alpha p + omega q; r = q - omega y;
+        // w = y - omega (t - alpha v); sums <r~, r>, <r~, w>, ||r||^2
+        const cx<double> ald = ld_c(c.sc, S_RQ), omd = ld_c(c.sc, S_ST);
+        const cx<R> al = to<R>(ald), om = to<R>(omd);
+        const cx<RX> alx = to<RX>(ald), omx = to<RX>(omd);
+        if (active) {
+            const Spinor<R> r = SpinorIO<P>::template load<kVNT>(c.c, Vh, i);
+            const Spinor<R> sv = SpinorIO<P>::template load<kVNT>(c.d, Vh, i);
+            Spinor<R> q;
+#pragma unroll
+            for (int k = 0; k < 12; k++) q.c[k] = r.c[k] - al * sv.c[k];
+            {
+                Spinor<RX> xv = SpinorIO<XP>::template load<kVNT>(c.a, Vh, i);
+                const Spinor<R> pv = SpinorIO<P>::template load<kVNT>(c.b, Vh, i);
+#pragma unroll
+                for (int k = 0; k < 12; k++) {
+                    const cx<RX> pk = {(RX)pv.c[k].re, (RX)pv.c[k].im}, qk = {(RX)q.c[k].re, (RX)q.c[k].im};
+                    xv.c[k] = xv.c[k] + alx * pk + omx * qk;
+                }
+                SpinorIO<XP>::template store<kVNT>(c.a, Vh, i, xv);
+            }
+            Spinor<R> y;
+            {
+                const Spinor<R> w = SpinorIO<P>::template load<kVNT>(c.e, Vh, i);
+                const Spinor<R> zv = SpinorIO<P>::template load<kVNT>(c.f, Vh, i);
+#pragma unroll
+                for (int k = 0; k < 12; k++) y.c[k] = w.c[k] - al * zv.c[k];
+            }
+            Spinor<R> rn;
+#pragma unroll
+            for (int k = 0; k < 12; k++) rn.c[k] = q.c[k] - om * y.c[k];
+            SpinorIO<P>::template store<kVNT>(c.c, Vh, i, rn);
+            Spinor<R> wn;
+            {
+                const Spinor<R> t = SpinorIO<P>::template load<kVNT>(c.g, Vh, i);
+                const Spinor<R> v = SpinorIO<P>::template load<kVNT>(c.h, Vh, i);
+#pragma unroll
+                for (int k = 0; k < 12; k++) wn.c[k] = y.c[k] - om * (t.c[k] - al * v.c[k]);
+            }
+            SpinorIO<P>::template store<kVNT>(c.e, Vh, i, wn);
+            const Spinor<R> rt = SpinorIO<P>::template load<kVNT>(c.j, Vh, i);
+#pragma unroll
+            for (int k = 0; k < 12; k++) {
+                dot_acc(a[0 % NA], a[1 % NA], rt.c[k], rn.c[k]);
+                dot_acc(a[2 % NA], a[3 % NA], rt.c[k], wn.c[k]);
+                a[4 % NA] += norm2(rn.c[k]);
+            }
+        }
+    } else if (OP == V_PIPE_FIX) {
+        // x += alpha p with alpha from the pipelined loop's slot
+        if (active) {
+            const cx<RX> alx = to<RX>(ld_c(c.sc, S_RQ));
+            Spinor<RX> xv = SpinorIO<XP>::template load<kVNT>(c.a, Vh, i);
+            const Spinor<R> pv = SpinorIO<P>::template load<kVNT>(c.b, Vh, i);
+#pragma unroll
+            for (int k = 0; k < 12; k++) xv.c[k] = xv.c[k] + alx * cx<RX>{(RX)pv.c[k].re, (RX)pv.c[k].im};
+            SpinorIO<XP>::template store<kVNT>(c.a, Vh, i, xv);
+        }
+    }
     if (N > 0) block_partials<NA>(a, c.partials, (Vh + kBlock - 1) / kBlock, lb);
 }
 
@@ -304,6 +439,61 @@ template <int N> __global__ __launch_bounds__(kBlock) void k_finalize(FinBatch B
         if (fl[F_DONE] != DONE_NO) fl[F_STOPPH] = 2;
         break;
     }
+    case FIN_PIPE_INIT: {
+        // alpha_0 = rho / <r~, w> (the D-hat reduction left <r~, w> in S_RQ)
+        const cx<double> al = cdiv(ld_c(sc, S_RHO0), ld_c(sc, S_RQ));
+        sc[S_RQ] = al.re;
+        sc[S_RQ + 1] = al.im;
+        sc[S_ST] = 1.0;
+        sc[S_ST + 1] = 0.0;
+        sc[S_RHO1] = 0.0;
+        sc[S_RHO1 + 1] = 0.0;
+        if (!finite_c(al)) {
+            fl[F_DONE] = DONE_BREAK;
+            fl[F_STOPPH] = 1;
+        }
+        break;
+    }
+    case FIN_PIPE_A: {
+        const double yy = a[2 % N], qq = a[3 % N];
+        const cx<double> om = {a[0] / yy, a[1 % N] / yy};
+        sc[S_ST] = om.re;
+        sc[S_ST + 1] = om.im;
+        sc[S_AUX] = a[4 % N];
+        sc[S_AUX + 1] = a[5 % N];
+        sc[S_AUX + 2] = a[6 % N];
+        sc[S_AUX + 3] = a[7 % N];
+        sc[S_SS] = qq;
+        sc[S_TT] = yy;
+        if (isfinite(qq) && qq < sc[S_TOL2]) fl[F_DONE] = DONE_HALF;
+        else if (!(yy > 0.0) || !finite_c(om) || !isfinite(qq)) fl[F_DONE] = DONE_BREAK;
+        if (fl[F_DONE] != DONE_NO) fl[F_STOPPH] = 1;
+        break;
+    }
+    case FIN_PIPE_B: {
+        const int it = fl[F_ITERS];
+        const cx<double> rho1 = {a[0], a[1 % N]}, rw = {a[2 % N], a[3 % N]};
+        const double rr = a[4 % N];
+        const cx<double> al = ld_c(sc, S_RQ), om = ld_c(sc, S_ST), rho0 = ld_c(sc, S_RHO0);
+        const cx<double> be = cdiv(al, om) * cdiv(rho1, rho0);
+        const cx<double> den = rw + be * ld_c(sc, S_AUX) - be * om * ld_c(sc, S_AUX + 2);
+        const cx<double> aln = cdiv(rho1, den);
+        sc[S_RHO0] = rho1.re;
+        sc[S_RHO0 + 1] = rho1.im;
+        sc[S_RHO1] = be.re;
+        sc[S_RHO1 + 1] = be.im;
+        sc[S_RQ] = aln.re;
+        sc[S_RQ + 1] = aln.im;
+        sc[S_RR] = rr;
+        fl[F_ITERS] = it + 1;
+        const double tol2 = sc[S_TOL2];
+        if (!finite_c(be) || !finite_c(aln) || !isfinite(rr) || (rho1.re == 0.0 && rho1.im == 0.0))
+            fl[F_DONE] = (rr < tol2) ? DONE_FULL : DONE_BREAK;
+        else if (rr < tol2)
+            fl[F_DONE] = DONE_FULL;
+        if (fl[F_DONE] != DONE_NO) fl[F_STOPPH] = 2;
+        break;
+    }
     case FIN_OUTER_B: {
         const int nxt = rho_slot(f.iter + 1);
         sc[S_RR] = a[0];
@@ -334,6 +524,10 @@ double vec_bytes(int op, int prec, int xprec, int Vh) {
     case V_INNER_FIX: return S + 2 * X;
     case V_INNER_FINAL: return X + D;
     case V_OUTER_A: return 6 * D;
+    case V_PIPE_INIT: return D + 6 * S + X;
+    case V_PIPE_A: return 11 * S;
+    case V_PIPE_B: return 10 * S + 2 * X;
+    case V_PIPE_FIX: return S + 2 * X;
     case V_OUTER_B: return 7 * D;
     }
     return 0;
@@ -360,7 +554,10 @@ int launch_fin_batch(hipStream_t s, const FinArgs *f, int n, int nvals) {
     switch (nvals) {
     case 1: hipLaunchKernelGGL(k_finalize<1>, dim3(n), dim3(kBlock), 0, s, B); break;
     case 2: hipLaunchKernelGGL(k_finalize<2>, dim3(n), dim3(kBlock), 0, s, B); break;
-    default: hipLaunchKernelGGL(k_finalize<3>, dim3(n), dim3(kBlock), 0, s, B); break;
+    case 3: hipLaunchKernelGGL(k_finalize<3>, dim3(n), dim3(kBlock), 0, s, B); break;
+    case 5: hipLaunchKernelGGL(k_finalize<5>, dim3(n), dim3(kBlock), 0, s, B); break;
+    case 8: hipLaunchKernelGGL(k_finalize<8>, dim3(n), dim3(kBlock), 0, s, B); break;
+    default: return wc_fail(WC_EINVAL, "unsupported reduction width");
     }
     WC_HIP(hipGetLastError());
     return WC_OK;
@@ -403,6 +600,10 @@ int launch_vec_batch(hipStream_t s, wc_lattice *tlat, int op, int prec, const Ve
     case V_INNER_C: dispatch_inner<V_INNER_C>(s, B, blocks, prec); break;
     case V_INNER_FIX: dispatch_inner<V_INNER_FIX>(s, B, blocks, prec); break;
     case V_INNER_FINAL: dispatch_inner<V_INNER_FINAL>(s, B, blocks, prec); break;
+    case V_PIPE_INIT: dispatch_inner<V_PIPE_INIT>(s, B, blocks, prec); break;
+    case V_PIPE_A: dispatch_inner<V_PIPE_A>(s, B, blocks, prec); break;
+    case V_PIPE_B: dispatch_inner<V_PIPE_B>(s, B, blocks, prec); break;
+    case V_PIPE_FIX: dispatch_inner<V_PIPE_FIX>(s, B, blocks, prec); break;
     case V_OUTER_A: launch_op<V_OUTER_A, P64, P64>(s, B, blocks); break;
     case V_OUTER_B: launch_op<V_OUTER_B, P64, P64>(s, B, blocks); break;
     default: return wc_fail(WC_EINVAL, "unknown vector op");
@@ -426,11 +627,13 @@ int launch_vec_batch(hipStream_t s, wc_lattice *tlat, int op, int prec, const Ve
         a.guard = c.guard ? c.fl : nullptr;
         a.iter = c.iter;
         a.tol2 = c.tol2;
-        a.op = (op == V_INNER_INIT) ? FIN_INIT
-             : (op == V_INNER_A)    ? FIN_INNER_A
-             : (op == V_INNER_B)    ? FIN_INNER_B
-             : (op == V_OUTER_B)    ? FIN_OUTER_B
-                                    : FIN_STORE;
+        a.op = (op == V_INNER_INIT || op == V_PIPE_INIT) ? FIN_INIT
+             : (op == V_INNER_A)                          ? FIN_INNER_A
+             : (op == V_INNER_B)                          ? FIN_INNER_B
+             : (op == V_OUTER_B)                          ? FIN_OUTER_B
+             : (op == V_PIPE_A)                           ? FIN_PIPE_A
+             : (op == V_PIPE_B)                           ? FIN_PIPE_B
+                                                          : FIN_STORE;
         if (op == V_OUTER_A) a.result = c.sc + S_RR;
     }
     return launch_fin_batch(s, f, n, N);

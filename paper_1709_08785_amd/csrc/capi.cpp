@@ -112,11 +112,12 @@ static void free_batch(BatchCache *b) {
 
 // allocate (or keep) the solve vectors of one system on lattice lat; a moved
 // buffer invalidates the graphs captured for the arena
-static int ensure_work(wc_lattice *lat, SysWork &w, int iprec, Arena &arena) {
+static int ensure_work(wc_lattice *lat, SysWork &w, int iprec, bool pipe, Arena &arena) {
     const size_t d = spinor_bytes(P64, lat->Vh), i = spinor_bytes(iprec, lat->Vh),
-                 x = spinor_bytes(iprec == P64 ? P64 : P32, lat->Vh);
-    const size_t need[W_SYS_COUNT] = {2 * d, 2 * d, d, d, d, d, d, d, d, d, d, i, i, i, i, i, i, x};
+                 x = spinor_bytes(iprec == P64 ? P64 : P32, lat->Vh), ip = pipe ? i : 0;
+    const size_t need[W_SYS_COUNT] = {2 * d, 2 * d, d, d, d, d, d, d, d, d, d, i, i, i, i, i, i, x, ip, ip, ip, ip};
     for (int k = 0; k < W_SYS_COUNT; k++) {
+        if (need[k] == 0) continue;  // not used by this solve
         void *before = w.buf[k];
         if (int rc = buf_get(&w.buf[k], &w.bytes[k], need[k], lat->stream)) return rc;
         if (w.buf[k] != before) arena_drop_graphs(arena);
@@ -314,6 +315,7 @@ extern "C" void wc_solve_params_default(wc_solve_params *p) {
     p->adjoint = 0;
     p->use_graph = 1;
     p->outer = WC_OUTER_BICGSTAB;
+    p->inner_method = WC_INNER_BICGSTAB;
 }
 
 static int check_params(const wc_solve_params &P, double tol) {
@@ -323,6 +325,8 @@ static int check_params(const wc_solve_params &P, double tol) {
         P.inner_tol >= 1.0)
         return wc_fail(WC_EINVAL, "bad solver parameters");
     if (P.outer != WC_OUTER_BICGSTAB && P.outer != WC_OUTER_DC) return wc_fail(WC_EINVAL, "bad outer method");
+    if (P.inner_method != WC_INNER_BICGSTAB && P.inner_method != WC_INNER_PIPELINED)
+        return wc_fail(WC_EINVAL, "bad inner method");
     return WC_OK;
 }
 
@@ -355,7 +359,7 @@ extern "C" int wc_solve(wc_lattice *lat, const void *b_dev, double kappa, double
     if (pin) P = *pin;
     if (int rc = check_params(P, tol)) return rc;
     if (int rc = prepare_lattice(lat, kappa, csw)) return rc;
-    if (int rc = ensure_work(lat, lat->swork, P.inner_prec, lat->arena)) return rc;
+    if (int rc = ensure_work(lat, lat->swork, P.inner_prec, P.inner_method == WC_INNER_PIPELINED, lat->arena)) return rc;
     std::vector<SolveSys> sys(1);
     sys[0].lat = lat;
     sys[0].st = &lat->sys;
@@ -419,7 +423,7 @@ extern "C" int wc_solve_multi(int n, wc_lattice *const *lats, const void *const 
     }
     std::vector<SolveSys> sys(n);
     for (int k = 0; k < n; k++) {
-        if (int rc = ensure_work(lats[k], bc->work[k], P.inner_prec, bc->arena)) {
+        if (int rc = ensure_work(lats[k], bc->work[k], P.inner_prec, P.inner_method == WC_INNER_PIPELINED, bc->arena)) {
             restore();
             return rc;
         }

@@ -24,6 +24,9 @@ enum ScalarSlot {
     S_RR = 6,      // ||r||^2
     S_RHO0 = 7,    // rho, slot 0        (complex)
     S_RHO1 = 9,    // rho, slot 1        (complex)
+    // the pipelined inner loop keeps its coefficients in fixed slots:
+    //   alpha in S_RQ, omega in S_ST, beta in S_RHO1, rho = <r~, r> in S_RHO0,
+    //   <r~, s> and <r~, z> in S_AUX and S_AUX + 2, ||q||^2 in S_SS, ||y||^2 in S_TT
     S_NORM = 11,   // ||p||^2 of the inner call's source (Algorithm 2, first step)
     S_AUX = 12,    // scratch norms (4 doubles)
     S_TOL2 = 16,   // squared relative tolerance of the running inner loop
@@ -110,6 +113,7 @@ enum WorkId {
     W_BHAT,   // b-hat_e
     W_R, W_RT, W_P, W_V, W_Q, W_T, W_TMP64, W_RES,   // single parity
     W_IR, W_IRT, W_IP, W_IQ, W_IT, W_ITMP, W_IX,     // inner precision
+    W_IW, W_IS, W_IZ, W_IV,                          // inner precision, pipelined loop only
     W_SYS_COUNT
 };
 
@@ -215,7 +219,10 @@ enum FinOp {
     FIN_INIT,        // rho0 = (sum, 0); reset the level's done flag and iteration count
     FIN_INNER_A,     // ||s||^2; done = HALF below tol2, BREAK on a non-finite alpha or sum
     FIN_INNER_B,     // ||r||^2, rho1 = <r~, r>, iterations = iter + 1; done = FULL / BREAK
-    FIN_OUTER_B      // ||r||^2, rho1 = <r~, r>
+    FIN_OUTER_B,     // ||r||^2, rho1 = <r~, r>
+    FIN_PIPE_INIT,   // alpha = rho / <r~, w>, beta = 0, omega = 1 (no partials)
+    FIN_PIPE_A,      // omega = <y, q> / ||y||^2; <r~, s>, <r~, z>; done = HALF on ||q||^2 < tol2
+    FIN_PIPE_B       // rho, beta, next alpha, ||r||^2; iterations + 1; done = FULL / BREAK
 };
 // second stage of one system's reduction: sums `blocks` partials per value in
 // block order, then applies `op` in one thread
@@ -281,12 +288,17 @@ enum VecOp {
     V_OUTER_B,      // a: x, b: r, c: v, d: t, e: r~      x += omega v, r -= omega t
     V_GAMMA5,       // a: FP64 two-parity field, in place
     V_COPY,         // a = b (FP64 single parity)
-    V_ZERO          // a = 0 (FP64 single parity)
+    V_ZERO,         // a = 0 (FP64 single parity)
+    // pipelined BiCGStab (the inner-solver variant with two reduction phases)
+    V_PIPE_INIT,    // a: src (FP64), b: r, c: r~, d: x, e: p, f: s, g: z, h: v   (set-up)
+    V_PIPE_A,       // a: r, b: w, c: t, d: p, e: s, f: z, g: v, h: r~      (p, s, z updates)
+    V_PIPE_B,       // a: x, b: p, c: r, d: s, e: w, f: z, g: t, h: v, j: r~ (x, r, w updates)
+    V_PIPE_FIX      // a: x, b: p                         x += alpha p (alpha from its slot)
 };
 
 struct VecCall {
     int Vh;
-    void *a, *b, *c, *d, *e;
+    void *a, *b, *c, *d, *e, *f, *g, *h, *j;
     double *sc;        // scalar block of the system's level
     int *fl;           // flag block of the system's level
     double *partials;

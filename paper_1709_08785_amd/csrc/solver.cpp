@@ -37,6 +37,7 @@ struct Run {
     wc_lattice *tl;     // receives timing records
     Arena *arena;
     bool use_graph;
+    bool pipe;          // pipelined inner loop (two reduction phases per iteration)
     int iprec;
     double itol;
     int imaxit, omaxit, fixed_work, check_every;
@@ -127,6 +128,59 @@ int dhat(Run &R, const std::vector<int> &act, int prec, int out_id, int in_id, i
     });
 }
 
+VecCall vc9(Run &R, int k, int lvl, void *a, void *b, void *c, void *d, void *e, void *f, void *g, void *h,
+            void *j = nullptr) {
+    VecCall v = vc(R, k, lvl, a, b, c, d, e);
+    v.f = f;
+    v.g = g;
+    v.h = h;
+    v.j = j;
+    return v;
+}
+
+// One chunk of n iterations of the pipelined BiCGStab (Cools and Vanroose,
+// Parallel Computing 65, 2017) on D-hat_ee: the same Krylov iterates as
+// Algorithm 2, with the recurrences rearranged so that each iteration has two
+// reduction phases instead of four.  It keeps s = A p, z = A s, w = A r,
+// t = A w and v = A z as vectors and updates them by recurrence, at the cost
+// of more vector traffic.  Per iteration:
+//   phase 0: p, s, z updates with the sums <y, q>, ||y||^2, ||q||^2, <r~, s>,
+//            <r~, z> (q = r - alpha s, y = w - alpha z) -> omega, half-step check
+//   phase 1: v = A z; x, r, w updates with <r~, r>, <r~, w>, ||r||^2 -> beta,
+//            the next alpha, full-step check
+//   phase 2: t = A w
+int inner_chunk_pipe(Run &R, const std::vector<int> &act, int n, int base = 0) {
+    const int L = 0, P = R.iprec;
+    auto loop = [&](VecCall v) {
+        v.iter_dev = 1;
+        v.guard = 1;
+        return v;
+    };
+    auto tag = [&](int it, int ph) {
+        R.tl->tag_iter = it;
+        R.tl->tag_phase = ph;
+    };
+    for (int j = 0; j < n; j++) {
+        tag(base + j, 0);
+        if (int rc = vec_over(R, act, V_PIPE_A, P, [&](int k) {
+                return loop(vc9(R, k, L, W(R, k, W_IR), W(R, k, W_IW), W(R, k, W_IT), W(R, k, W_IP), W(R, k, W_IS),
+                                W(R, k, W_IZ), W(R, k, W_IV), W(R, k, W_IRT)));
+            }))
+            return rc;
+        tag(base + j, 1);
+        if (int rc = dhat(R, act, P, W_IV, W_IZ, W_ITMP, R_NONE, -1, L, 0, true)) return rc;
+        if (int rc = vec_over(R, act, V_PIPE_B, P, [&](int k) {
+                return loop(vc9(R, k, L, W(R, k, W_IX), W(R, k, W_IP), W(R, k, W_IR), W(R, k, W_IS), W(R, k, W_IW),
+                                W(R, k, W_IZ), W(R, k, W_IT), W(R, k, W_IV), W(R, k, W_IRT)));
+            }))
+            return rc;
+        tag(base + j, 2);
+        if (int rc = dhat(R, act, P, W_IT, W_IW, W_ITMP, R_NONE, -1, L, 0, true)) return rc;
+    }
+    tag(-1, 0);
+    return WC_OK;
+}
+
 // one chunk of n iterations of Algorithm 2 for the systems in act; every
 // kernel takes the iteration index from the system's device flags, so the
 // same launches serve any chunk (and can be recorded once as a graph)
@@ -172,6 +226,7 @@ int inner_chunk_graph(Run &R, const std::vector<int> &act, int n) {
     auto mix = [&](unsigned long long v) { key = (key ^ v) * 1099511628211ull; };
     mix((unsigned long long)R.iprec);
     mix((unsigned long long)n);
+    mix((unsigned long long)R.pipe);
     for (int k : act) {
         mix((unsigned long long)k);
         mix((unsigned long long)(uintptr_t)S_(R, k).lat);
@@ -187,7 +242,7 @@ int inner_chunk_graph(Run &R, const std::vector<int> &act, int n) {
         const std::vector<long> saved = R.dslash;
         R.stream = lead->capture_stream;
         WC_HIP(hipStreamBeginCapture(R.stream, hipStreamCaptureModeThreadLocal));
-        const int rc = inner_chunk(R, act, n);
+        const int rc = R.pipe ? inner_chunk_pipe(R, act, n) : inner_chunk(R, act, n);
         hipGraph_t graph = nullptr;
         const hipError_t e = hipStreamEndCapture(R.stream, &graph);
         R.stream = user;
@@ -219,10 +274,31 @@ int inner_solve(Run &R, const std::vector<int> &act, int src_id, int v_id) {
             return v;
         }))
         return rc;
-    if (int rc = vec_over(R, act, V_INNER_INIT, P, [&](int k) {
-            return vc(R, k, L, W(R, k, src_id), W(R, k, W_IR), W(R, k, W_IRT), W(R, k, W_IP), W(R, k, W_IX));
-        }))
+    if (R.pipe) {
+        // r = r~ = b, x = 0; w = A r with <r~, w>; t = A w; alpha_0 = <r~, r> / <r~, w>
+        if (int rc = vec_over(R, act, V_PIPE_INIT, P, [&](int k) {
+                return vc9(R, k, L, W(R, k, src_id), W(R, k, W_IR), W(R, k, W_IRT), W(R, k, W_IX), W(R, k, W_IP),
+                           W(R, k, W_IS), W(R, k, W_IZ), W(R, k, W_IV));
+            }))
+            return rc;
+        if (int rc = dhat(R, act, P, W_IW, W_IR, W_ITMP, R_DOT, W_IRT, L, S_RQ, true)) return rc;
+        if (int rc = dhat(R, act, P, W_IT, W_IW, W_ITMP, R_NONE, -1, L, 0, true)) return rc;
+        FinArgs f[kMaxSys];
+        int nf = 0;
+        for (int k : act) {
+            FinArgs a = FinArgs{};
+            a.op = FIN_PIPE_INIT;
+            a.sc = S_(R, k).st->sc(L);
+            a.fl = S_(R, k).st->fl(L);
+            a.guard = a.fl;
+            f[nf++] = a;
+        }
+        if (int rc = launch_fin_batch(R.stream, f, nf, 1)) return rc;
+    } else if (int rc = vec_over(R, act, V_INNER_INIT, P, [&](int k) {
+                   return vc(R, k, L, W(R, k, src_id), W(R, k, W_IR), W(R, k, W_IRT), W(R, k, W_IP), W(R, k, W_IX));
+               })) {
         return rc;
+    }
     const int maxit = R.fixed_work > 0 ? R.fixed_work : R.imaxit;
     const bool graph = R.use_graph && !R.tl->timing;
     const size_t timed_from = R.tl->launches.size();
@@ -230,7 +306,10 @@ int inner_solve(Run &R, const std::vector<int> &act, int src_id, int v_id) {
     int queued = 0;
     while (queued < maxit) {
         const int n = std::min(R.check_every, maxit - queued);
-        if (int rc = graph ? inner_chunk_graph(R, act, n) : inner_chunk(R, act, n, queued)) return rc;
+        if (int rc = graph    ? inner_chunk_graph(R, act, n)
+                     : R.pipe ? inner_chunk_pipe(R, act, n, queued)
+                              : inner_chunk(R, act, n, queued))
+            return rc;
         queued += n;
         if (int rc = sync(R)) return rc;
         bool all = true;
@@ -264,10 +343,13 @@ int inner_solve(Run &R, const std::vector<int> &act, int src_id, int v_id) {
         // launches queued after the stop returned at once)
         const int stopph = s.st->hf(L, F_STOPPH);
         const long full = s.st->hf(L, F_ITERS);
-        R.dslash[k] = dslash_before[k] + 4 * full + ((code != DONE_NO && stopph == 1) ? 2 : 0);
+        // the pipelined loop also applies D-hat twice to set up, and its
+        // half-step check comes before that iteration's D-hat
+        R.dslash[k] = dslash_before[k] + 4 * full +
+                      (R.pipe ? 4 : ((code != DONE_NO && stopph == 1) ? 2 : 0));
     }
     if (!fix.empty())
-        if (int rc = vec_over(R, fix, V_INNER_FIX, P, [&](int k) {
+        if (int rc = vec_over(R, fix, R.pipe ? V_PIPE_FIX : V_INNER_FIX, P, [&](int k) {
                 VecCall v = vc(R, k, L, W(R, k, W_IX), W(R, k, W_IP));
                 v.iter = S_(R, k).st->hf(L, F_ITERS);
                 return v;
@@ -524,6 +606,7 @@ int solve_systems(std::vector<SolveSys> &sys, Arena &arena, double tol, const wc
     R.tl = sys[0].lat;
     R.arena = &arena;
     R.use_graph = P.use_graph != 0;
+    R.pipe = P.inner_method == WC_INNER_PIPELINED;
     R.iprec = P.inner_prec;
     R.itol = P.inner_tol > 0.0 ? P.inner_tol : (P.inner_prec == WC_FP16 ? 1e-3 : 1e-6);
     R.imaxit = P.inner_maxit;
