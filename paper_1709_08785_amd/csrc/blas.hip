@@ -38,6 +38,8 @@ __host__ __device__ constexpr int red_count(int op) {
          : 0;
 }
 
+static_assert(red_count(V_PIPE_A) <= kMaxRed && red_count(V_PIPE_B) <= kMaxRed, "partials too small");
+
 // a += conj(x) y as (re, im) into two accumulators
 template <class T> __device__ __forceinline__ void dot_acc(double &re, double &im, cx<T> x, cx<T> y) {
     const double xr = x.re, xi = x.im, yr = y.re, yi = y.im;

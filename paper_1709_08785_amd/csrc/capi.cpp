@@ -278,7 +278,7 @@ extern "C" int wc_create_lattice(const int dims[4], void *stream, wc_lattice **o
     int rc = arena_alloc(lat->arena, 1, lat->stream);
     if (!rc) {
         arena_bind(lat->arena, 0, lat->sys);
-        rc = dev_alloc((void **)&lat->sys.partials, sizeof(double) * 8 * (size_t)lat->nblocks);
+        rc = dev_alloc((void **)&lat->sys.partials, sizeof(double) * kMaxRed * (size_t)lat->nblocks);
     }
     if (!rc && hipStreamSynchronize(lat->stream) != hipSuccess)
         rc = wc_fail(WC_EHIP, std::string("initialising lattice scratch: ") + hipGetErrorString(hipGetLastError()));
@@ -415,7 +415,7 @@ extern "C" int wc_solve_multi(int n, wc_lattice *const *lats, const void *const 
         for (int k = 0; k < n; k++) {
             arena_bind(bc->arena, k, bc->sys[k]);
             if (int rc = buf_get((void **)&bc->sys[k].partials, &bc->sys[k].partials_bytes,
-                                 sizeof(double) * 8 * (size_t)lats[k]->nblocks, lead->stream)) {
+                                 sizeof(double) * kMaxRed * (size_t)lats[k]->nblocks, lead->stream)) {
                 restore();
                 return rc;
             }

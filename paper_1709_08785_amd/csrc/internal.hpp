@@ -40,6 +40,7 @@ enum DoneCode { DONE_NO = 0, DONE_FULL = 1, DONE_HALF = 2, DONE_BREAK = 4 };
 
 enum { NUM_LEVELS = 2 };  // 0 = inner loop, 1 = outer / FP64 loop
 constexpr int kMaxSys = 16;  // systems per batched launch
+constexpr int kMaxRed = 8;   // values one fused reduction may carry (partials are sized for it)
 constexpr float kRecon8MinN = 1e-6f;  // smallest |U01|^2 + |U02|^2 reconstruct-8 accepts
 
 // kinds of timed kernel launches
