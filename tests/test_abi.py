@@ -46,6 +46,12 @@ def test_create_rejects_bad_extents_before_gpu(lib):
         assert rc == -1 and not h.value
         assert b"even" in lib.wc_last_error()
     assert lib.wc_create_lattice(None, None, None) == -1
+    # the largest accepted lattice has V/2 = 2^30 sites per parity; one more
+    # doubling is refused before anything is allocated
+    h = ctypes.c_void_p()
+    rc = lib.wc_create_lattice((ctypes.c_int * 4)(2048, 2048, 1024, 2), None, ctypes.byref(h))
+    assert rc == -1 and not h.value
+    assert b"too large" in lib.wc_last_error()
 
 
 def test_null_handles_rejected(lib):
