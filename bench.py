@@ -280,10 +280,12 @@ def batch_mode(args):
 
 
 def inner_mode(args):
-    """Algorithm 2 against the pipelined inner BiCGStab (two reduction phases per
-    iteration instead of four, more vector traffic) from the launch-bound 8^4 to
-    the bandwidth-bound 32^3x64: FP32 inner, Algorithm 1 outer, kappa 0.13,
-    c_SW 1.0, Gaussian source, tol on the true residual; chunk graphs on."""
+    """Algorithm 2 (launched loop with chunk graphs) against the pipelined inner
+    BiCGStab (two reduction phases per iteration instead of four, more vector
+    traffic) and against the one-launch loop (a cooperative kernel, where the
+    lattice fits), from the launch-bound 8^4 to the bandwidth-bound 32^3x64:
+    FP32 inner, Algorithm 1 outer, kappa 0.13, c_SW 1.0, Gaussian source, tol
+    on the true residual."""
     import torch
 
     import paper_1709_08785_amd as wc
@@ -298,21 +300,24 @@ def inner_mode(args):
         lat.build_clover(kappa, csw)
         b = torch.from_numpy(synth.gaussian_source(d, 2100 + i)).to(dev)
         row = {}
-        for name in ("bicgstab", "pipelined"):
-            lat.solve(b, kappa, csw, args.tol, inner_method=name)
+        for name in ("bicgstab", "pipelined", "persistent"):
+            kw = {"persistent": 1} if name == "persistent" else {"inner_method": name}
+            lat.solve(b, kappa, csw, args.tol, **kw)
             reps = 20 if d[0] <= 16 else 3
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             for r in range(reps):
-                x, info = lat.solve(b, kappa, csw, args.tol, inner_method=name)
+                x, info = lat.solve(b, kappa, csw, args.tol, **kw)
             torch.cuda.synchronize()
             el = (time.perf_counter() - t0) / reps
             row[name] = {"ms": round(el * 1e3, 3), "inner_iters": info["inner_iters_total"],
                          "inner_calls": info["inner_calls"], "outer_iters": info["outer_iters"],
                          "us_per_inner_iter": round(el * 1e6 / info["inner_iters_total"], 2),
-                         "true_rel_residual": info["true_rel_residual"]}
+                         "true_rel_residual": info["true_rel_residual"],
+                         "one_launch_inner_calls": info["persistent_calls"]}
             log("inner %s %s %s" % ("x".join(map(str, d)), name, json.dumps(row[name])))
         row["pipelined_speedup"] = round(row["bicgstab"]["ms"] / row["pipelined"]["ms"], 3)
+        row["persistent_speedup"] = round(row["bicgstab"]["ms"] / row["persistent"]["ms"], 3)
         rows["x".join(map(str, d))] = row
         lat.close()
     print(json.dumps({"mode": "inner", "kappa": kappa, "csw": csw, "tol": args.tol, "inner": "fp32",

@@ -94,6 +94,12 @@ typedef struct {
                              with two reduction phases per iteration instead of four and
                              about 9 more vector passes; it also needs 4 more inner-precision
                              work vectors per system */
+    int persistent;       /* != 0: a single-system solve runs each inner loop (Algorithm 2) as one
+                             cooperative launch with grid-wide barriers between its phases, when
+                             every workgroup of the lattice fits on the device at once (small
+                             lattices: launch overhead dominates there); otherwise, for batches,
+                             the pipelined loop or kernel timing, the launched loop runs.
+                             Default 0. */
 } wc_solve_params;
 
 enum wc_outer { WC_OUTER_BICGSTAB = 0, WC_OUTER_DC = 1 };
@@ -110,6 +116,7 @@ typedef struct {
     double eo_rel_residual;   /* last recursive ||r_e|| / ||b-hat_e|| of the outer loop */
     double true_rel_residual; /* ||b - D x|| / ||b|| in FP64 on the full lattice */
     double seconds;           /* wall time of the solve (host clock, after the final sync) */
+    int persistent_calls;     /* inner calls that ran as one cooperative launch (persistent) */
 } wc_solve_info;
 
 void wc_solve_params_default(wc_solve_params *p);

@@ -40,7 +40,7 @@ class SolveParams(ctypes.Structure):
     _fields_ = [("inner_prec", ctypes.c_int), ("inner_tol", ctypes.c_double), ("inner_maxit", ctypes.c_int),
                 ("outer_maxit", ctypes.c_int), ("fixed_work", ctypes.c_int), ("check_every", ctypes.c_int),
                 ("adjoint", ctypes.c_int), ("use_graph", ctypes.c_int), ("outer", ctypes.c_int),
-                ("inner_method", ctypes.c_int)]
+                ("inner_method", ctypes.c_int), ("persistent", ctypes.c_int)]
 
 
 OUTER = {"bicgstab": 0, "dc": 1}
@@ -51,7 +51,7 @@ class SolveInfo(ctypes.Structure):
     _fields_ = [("outer_iters", ctypes.c_int), ("inner_iters_total", ctypes.c_int), ("inner_calls", ctypes.c_int),
                 ("restarts", ctypes.c_int), ("dslash_count", ctypes.c_long), ("status", ctypes.c_int),
                 ("eo_rel_residual", ctypes.c_double), ("true_rel_residual", ctypes.c_double),
-                ("seconds", ctypes.c_double)]
+                ("seconds", ctypes.c_double), ("persistent_calls", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

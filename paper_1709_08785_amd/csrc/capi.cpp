@@ -242,6 +242,7 @@ static void free_all(wc_lattice *lat) {
         if (lat->lwork[k]) (void)hipFree(lat->lwork[k]);
     free_work(lat->swork);
     if (lat->sys.partials) (void)hipFree(lat->sys.partials);
+    if (lat->sys.partials2) (void)hipFree(lat->sys.partials2);
     arena_free(lat->arena);
     free_batch(lat->batch);
     lat->batch = nullptr;
@@ -279,6 +280,7 @@ extern "C" int wc_create_lattice(const int dims[4], void *stream, wc_lattice **o
     if (!rc) {
         arena_bind(lat->arena, 0, lat->sys);
         rc = dev_alloc((void **)&lat->sys.partials, sizeof(double) * kMaxRed * (size_t)lat->nblocks);
+        if (!rc) rc = dev_alloc((void **)&lat->sys.partials2, sizeof(double) * kMaxRed * (size_t)lat->nblocks);
     }
     if (!rc && hipStreamSynchronize(lat->stream) != hipSuccess)
         rc = wc_fail(WC_EHIP, std::string("initialising lattice scratch: ") + hipGetErrorString(hipGetLastError()));
@@ -316,6 +318,7 @@ extern "C" void wc_solve_params_default(wc_solve_params *p) {
     p->use_graph = 1;
     p->outer = WC_OUTER_BICGSTAB;
     p->inner_method = WC_INNER_BICGSTAB;
+    p->persistent = 0;
 }
 
 static int check_params(const wc_solve_params &P, double tol) {

@@ -17,6 +17,8 @@
 // L2.  The block index is remapped so that XCD k sweeps one contiguous slab of
 // the lattice: the y, z and t neighbours a block needs were then loaded by
 // blocks of the same XCD shortly before, and hit in that XCD's L2.
+#include <hip/hip_cooperative_groups.h>
+
 #include "reduce.hpp"
 
 namespace {
@@ -277,6 +279,275 @@ double mult_operator_bytes(int prec, int mode, bool r8, int Vh) {
     return b;
 }
 
+
+// ---------------------------------------------------------------------------
+// The whole inner loop (Algorithm 2) in one cooperative launch, for lattices
+// small enough that every workgroup is resident at once.  Each phase of an
+// iteration ends in a grid-wide barrier instead of a kernel boundary; every
+// block then sums the reduction partials itself, in the same order as the
+// finalize kernel of the launched path, so all blocks take the same
+// decisions and leave the loop together.  The per-site arithmetic is that of
+// the stencil and vector kernels, and the scalars and flags are left exactly
+// as the launched path leaves them, so the host finishes the call the same
+// way.  Partials alternate between two buffers: a buffer is written again
+// only after a barrier that follows its last read.
+// ---------------------------------------------------------------------------
+struct PersistArgs {
+    Geom g;
+    const char *links;
+    size_t link_slab;
+    const void *clov_e, *clov_o;  // F_ee^-1, F_oo^-1
+    void *r, *rt, *p, *q, *t, *tmp, *x;
+    double *part[2];              // [kMaxRed][nblk] each
+    double *sc;
+    int *fl;
+    double kappa2;
+    int maxit;
+    int nblk;
+};
+
+__device__ __forceinline__ int rho_slot_p(int iter) { return (iter & 1) ? S_RHO1 : S_RHO0; }
+
+// every block: the N sums of the partials, in the finalize kernel's order
+template <int N> __device__ __forceinline__ void sum_partials(const double *part, int nblk, double (&out)[N]) {
+    __shared__ double sh[N][kWaves];
+    __shared__ double tot[N];
+    double a[N];
+#pragma unroll
+    for (int k = 0; k < N; k++) a[k] = 0.0;
+    for (int j = threadIdx.x; j < nblk; j += kBlock) {
+#pragma unroll
+        for (int k = 0; k < N; k++) a[k] += part[(size_t)k * nblk + j];
+    }
+    block_fold<N>(a, sh);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < N; k++) tot[k] = a[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < N; k++) out[k] = tot[k];
+    __syncthreads();
+}
+
+// out = F^-1 H in (one parity), the MULT of the launched path.  Kept out of
+// line: inlined four times into the loop it drove the kernel to 256 VGPRs
+// with spills, while as a call each instance gets its own allocation.
+template <int P, bool R8>
+__device__ __noinline__ Spinor<typename Real<P>::T> mult_site(const PersistArgs &A, const void *in, int out_par,
+                                                                  const void *clov, int i) {
+    using R = typename Real<P>::T;
+    MultKArgs a;
+    a.g = A.g;
+    a.out_par = out_par;
+    a.in = in;
+    a.links = A.links;
+    a.link_slab = A.link_slab;
+    Spinor<R> acc, out;
+#pragma unroll
+    for (int k = 0; k < 12; k++) acc.c[k] = {R(0), R(0)};
+    const SiteCoord c = eo_coords(A.g, i, out_par);
+    hop_dir<P, 0, false, R8>(a, c, i, acc);
+    hop_dir<P, 1, false, R8>(a, c, i, acc);
+    hop_dir<P, 2, false, R8>(a, c, i, acc);
+    hop_dir<P, 3, false, R8>(a, c, i, acc);
+    clover_apply<P, R, false>(clov, A.g.Vh, i, acc, out);
+    return out;
+}
+
+template <class R> __device__ __forceinline__ cx<R> to_r(cx<double> a) { return {(R)a.re, (R)a.im}; }
+
+template <int P, bool R8>
+__global__ __launch_bounds__(kBlock) void k_inner_persistent(PersistArgs A) {
+    using R = typename Real<P>::T;
+    constexpr int XP = P == P64 ? P64 : P32;
+    using RX = typename Real<XP>::T;
+    namespace cg = cooperative_groups;
+    cg::grid_group grid = cg::this_grid();
+    const int Vh = A.g.Vh;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const bool active = i < Vh;
+    const double tol2 = A.sc[S_TOL2];
+    cx<double> rho = ld_c(A.sc, S_RHO0), rq = {0.0, 0.0}, st = {0.0, 0.0};
+    double ss = 0.0, tt = 0.0, rr = 0.0;
+    int it = 0, done = DONE_NO, stopph = 0;
+    for (; it < A.maxit; it++) {
+        // q = D-hat p with <r~, q>   (tmp = F_oo^-1 H_oe p first)
+        if (active) SpinorIO<P>::store(A.tmp, Vh, i, mult_site<P, R8>(A, A.p, 1, A.clov_o, i));
+        grid.sync();
+        {
+            double v[2] = {0.0, 0.0};
+            if (active) {
+                const Spinor<R> h = mult_site<P, R8>(A, A.tmp, 0, A.clov_e, i);
+                const Spinor<R> cen = SpinorIO<P>::load(A.p, Vh, i);
+                const R coef = (R)(-A.kappa2);
+                Spinor<R> out;
+#pragma unroll
+                for (int k = 0; k < 12; k++) out.c[k] = cen.c[k] + coef * h.c[k];
+                SpinorIO<P>::store(A.q, Vh, i, out);
+                const Spinor<R> ax = SpinorIO<P>::load(A.rt, Vh, i);
+#pragma unroll
+                for (int k = 0; k < 12; k++) {
+                    const double ar = ax.c[k].re, ai = ax.c[k].im, orr = out.c[k].re, oi = out.c[k].im;
+                    v[0] += ar * orr + ai * oi;
+                    v[1] += ar * oi - ai * orr;
+                }
+            }
+            block_partials<2>(v, A.part[0], A.nblk, blockIdx.x);
+        }
+        grid.sync();
+        {
+            double sm[2];
+            sum_partials<2>(A.part[0], A.nblk, sm);
+            rq = {sm[0], sm[1]};
+        }
+        // s = r - alpha q (in r) with ||s||^2; the half-step check
+        const cx<double> al = cdiv(rho, rq);
+        {
+            double v[1] = {0.0};
+            if (active) {
+                const cx<R> alpha = to_r<R>(al);
+                Spinor<R> rv = SpinorIO<P>::load(A.r, Vh, i);
+                const Spinor<R> qv = SpinorIO<P>::load(A.q, Vh, i);
+#pragma unroll
+                for (int k = 0; k < 12; k++) rv.c[k] = rv.c[k] - alpha * qv.c[k];
+                SpinorIO<P>::store(A.r, Vh, i, rv);
+#pragma unroll
+                for (int k = 0; k < 12; k++) v[0] += norm2(rv.c[k]);
+            }
+            block_partials<1>(v, A.part[1], A.nblk, blockIdx.x);
+        }
+        grid.sync();
+        {
+            double sm[1];
+            sum_partials<1>(A.part[1], A.nblk, sm);
+            ss = sm[0];
+        }
+        if (!(isfinite(al.re) && isfinite(al.im)) || !isfinite(ss)) {
+            done = DONE_BREAK;
+            stopph = 1;
+            break;
+        }
+        if (ss < tol2) {
+            done = DONE_HALF;
+            stopph = 1;
+            break;
+        }
+        // t = D-hat s with <s, t>, ||t||^2
+        if (active) SpinorIO<P>::store(A.tmp, Vh, i, mult_site<P, R8>(A, A.r, 1, A.clov_o, i));
+        grid.sync();
+        {
+            double v[3] = {0.0, 0.0, 0.0};
+            if (active) {
+                const Spinor<R> h = mult_site<P, R8>(A, A.tmp, 0, A.clov_e, i);
+                const Spinor<R> cen = SpinorIO<P>::load(A.r, Vh, i);
+                const R coef = (R)(-A.kappa2);
+                Spinor<R> out;
+#pragma unroll
+                for (int k = 0; k < 12; k++) out.c[k] = cen.c[k] + coef * h.c[k];
+                SpinorIO<P>::store(A.t, Vh, i, out);
+#pragma unroll
+                for (int k = 0; k < 12; k++) {
+                    const double ar = cen.c[k].re, ai = cen.c[k].im, orr = out.c[k].re, oi = out.c[k].im;
+                    v[0] += ar * orr + ai * oi;
+                    v[1] += ar * oi - ai * orr;
+                    v[2] += orr * orr + oi * oi;
+                }
+            }
+            block_partials<3>(v, A.part[0], A.nblk, blockIdx.x);
+        }
+        grid.sync();
+        {
+            double sm[3];
+            sum_partials<3>(A.part[0], A.nblk, sm);
+            st = {sm[0], sm[1]};
+            tt = sm[2];
+        }
+        // x += alpha p + omega s; r = s - omega t with ||r||^2, <r~, r>
+        const cx<double> om = {st.re / tt, -st.im / tt};
+        double v3[3] = {0.0, 0.0, 0.0};
+        if (active) {
+            const cx<RX> alx = to_r<RX>(al), omx = to_r<RX>(om);
+            const cx<R> omega = to_r<R>(om);
+            Spinor<R> sv = SpinorIO<P>::load(A.r, Vh, i);
+            const Spinor<R> pv = SpinorIO<P>::load(A.p, Vh, i);
+            Spinor<RX> xv = SpinorIO<XP>::load(A.x, Vh, i);
+#pragma unroll
+            for (int k = 0; k < 12; k++) {
+                const cx<RX> pk = {(RX)pv.c[k].re, (RX)pv.c[k].im}, sk = {(RX)sv.c[k].re, (RX)sv.c[k].im};
+                xv.c[k] = xv.c[k] + alx * pk + omx * sk;
+            }
+            SpinorIO<XP>::store(A.x, Vh, i, xv);
+            const Spinor<R> tv = SpinorIO<P>::load(A.t, Vh, i);
+#pragma unroll
+            for (int k = 0; k < 12; k++) sv.c[k] = sv.c[k] - omega * tv.c[k];
+            SpinorIO<P>::store(A.r, Vh, i, sv);
+            const Spinor<R> rtv = SpinorIO<P>::load(A.rt, Vh, i);
+#pragma unroll
+            for (int k = 0; k < 12; k++) {
+                v3[0] += norm2(sv.c[k]);
+                const double ar = rtv.c[k].re, ai = rtv.c[k].im, br = sv.c[k].re, bi = sv.c[k].im;
+                v3[1] += ar * br + ai * bi;
+                v3[2] += ar * bi - ai * br;
+            }
+        }
+        block_partials<3>(v3, A.part[1], A.nblk, blockIdx.x);
+        grid.sync();
+        cx<double> rho1;
+        {
+            double sm[3];
+            sum_partials<3>(A.part[1], A.nblk, sm);
+            rr = sm[0];
+            rho1 = {sm[1], sm[2]};
+        }
+        const bool bad = !(tt > 0.0) || !(isfinite(om.re) && isfinite(om.im)) || !isfinite(rr) ||
+                         (rho1.re == 0.0 && rho1.im == 0.0);
+        if (bad || rr < tol2) {
+            done = (rr < tol2) ? DONE_FULL : DONE_BREAK;
+            stopph = 2;
+            // the scalars of a full step, as the launched path leaves them
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                const int nxt = rho_slot_p(it + 1);
+                A.sc[nxt] = rho1.re;
+                A.sc[nxt + 1] = rho1.im;
+            }
+            it++;
+            break;
+        }
+        // p = r + beta (p - omega q)
+        if (active) {
+            const cx<R> beta = to_r<R>(cdiv(rho1, rho) * cdiv(al, om)), omega = to_r<R>(om);
+            Spinor<R> pv = SpinorIO<P>::load(A.p, Vh, i);
+            const Spinor<R> rv = SpinorIO<P>::load(A.r, Vh, i);
+            const Spinor<R> qv = SpinorIO<P>::load(A.q, Vh, i);
+#pragma unroll
+            for (int k = 0; k < 12; k++) pv.c[k] = rv.c[k] + beta * (pv.c[k] - omega * qv.c[k]);
+            SpinorIO<P>::store(A.p, Vh, i, pv);
+        }
+        rho = rho1;
+        grid.sync();
+    }
+    // leave the scalars and flags as the launched path would
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        double *sc = A.sc;
+        if (stopph != 2) {
+            const int cur = rho_slot_p(it);
+            sc[cur] = rho.re;
+            sc[cur + 1] = rho.im;
+        }
+        sc[S_RQ] = rq.re;
+        sc[S_RQ + 1] = rq.im;
+        sc[S_SS] = ss;
+        sc[S_ST] = st.re;
+        sc[S_ST + 1] = st.im;
+        sc[S_TT] = tt;
+        sc[S_RR] = rr;
+        A.fl[F_DONE] = done;
+        A.fl[F_ITERS] = it;
+        A.fl[F_STOPPH] = stopph;
+    }
+}
+
 }  // namespace
 
 int launch_mult_batch(hipStream_t s, const MultCall *calls, int n, wc_lattice *timing_lat) {
@@ -363,5 +634,54 @@ int launch_mult_batch(hipStream_t s, const MultCall *calls, int n, wc_lattice *t
         }
         return launch_fin_batch(s, f, n, c0.red == R_DOT ? 2 : 3);
     }
+    return WC_OK;
+}
+
+// The inner loop as one cooperative launch; *ran = false (and WC_OK) when the
+// lattice is too large for all its workgroups to be resident at once, so the
+// caller uses the launched loop instead.
+int launch_inner_persistent(const PersistCall &c, hipStream_t s, bool *ran) {
+    *ran = false;
+    wc_lattice *lat = c.lat;
+    const bool r8 = c.prec == P32 && lat->recon == 8;
+    PersistArgs A;
+    A.g = lat->g;
+    A.links = (const char *)(r8 ? lat->links8 : lat->links[c.prec]);
+    A.link_slab = r8 ? link8_slab_bytes(lat->Vh) : link_slab_bytes(c.prec, lat->Vh);
+    const char *ci = (const char *)lat->clovinv[c.prec];
+    A.clov_e = ci;
+    A.clov_o = ci + clover_slab_bytes(c.prec, lat->Vh);
+    A.r = c.r;
+    A.rt = c.rt;
+    A.p = c.p;
+    A.q = c.q;
+    A.t = c.t;
+    A.tmp = c.tmp;
+    A.x = c.x;
+    A.part[0] = c.part0;
+    A.part[1] = c.part1;
+    A.sc = c.sc;
+    A.fl = c.fl;
+    A.kappa2 = lat->kappa * lat->kappa;
+    A.maxit = c.maxit;
+    A.nblk = lat->nblocks;
+    const void *fn = c.prec == P64   ? (const void *)k_inner_persistent<P64, false>
+                     : c.prec == P16 ? (const void *)k_inner_persistent<P16, false>
+                     : r8            ? (const void *)k_inner_persistent<P32, true>
+                                     : (const void *)k_inner_persistent<P32, false>;
+    int dev = 0, cus = 0, per_cu = 0, coop = 0;
+    WC_HIP(hipGetDevice(&dev));
+    WC_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+    WC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    WC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, 0));
+    if (!coop || (long)per_cu * cus < A.nblk) return WC_OK;
+    void *args[] = {&A};
+    const hipError_t e = hipLaunchCooperativeKernel(fn, dim3(A.nblk), dim3(kBlock), args, 0, s);
+    if (e == hipErrorCooperativeLaunchTooLarge) {
+        (void)hipGetLastError();  // not resident all at once after all: use the launched loop
+        return WC_OK;
+    }
+    if (e != hipSuccess) return wc_fail(WC_EHIP, std::string("cooperative launch: ") + hipGetErrorString(e));
+    *ran = true;
     return WC_OK;
 }

@@ -81,6 +81,7 @@ struct SysState {
     int *flags = nullptr;          // [NUM_LEVELS][F_COUNT]
     double *partials = nullptr;    // [8][blocks of the system's lattice]
     size_t partials_bytes = 0;
+    double *partials2 = nullptr;   // a second set, for the one-launch inner loop (single-system state only)
     double *h_scalars = nullptr;   // pinned mirror
     int *h_flags = nullptr;
     double *sc(int lvl) const { return scalars + lvl * S_COUNT; }
@@ -271,6 +272,18 @@ inline int launch_mult(wc_lattice *lat, MultCall c) {
     c.lat = lat;
     return launch_mult_batch(lat->stream, &c, 1);
 }
+
+// the inner loop of one system as a single cooperative launch (dslash.hip)
+struct PersistCall {
+    wc_lattice *lat;
+    int prec;
+    void *r, *rt, *p, *q, *t, *tmp, *x;
+    double *part0, *part1;  // two partial buffers of kMaxRed x nblocks doubles
+    double *sc;
+    int *fl;
+    int maxit;
+};
+int launch_inner_persistent(const PersistCall &c, hipStream_t s, bool *ran);
 
 // ---------------------------------------------------------------------------
 // vector kernels (blas.hip), batched the same way; one call per system

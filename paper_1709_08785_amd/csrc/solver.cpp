@@ -38,6 +38,7 @@ struct Run {
     Arena *arena;
     bool use_graph;
     bool pipe;          // pipelined inner loop (two reduction phases per iteration)
+    bool persistent;    // one cooperative launch per inner solve when the lattice allows
     int iprec;
     double itol;
     int imaxit, omaxit, fixed_work, check_every;
@@ -304,6 +305,34 @@ int inner_solve(Run &R, const std::vector<int> &act, int src_id, int v_id) {
     const size_t timed_from = R.tl->launches.size();
     const std::vector<long> dslash_before = R.dslash;
     int queued = 0;
+    // one system of a small lattice: the whole loop as one cooperative launch
+    // (not under kernel timing, whose per-launch records it would bypass)
+    if (R.persistent && !R.pipe && act.size() == 1 && !R.tl->timing && S_(R, act[0]).st->partials2) {
+        const int k = act[0];
+        SolveSys &s = S_(R, k);
+        PersistCall c;
+        c.lat = s.lat;
+        c.prec = P;
+        c.r = W(R, k, W_IR);
+        c.rt = W(R, k, W_IRT);
+        c.p = W(R, k, W_IP);
+        c.q = W(R, k, W_IQ);
+        c.t = W(R, k, W_IT);
+        c.tmp = W(R, k, W_ITMP);
+        c.x = W(R, k, W_IX);
+        c.part0 = s.st->partials;
+        c.part1 = s.st->partials2;
+        c.sc = s.st->sc(L);
+        c.fl = s.st->fl(L);
+        c.maxit = maxit;
+        bool ran = false;
+        if (int rc = launch_inner_persistent(c, R.stream, &ran)) return rc;
+        if (ran) {
+            if (int rc = sync(R)) return rc;
+            queued = maxit;  // the loop below is done
+            s.info.persistent_calls++;
+        }
+    }
     while (queued < maxit) {
         const int n = std::min(R.check_every, maxit - queued);
         if (int rc = graph    ? inner_chunk_graph(R, act, n)
@@ -607,6 +636,7 @@ int solve_systems(std::vector<SolveSys> &sys, Arena &arena, double tol, const wc
     R.arena = &arena;
     R.use_graph = P.use_graph != 0;
     R.pipe = P.inner_method == WC_INNER_PIPELINED;
+    R.persistent = P.persistent != 0;
     R.iprec = P.inner_prec;
     R.itol = P.inner_tol > 0.0 ? P.inner_tol : (P.inner_prec == WC_FP16 ? 1e-3 : 1e-6);
     R.imaxit = P.inner_maxit;
