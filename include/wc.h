@@ -99,7 +99,9 @@ typedef struct {
                              every workgroup of the lattice fits on the device at once (small
                              lattices: launch overhead dominates there); otherwise, for batches,
                              the pipelined loop or kernel timing, the launched loop runs.
-                             Default 0. */
+                             Every wait at a grid barrier is bounded (wc_set_barrier_timeout):
+                             a wait that runs out makes every workgroup leave the loop, and
+                             the solve returns WC_EHIP.  Default 0. */
 } wc_solve_params;
 
 enum wc_outer { WC_OUTER_BICGSTAB = 0, WC_OUTER_DC = 1 };
@@ -120,6 +122,13 @@ typedef struct {
 } wc_solve_info;
 
 void wc_solve_params_default(wc_solve_params *p);
+
+/* Longest time (seconds, > 0 finite, or 0 for "no waiting allowed") a
+   workgroup of the one-launch inner loop (wc_solve_params.persistent) waits
+   at a grid barrier before the call gives up with WC_EHIP.  Process-wide;
+   default 2 s, far above a barrier's microseconds.  Returns WC_EINVAL for a
+   negative or non-finite value. */
+int wc_set_barrier_timeout(double seconds);
 
 /* Create a lattice of extents dims = {Lx, Ly, Lz, Lt}; every extent even and >= 2
    (the even-odd split of Sec. II-B with periodic wrap needs even extents).

@@ -99,6 +99,7 @@ def load_library():
                                 ctypes.POINTER(D), ctypes.POINTER(D)]),
         "wc_reset_kernel_stats": (I, [P]),
         "wc_last_error": (ctypes.c_char_p, []),
+        "wc_set_barrier_timeout": (I, [D]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -313,6 +314,13 @@ class Lattice:
                                             ctypes.byref(by)))
             out[name.value.decode()] = {"launches": n.value, "ms": ms.value, "bytes": by.value}
         return out
+
+
+def set_barrier_timeout(seconds: float):
+    """Longest wait of a workgroup at a grid barrier of the one-launch inner
+    loop (persistent=1) before the solve fails with WC_EHIP; process-wide."""
+    load_library()
+    _check(_lib.wc_set_barrier_timeout(float(seconds)))
 
 
 def solve_multi(lats, bs, kappas, csws, tol: float, raise_on_error: bool = True, **params):

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -195,6 +196,12 @@ static int collect_stats(wc_lattice *lat, SlotStats *st) {
     return WC_OK;
 }
 
+extern "C" int wc_set_barrier_timeout(double seconds) {
+    if (!(seconds >= 0.0) || !std::isfinite(seconds)) return wc_fail(WC_EINVAL, "barrier timeout must be >= 0 and finite");
+    g_barrier_timeout_s = seconds;
+    return WC_OK;
+}
+
 extern "C" int wc_set_timing(wc_lattice *lat, int enable) {
     if (!lat) return wc_fail(WC_EINVAL, "null lattice");
     lat->timing = enable != 0;
@@ -243,6 +250,7 @@ static void free_all(wc_lattice *lat) {
     free_work(lat->swork);
     if (lat->sys.partials) (void)hipFree(lat->sys.partials);
     if (lat->sys.partials2) (void)hipFree(lat->sys.partials2);
+    if (lat->sys.bar) (void)hipFree(lat->sys.bar);
     arena_free(lat->arena);
     free_batch(lat->batch);
     lat->batch = nullptr;
@@ -281,6 +289,10 @@ extern "C" int wc_create_lattice(const int dims[4], void *stream, wc_lattice **o
         arena_bind(lat->arena, 0, lat->sys);
         rc = dev_alloc((void **)&lat->sys.partials, sizeof(double) * kMaxRed * (size_t)lat->nblocks);
         if (!rc) rc = dev_alloc((void **)&lat->sys.partials2, sizeof(double) * kMaxRed * (size_t)lat->nblocks);
+        const size_t bar_bytes = sizeof(unsigned long long) * ((size_t)lat->nblocks + 2);
+        if (!rc) rc = dev_alloc((void **)&lat->sys.bar, bar_bytes);
+        if (!rc && hipMemsetAsync(lat->sys.bar, 0, bar_bytes, lat->stream) != hipSuccess)
+            rc = wc_fail(WC_EHIP, "clearing the grid barrier words");
     }
     if (!rc && hipStreamSynchronize(lat->stream) != hipSuccess)
         rc = wc_fail(WC_EHIP, std::string("initialising lattice scratch: ") + hipGetErrorString(hipGetLastError()));

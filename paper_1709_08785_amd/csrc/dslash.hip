@@ -304,9 +304,90 @@ struct PersistArgs {
     double kappa2;
     int maxit;
     int nblk;
+    unsigned long long *bar;  // the kernel's own barrier words (OWN instances)
+    unsigned long long tag0;  // call number << 32; barrier k of the call has tag tag0 + k
+    unsigned long long epoch; // written to the abort word when a wait runs out
+    long long limit;          // wall-clock ticks a wait may take
 };
 
 __device__ __forceinline__ int rho_slot_p(int iter) { return (iter & 1) ? S_RHO1 : S_RHO0; }
+
+// from this many blocks up the kernel's own barrier beats the runtime's
+constexpr int kOwnBarrierMinBlocks = 16;
+
+__device__ __forceinline__ unsigned long long ld_agent(const unsigned long long *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(unsigned long long *p, unsigned long long v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Grid-wide barrier of the one-launch loop.  The runtime's barrier fences
+// every wave of every block, which costs about 0.13 us per block; here every
+// wave only waits for its own stores to reach L2, and one wave per block
+// writes the L2 back (release) and, on the way out, invalidates the caches
+// (acquire) before its block reads again.  Each block posts its arrival in a
+// word of its own (no contended atomics); one wave of block 0 gathers them
+// and posts the release.  Tags only grow, so no word is ever reset.  Every
+// wait is bounded in wall-clock time: a wait that runs out posts the abort
+// word, every other waiter sees it, and the function returns false in every
+// block, so the kernel always ends.
+template <bool OWN> __device__ __forceinline__ bool grid_barrier(const PersistArgs &A, unsigned long long &tag, int lb) {
+    __shared__ int ok;
+    ++tag;
+    if constexpr (!OWN) {
+        cooperative_groups::this_grid().sync();
+        return true;
+    }
+    unsigned long long *w = A.bar;
+    unsigned long long *rel = w + A.nblk, *abort = w + A.nblk + 1;
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's stores have reached L2
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        st_agent(&w[lb], tag);
+    }
+    const long long t0 = wall_clock64();
+    if (lb == 0 && threadIdx.x < 64) {
+        int all = 0;
+        for (;;) {
+            int mine = 1;
+            for (int j = threadIdx.x; j < A.nblk; j += 64) mine &= ld_agent(&w[j]) >= tag;
+            all = __all(mine);
+            if (all || ld_agent(abort) == A.epoch || wall_clock64() - t0 > A.limit) break;
+            __builtin_amdgcn_s_sleep(1);
+        }
+        if (threadIdx.x == 0) {
+            __threadfence();
+            if (all) st_agent(rel, tag);
+            else st_agent(abort, A.epoch);
+        }
+    }
+    if (threadIdx.x == 0) {
+        int good = 1;
+        while (ld_agent(rel) < tag) {
+            if (ld_agent(abort) == A.epoch || wall_clock64() - t0 > A.limit) {
+                st_agent(abort, A.epoch);
+                good = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __threadfence();
+        ok = good;
+    }
+    __syncthreads();
+    return ok;
+}
+
+// a value every lane holds alike, read from lane 0 so the compiler knows it
+// is uniform (branches on it stay scalar, pointers chosen by it stay in SGPRs)
+__device__ __forceinline__ double uniform(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffff));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 
 // every block: the N sums of the partials, in the finalize kernel's order
 template <int N> __device__ __forceinline__ void sum_partials(const double *part, int nblk, double (&out)[N]) {
@@ -326,16 +407,14 @@ template <int N> __device__ __forceinline__ void sum_partials(const double *part
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < N; k++) out[k] = tot[k];
+    for (int k = 0; k < N; k++) out[k] = uniform(tot[k]);
     __syncthreads();
 }
 
-// out = F^-1 H in (one parity), the MULT of the launched path.  Kept out of
-// line: inlined four times into the loop it drove the kernel to 256 VGPRs
-// with spills, while as a call each instance gets its own allocation.
+// out = F^-1 H in (one parity), the MULT of the launched path
 template <int P, bool R8>
-__device__ __noinline__ Spinor<typename Real<P>::T> mult_site(const PersistArgs &A, const void *in, int out_par,
-                                                                  const void *clov, int i) {
+__device__ __forceinline__ Spinor<typename Real<P>::T> mult_site(const PersistArgs &A, const void *in, int out_par,
+                                                                     const void *clov, int i) {
     using R = typename Real<P>::T;
     MultKArgs a;
     a.g = A.g;
@@ -357,112 +436,127 @@ __device__ __noinline__ Spinor<typename Real<P>::T> mult_site(const PersistArgs 
 
 template <class R> __device__ __forceinline__ cx<R> to_r(cx<double> a) { return {(R)a.re, (R)a.im}; }
 
-template <int P, bool R8>
-__global__ __launch_bounds__(kBlock) void k_inner_persistent(PersistArgs A) {
+// The loop runs as four stages per iteration, each opening with the one
+// stencil instance of the kernel:
+//   0: tmp = F_oo^-1 H_oe p               2: tmp = F_oo^-1 H_oe s
+//   1: q = p - kappa^2 F_ee^-1 H_eo tmp   3: t = s - kappa^2 F_ee^-1 H_eo tmp
+// followed by the vector updates and reductions of that half-iteration.  A
+// single instance keeps the register allocation that of one stencil launch;
+// the scalars every thread needs (rho, alpha) stay in registers, the ones
+// only the final write-out needs sit in LDS.
+template <int P, bool R8, bool OWN>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(P == P64 ? 1 : 2))) void k_inner_persistent(PersistArgs A) {
     using R = typename Real<P>::T;
     constexpr int XP = P == P64 ? P64 : P32;
     using RX = typename Real<XP>::T;
-    namespace cg = cooperative_groups;
-    cg::grid_group grid = cg::this_grid();
+    enum { K_RQ = 0, K_SS = 2, K_ST = 3, K_TT = 5, K_RR = 6, K_N = 7 };
+    __shared__ double kept[K_N];  // last values, for the write-out by block 0
     const int Vh = A.g.Vh;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const int lb = xcd_block(blockIdx.x, gridDim.x);  // neighbouring sites share an XCD's L2
+    const int i = lb * kBlock + threadIdx.x;
     const bool active = i < Vh;
     const double tol2 = A.sc[S_TOL2];
-    cx<double> rho = ld_c(A.sc, S_RHO0), rq = {0.0, 0.0}, st = {0.0, 0.0};
-    double ss = 0.0, tt = 0.0, rr = 0.0;
-    int it = 0, done = DONE_NO, stopph = 0;
-    for (; it < A.maxit; it++) {
-        // q = D-hat p with <r~, q>   (tmp = F_oo^-1 H_oe p first)
-        if (active) SpinorIO<P>::store(A.tmp, Vh, i, mult_site<P, R8>(A, A.p, 1, A.clov_o, i));
-        grid.sync();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K_N; k++) kept[k] = 0.0;
+    }
+    cx<double> rho = ld_c(A.sc, S_RHO0), al = {0.0, 0.0};
+    int it = 0, stage = 0, done = DONE_NO, stopph = 0;
+    unsigned long long tag = A.tag0;
+    bool timed_out = false;
+    while (it < A.maxit) {
+        const bool mult = !(stage & 1);
+        const bool second = stage >= 2;
+        const void *v = second ? A.r : A.p;  // p, or s (held in r)
+        Spinor<R> h;
+        if (active) h = mult_site<P, R8>(A, mult ? v : A.tmp, mult ? 1 : 0, mult ? A.clov_o : A.clov_e, i);
+        if (mult) {
+            if (active) SpinorIO<P>::store(A.tmp, Vh, i, h);
+            if (!grid_barrier<OWN>(A, tag, lb)) {
+                timed_out = true;
+                break;
+            }
+            stage++;
+            continue;
+        }
+        // D-hat v = v - kappa^2 h into q or t, with <r~, q> or <s, t>, ||t||^2
+        Spinor<R> out;
         {
-            double v[2] = {0.0, 0.0};
+            double d[3] = {0.0, 0.0, 0.0};
             if (active) {
-                const Spinor<R> h = mult_site<P, R8>(A, A.tmp, 0, A.clov_e, i);
-                const Spinor<R> cen = SpinorIO<P>::load(A.p, Vh, i);
+                const Spinor<R> cen = SpinorIO<P>::load(v, Vh, i);
                 const R coef = (R)(-A.kappa2);
-                Spinor<R> out;
 #pragma unroll
                 for (int k = 0; k < 12; k++) out.c[k] = cen.c[k] + coef * h.c[k];
-                SpinorIO<P>::store(A.q, Vh, i, out);
-                const Spinor<R> ax = SpinorIO<P>::load(A.rt, Vh, i);
+                SpinorIO<P>::store(second ? A.t : A.q, Vh, i, out);
+                const Spinor<R> ax = second ? cen : SpinorIO<P>::load(A.rt, Vh, i);
 #pragma unroll
                 for (int k = 0; k < 12; k++) {
                     const double ar = ax.c[k].re, ai = ax.c[k].im, orr = out.c[k].re, oi = out.c[k].im;
-                    v[0] += ar * orr + ai * oi;
-                    v[1] += ar * oi - ai * orr;
+                    d[0] += ar * orr + ai * oi;
+                    d[1] += ar * oi - ai * orr;
+                    d[2] += orr * orr + oi * oi;
                 }
             }
-            block_partials<2>(v, A.part[0], A.nblk, blockIdx.x);
+            if (second) {
+                block_partials<3>(d, A.part[0], A.nblk, lb);
+            } else {
+                double d2[2] = {d[0], d[1]};
+                block_partials<2>(d2, A.part[0], A.nblk, lb);
+            }
+            // the updates below use q or t as stored (FP16 storage rounds)
+            if constexpr (P == P16) {
+                if (active) out = SpinorIO<P>::load(second ? A.t : A.q, Vh, i);
+            }
         }
-        grid.sync();
-        {
+        if (!grid_barrier<OWN>(A, tag, lb)) {
+            timed_out = true;
+            break;
+        }
+        if (!second) {
             double sm[2];
             sum_partials<2>(A.part[0], A.nblk, sm);
-            rq = {sm[0], sm[1]};
-        }
-        // s = r - alpha q (in r) with ||s||^2; the half-step check
-        const cx<double> al = cdiv(rho, rq);
-        {
-            double v[1] = {0.0};
+            const cx<double> rq = {sm[0], sm[1]};
+            al = cdiv(rho, rq);
+            // s = r - alpha q (in r) with ||s||^2; the half-step check
+            double n[1] = {0.0};
             if (active) {
                 const cx<R> alpha = to_r<R>(al);
                 Spinor<R> rv = SpinorIO<P>::load(A.r, Vh, i);
-                const Spinor<R> qv = SpinorIO<P>::load(A.q, Vh, i);
 #pragma unroll
-                for (int k = 0; k < 12; k++) rv.c[k] = rv.c[k] - alpha * qv.c[k];
+                for (int k = 0; k < 12; k++) rv.c[k] = rv.c[k] - alpha * out.c[k];
                 SpinorIO<P>::store(A.r, Vh, i, rv);
 #pragma unroll
-                for (int k = 0; k < 12; k++) v[0] += norm2(rv.c[k]);
+                for (int k = 0; k < 12; k++) n[0] += norm2(rv.c[k]);
             }
-            block_partials<1>(v, A.part[1], A.nblk, blockIdx.x);
-        }
-        grid.sync();
-        {
-            double sm[1];
-            sum_partials<1>(A.part[1], A.nblk, sm);
-            ss = sm[0];
-        }
-        if (!(isfinite(al.re) && isfinite(al.im)) || !isfinite(ss)) {
-            done = DONE_BREAK;
-            stopph = 1;
-            break;
-        }
-        if (ss < tol2) {
-            done = DONE_HALF;
-            stopph = 1;
-            break;
-        }
-        // t = D-hat s with <s, t>, ||t||^2
-        if (active) SpinorIO<P>::store(A.tmp, Vh, i, mult_site<P, R8>(A, A.r, 1, A.clov_o, i));
-        grid.sync();
-        {
-            double v[3] = {0.0, 0.0, 0.0};
-            if (active) {
-                const Spinor<R> h = mult_site<P, R8>(A, A.tmp, 0, A.clov_e, i);
-                const Spinor<R> cen = SpinorIO<P>::load(A.r, Vh, i);
-                const R coef = (R)(-A.kappa2);
-                Spinor<R> out;
-#pragma unroll
-                for (int k = 0; k < 12; k++) out.c[k] = cen.c[k] + coef * h.c[k];
-                SpinorIO<P>::store(A.t, Vh, i, out);
-#pragma unroll
-                for (int k = 0; k < 12; k++) {
-                    const double ar = cen.c[k].re, ai = cen.c[k].im, orr = out.c[k].re, oi = out.c[k].im;
-                    v[0] += ar * orr + ai * oi;
-                    v[1] += ar * oi - ai * orr;
-                    v[2] += orr * orr + oi * oi;
-                }
+            block_partials<1>(n, A.part[1], A.nblk, lb);
+            if (!grid_barrier<OWN>(A, tag, lb)) {
+                timed_out = true;
+                break;
             }
-            block_partials<3>(v, A.part[0], A.nblk, blockIdx.x);
+            sum_partials<1>(A.part[1], A.nblk, n);
+            if (threadIdx.x == 0) {
+                kept[K_RQ] = rq.re;
+                kept[K_RQ + 1] = rq.im;
+                kept[K_SS] = n[0];
+            }
+            if (!(isfinite(al.re) && isfinite(al.im)) || !isfinite(n[0])) {
+                done = DONE_BREAK;
+                stopph = 1;
+                break;
+            }
+            if (n[0] < tol2) {
+                done = DONE_HALF;
+                stopph = 1;
+                break;
+            }
+            stage = 2;
+            continue;
         }
-        grid.sync();
-        {
-            double sm[3];
-            sum_partials<3>(A.part[0], A.nblk, sm);
-            st = {sm[0], sm[1]};
-            tt = sm[2];
-        }
+        double sm[3];
+        sum_partials<3>(A.part[0], A.nblk, sm);
+        const cx<double> st = {sm[0], sm[1]};
+        const double tt = sm[2];
         // x += alpha p + omega s; r = s - omega t with ||r||^2, <r~, r>
         const cx<double> om = {st.re / tt, -st.im / tt};
         double v3[3] = {0.0, 0.0, 0.0};
@@ -478,9 +572,8 @@ __global__ __launch_bounds__(kBlock) void k_inner_persistent(PersistArgs A) {
                 xv.c[k] = xv.c[k] + alx * pk + omx * sk;
             }
             SpinorIO<XP>::store(A.x, Vh, i, xv);
-            const Spinor<R> tv = SpinorIO<P>::load(A.t, Vh, i);
 #pragma unroll
-            for (int k = 0; k < 12; k++) sv.c[k] = sv.c[k] - omega * tv.c[k];
+            for (int k = 0; k < 12; k++) sv.c[k] = sv.c[k] - omega * out.c[k];
             SpinorIO<P>::store(A.r, Vh, i, sv);
             const Spinor<R> rtv = SpinorIO<P>::load(A.rt, Vh, i);
 #pragma unroll
@@ -491,14 +584,19 @@ __global__ __launch_bounds__(kBlock) void k_inner_persistent(PersistArgs A) {
                 v3[2] += ar * bi - ai * br;
             }
         }
-        block_partials<3>(v3, A.part[1], A.nblk, blockIdx.x);
-        grid.sync();
-        cx<double> rho1;
-        {
-            double sm[3];
-            sum_partials<3>(A.part[1], A.nblk, sm);
-            rr = sm[0];
-            rho1 = {sm[1], sm[2]};
+        block_partials<3>(v3, A.part[1], A.nblk, lb);
+        if (!grid_barrier<OWN>(A, tag, lb)) {
+            timed_out = true;
+            break;
+        }
+        sum_partials<3>(A.part[1], A.nblk, v3);
+        const double rr = v3[0];
+        const cx<double> rho1 = {v3[1], v3[2]};
+        if (threadIdx.x == 0) {
+            kept[K_ST] = st.re;
+            kept[K_ST + 1] = st.im;
+            kept[K_TT] = tt;
+            kept[K_RR] = rr;
         }
         const bool bad = !(tt > 0.0) || !(isfinite(om.re) && isfinite(om.im)) || !isfinite(rr) ||
                          (rho1.re == 0.0 && rho1.im == 0.0);
@@ -506,7 +604,7 @@ __global__ __launch_bounds__(kBlock) void k_inner_persistent(PersistArgs A) {
             done = (rr < tol2) ? DONE_FULL : DONE_BREAK;
             stopph = 2;
             // the scalars of a full step, as the launched path leaves them
-            if (blockIdx.x == 0 && threadIdx.x == 0) {
+            if (lb == 0 && threadIdx.x == 0) {
                 const int nxt = rho_slot_p(it + 1);
                 A.sc[nxt] = rho1.re;
                 A.sc[nxt + 1] = rho1.im;
@@ -525,23 +623,32 @@ __global__ __launch_bounds__(kBlock) void k_inner_persistent(PersistArgs A) {
             SpinorIO<P>::store(A.p, Vh, i, pv);
         }
         rho = rho1;
-        grid.sync();
+        if (!grid_barrier<OWN>(A, tag, lb)) {
+            timed_out = true;
+            break;
+        }
+        stage = 0;
+        it++;
+    }
+    if (timed_out) {
+        done = DONE_BREAK;
+        stopph = 3;
     }
     // leave the scalars and flags as the launched path would
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (lb == 0 && threadIdx.x == 0) {
         double *sc = A.sc;
         if (stopph != 2) {
             const int cur = rho_slot_p(it);
             sc[cur] = rho.re;
             sc[cur + 1] = rho.im;
         }
-        sc[S_RQ] = rq.re;
-        sc[S_RQ + 1] = rq.im;
-        sc[S_SS] = ss;
-        sc[S_ST] = st.re;
-        sc[S_ST + 1] = st.im;
-        sc[S_TT] = tt;
-        sc[S_RR] = rr;
+        sc[S_RQ] = kept[K_RQ];
+        sc[S_RQ + 1] = kept[K_RQ + 1];
+        sc[S_SS] = kept[K_SS];
+        sc[S_ST] = kept[K_ST];
+        sc[S_ST + 1] = kept[K_ST + 1];
+        sc[S_TT] = kept[K_TT];
+        sc[S_RR] = kept[K_RR];
         A.fl[F_DONE] = done;
         A.fl[F_ITERS] = it;
         A.fl[F_STOPPH] = stopph;
@@ -637,6 +744,8 @@ int launch_mult_batch(hipStream_t s, const MultCall *calls, int n, wc_lattice *t
     return WC_OK;
 }
 
+double g_barrier_timeout_s = 2.0;
+
 // The inner loop as one cooperative launch; *ran = false (and WC_OK) when the
 // lattice is too large for all its workgroups to be resident at once, so the
 // caller uses the launched loop instead.
@@ -665,12 +774,23 @@ int launch_inner_persistent(const PersistCall &c, hipStream_t s, bool *ran) {
     A.kappa2 = lat->kappa * lat->kappa;
     A.maxit = c.maxit;
     A.nblk = lat->nblocks;
-    const void *fn = c.prec == P64   ? (const void *)k_inner_persistent<P64, false>
-                     : c.prec == P16 ? (const void *)k_inner_persistent<P16, false>
-                     : r8            ? (const void *)k_inner_persistent<P32, true>
-                                     : (const void *)k_inner_persistent<P32, false>;
-    int dev = 0, cus = 0, per_cu = 0, coop = 0;
+    // the runtime's barrier is the cheaper one for a handful of blocks only
+    A.bar = A.nblk >= kOwnBarrierMinBlocks ? c.bar : nullptr;
+    A.epoch = c.epoch;
+    A.tag0 = (unsigned long long)c.epoch << 32;
+    const bool own = A.bar != nullptr;
+    const void *fn = c.prec == P64 ? (own ? (const void *)k_inner_persistent<P64, false, true>
+                                          : (const void *)k_inner_persistent<P64, false, false>)
+                     : c.prec == P16 ? (own ? (const void *)k_inner_persistent<P16, false, true>
+                                            : (const void *)k_inner_persistent<P16, false, false>)
+                     : r8 ? (own ? (const void *)k_inner_persistent<P32, true, true>
+                                 : (const void *)k_inner_persistent<P32, true, false>)
+                          : (own ? (const void *)k_inner_persistent<P32, false, true>
+                                 : (const void *)k_inner_persistent<P32, false, false>);
+    int dev = 0, cus = 0, per_cu = 0, coop = 0, clock_khz = 0;
     WC_HIP(hipGetDevice(&dev));
+    WC_HIP(hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev));
+    A.limit = (long long)(g_barrier_timeout_s * 1e3 * clock_khz);
     WC_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
     WC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     WC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, 0));

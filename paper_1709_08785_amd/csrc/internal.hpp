@@ -34,7 +34,8 @@ enum ScalarSlot {
 };
 // flags block (ints): done code, iterations completed
 // F_STOPPH: where the inner loop stopped: 1 at the half-step check (after the
-// first D-hat), 2 at the full-step check (after the second)
+// first D-hat), 2 at the full-step check (after the second), 3 when a grid
+// barrier of the one-launch loop ran out of time (the call then fails)
 enum FlagSlot { F_DONE = 0, F_ITERS = 1, F_STOPPH = 2, F_COUNT = 4 };
 enum DoneCode { DONE_NO = 0, DONE_FULL = 1, DONE_HALF = 2, DONE_BREAK = 4 };
 
@@ -82,6 +83,8 @@ struct SysState {
     double *partials = nullptr;    // [8][blocks of the system's lattice]
     size_t partials_bytes = 0;
     double *partials2 = nullptr;   // a second set, for the one-launch inner loop (single-system state only)
+    unsigned long long *bar = nullptr;  // its grid barrier: [blocks] arrivals, release, abort (zeroed once)
+    unsigned int bar_epoch = 0;         // one-launch calls so far (tags of a call exceed all earlier ones)
     double *h_scalars = nullptr;   // pinned mirror
     int *h_flags = nullptr;
     double *sc(int lvl) const { return scalars + lvl * S_COUNT; }
@@ -282,7 +285,12 @@ struct PersistCall {
     double *sc;
     int *fl;
     int maxit;
+    unsigned long long *bar;  // nblocks + 2 words, zero before the first call
+    unsigned int epoch;       // distinct and increasing per call on one bar
 };
+// longest a block of the one-launch loop waits at a grid barrier before the
+// call gives up (seconds)
+extern double g_barrier_timeout_s;
 int launch_inner_persistent(const PersistCall &c, hipStream_t s, bool *ran);
 
 // ---------------------------------------------------------------------------

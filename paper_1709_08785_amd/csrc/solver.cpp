@@ -307,7 +307,8 @@ int inner_solve(Run &R, const std::vector<int> &act, int src_id, int v_id) {
     int queued = 0;
     // one system of a small lattice: the whole loop as one cooperative launch
     // (not under kernel timing, whose per-launch records it would bypass)
-    if (R.persistent && !R.pipe && act.size() == 1 && !R.tl->timing && S_(R, act[0]).st->partials2) {
+    if (R.persistent && !R.pipe && act.size() == 1 && !R.tl->timing && S_(R, act[0]).st->partials2 &&
+        S_(R, act[0]).st->bar) {
         const int k = act[0];
         SolveSys &s = S_(R, k);
         PersistCall c;
@@ -325,10 +326,14 @@ int inner_solve(Run &R, const std::vector<int> &act, int src_id, int v_id) {
         c.sc = s.st->sc(L);
         c.fl = s.st->fl(L);
         c.maxit = maxit;
+        c.bar = s.st->bar;
+        c.epoch = ++s.st->bar_epoch;
         bool ran = false;
         if (int rc = launch_inner_persistent(c, R.stream, &ran)) return rc;
         if (ran) {
             if (int rc = sync(R)) return rc;
+            if (s.st->hf(L, F_STOPPH) == 3)
+                return wc_fail(WC_EHIP, "one-launch inner loop: a grid barrier wait ran out of time");
             queued = maxit;  // the loop below is done
             s.info.persistent_calls++;
         }

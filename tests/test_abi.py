@@ -67,6 +67,14 @@ def test_null_handles_rejected(lib):
     lib.wc_destroy_lattice(None)
 
 
+def test_barrier_timeout_validated_on_host(lib):
+    lib.wc_set_barrier_timeout.argtypes = [ctypes.c_double]
+    assert lib.wc_set_barrier_timeout(-1.0) == -1
+    assert lib.wc_set_barrier_timeout(float("nan")) == -1
+    assert lib.wc_set_barrier_timeout(float("inf")) == -1
+    assert lib.wc_set_barrier_timeout(2.0) == 0
+
+
 def test_default_params(lib):
     import paper_1709_08785_amd as wc
     p = wc.SolveParams()

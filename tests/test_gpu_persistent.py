@@ -98,3 +98,48 @@ def test_persistent_iteration_cap_and_fallback():
     r, bn = oracle.residual(U, 0.13, 1.0, b, host(x))
     assert r / bn < 1e-10
     lat.close()
+
+
+@pytest.mark.parametrize("dims", [(16, 16, 16, 16), (16, 16, 16, 32)])
+def test_persistent_own_barrier_matches_oracle(dims):
+    # 128 and 256 workgroups: the kernel's own grid barrier (per-block arrival
+    # words, one cache write-back and invalidate per block) instead of the
+    # runtime's; the solution must agree with the launched loop's and pass the
+    # oracle's FP64 true residual
+    kappa = 0.13
+    say("persistent, own barrier", dims)
+    U = synth.random_links(dims, 0.3, 1034)
+    lat = wc.Lattice(dims)
+    lat.load_links(dev(U))
+    b = synth.gaussian_source(dims, 2034)
+    x, info = lat.solve(dev(b), kappa, 1.0, 1e-12, persistent=1)
+    say(info)
+    assert info["persistent_calls"] == info["inner_calls"] > 0
+    r, bn = oracle.residual(U, kappa, 1.0, b, host(x))
+    assert r / bn < 1e-12
+    x2, info2 = lat.solve(dev(b), kappa, 1.0, 1e-12, persistent=0)
+    assert rel(host(x), host(x2)) < 1e-10
+    assert abs(info["inner_iters_total"] - info2["inner_iters_total"]) <= max(2, 0.05 * info2["inner_iters_total"])
+    lat.close()
+
+
+def test_persistent_barrier_timeout_fails_cleanly():
+    # a zero wait limit makes the first barrier that is not already complete
+    # give up: every workgroup leaves the loop, the kernel ends, the solve
+    # reports WC_EHIP, and the lattice solves normally afterwards
+    dims, kappa = (16, 16, 16, 16), 0.13
+    U = synth.random_links(dims, 0.3, 1035)
+    lat = wc.Lattice(dims)
+    lat.load_links(dev(U))
+    b = dev(synth.gaussian_source(dims, 2035))
+    wc.set_barrier_timeout(0.0)
+    try:
+        with pytest.raises(wc.WCError) as e:
+            lat.solve(b, kappa, 1.0, 1e-10, persistent=1)
+        say(e.value)
+        assert e.value.code == -3 and "grid barrier" in str(e.value)
+    finally:
+        wc.set_barrier_timeout(2.0)
+    x, info = lat.solve(b, kappa, 1.0, 1e-10, persistent=1)
+    assert info["persistent_calls"] > 0 and info["true_rel_residual"] < 1e-10
+    lat.close()
