@@ -384,9 +384,101 @@ def precisions_mode(args):
                       "source": "Z2", "forms": res, "oracle_threads": oracle.num_threads()}), flush=True)
 
 
+def host_info():
+    """Model name and core counts of the host CPU (from /proc/cpuinfo)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None
+    return {"cpu_model": model, "cpu_count": os.cpu_count(), "usable_cpus": aff,
+            "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS")}
+
+
+def oracle_mode(args):
+    """The FP64 oracle on the host cores, as it stands (never tuned): one full D
+    and one D-hat_ee at 8^4 and 32^3x64, with one thread and with all, then the
+    full solves to 1e-10 of the 8^4 (kappa 0.12, links 1001, source 2001) and
+    32^3x64 (kappa 0.135, links 1002, source 2002) systems with all threads,
+    beside the GPU's solves of the same systems (FP32 inner / FP64 outer, and
+    all-FP64).  Rates use the algorithmic bytes of the FP64 operator (full D:
+    1536 B per site; D-hat_ee: 4416 B per even site) and the paper's Table 1
+    flop counts (2232 per site for an operator application over all sites,
+    4512 per even site for D-hat_ee)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1709_08785_amd as wc
+    import synth
+
+    csw = 1.0
+    nall = oracle.num_threads()
+    out = {"mode": "oracle", "host": host_info(), "oracle_threads_all": nall, "apply": {}, "solve": {}}
+    for dims, kappa, seed in [((8, 8, 8, 8), 0.12, 1001), ((32, 32, 32, 64), 0.135, 1002)]:
+        name = "x".join(map(str, dims))
+        V = int(np.prod(dims))
+        U = synth.random_links(dims, 0.3, seed)
+        b = synth.gaussian_source(dims, seed + 1000)
+        F = oracle.clover_field(U, dims, kappa, csw)
+        Finv = oracle.site_invert(F)
+        be = oracle.restrict(b, 0)
+        row = {}
+        for nt in sorted({1, nall}):
+            oracle.set_num_threads(nt)
+            reps = 20 if V < 100000 else 1
+            t0 = time.perf_counter()
+            for r in range(reps):
+                oracle.apply_D(U, F, kappa, b)
+            t_d = (time.perf_counter() - t0) / reps
+            t0 = time.perf_counter()
+            for r in range(reps):
+                oracle.dhat_ee(U, Finv, kappa, be)
+            t_h = (time.perf_counter() - t0) / reps
+            row["threads_%d" % nt] = {
+                "D_s": round(t_d, 5), "D_GBs": round(V * 1536 / t_d / 1e9, 3),
+                "D_GFLOPS": round(V * 2232 / t_d / 1e9, 3),
+                "dhat_s": round(t_h, 5), "dhat_GBs": round(V / 2 * 4416 / t_h / 1e9, 3),
+                "dhat_GFLOPS": round(V / 2 * 4512 / t_h / 1e9, 3)}
+            log("oracle %s threads %d: %s" % (name, nt, json.dumps(row["threads_%d" % nt])))
+        oracle.set_num_threads(nall)
+        out["apply"][name] = row
+        # the full solves: oracle (all threads) and GPU
+        t0 = time.perf_counter()
+        x_ref, its, relres = oracle.solve(U, F, kappa, b, tol=args.tol)
+        t_or = time.perf_counter() - t0
+        log("oracle solve %s: %.1f s, %d iterations, true relres %.2e" % (name, t_or, its, relres))
+        lat = wc.Lattice(dims)
+        lat.load_links(torch.from_numpy(U).cuda())
+        bd = torch.from_numpy(b).cuda()
+        gpu = {}
+        for form, kw in [("mixed_fp32_inner", {}), ("fp64", {"inner_prec": wc.FP64})]:
+            lat.solve(bd, kappa, csw, args.tol, **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, info = lat.solve(bd, kappa, csw, args.tol, **kw)
+            torch.cuda.synchronize()
+            t_g = time.perf_counter() - t0
+            xh = x.cpu().numpy()
+            gpu[form] = {"seconds": round(t_g, 5), "inner_iters": info["inner_iters_total"],
+                         "true_rel_residual": info["true_rel_residual"],
+                         "solution_rel_diff_vs_oracle": float(np.linalg.norm(xh - x_ref) / np.linalg.norm(x_ref)),
+                         "oracle_over_gpu": round(t_or / t_g, 1)}
+        lat.close()
+        out["solve"][name] = {"kappa": kappa, "tol": args.tol, "oracle_s": round(t_or, 3), "oracle_iters": its,
+                              "oracle_true_rel_residual": relres, "oracle_threads": nall, "gpu": gpu}
+        del U, b, F, Finv, be, x_ref
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--mode", choices=["solve", "dslash", "batch", "precisions", "inner"], default="solve")
+    ap.add_argument("--mode", choices=["solve", "dslash", "batch", "precisions", "inner", "oracle"], default="solve")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
@@ -425,6 +517,9 @@ def main():
         return
     if args.mode == "inner":
         inner_mode(args)
+        return
+    if args.mode == "oracle":
+        oracle_mode(args)
         return
     t0 = time.perf_counter()
     U = synth.random_links(dims, 0.3, args.seed)
