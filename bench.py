@@ -136,8 +136,9 @@ def small_config():
 def dslash_mode(args, dims):
     """Operator micro-benchmark: MULT and D-hat_ee in each precision, K launches each,
     timed with HIP events on the library stream; plus a device copy of known size
-    (the calibration kernel for the HBM byte counters) and a read stream, against
-    which each operator's rate is also given as a fraction."""
+    (the calibration kernel for the HBM byte counters) and a stream with the
+    stencil's 8:1 read/write mix, against which each operator's rate is also
+    given as a fraction."""
     import numpy as np
     import torch
 
@@ -197,24 +198,28 @@ def dslash_mode(args, dims):
     copy_gbs = 2 * 4 * n / (ms * 1e-3) / 1e9
     res["copy_1GiB"] = {"avg_us": round(ms * 1e3, 2), "GBs": round(copy_gbs, 1),
                         "bytes_read": 4 * n, "bytes_written": 4 * n}
-    # a read stream of the same 1 GiB (a sum; its output is one float)
-    s_out = torch.empty((), dtype=torch.float32, device=dev)
+    # torch's column sum as a stream with the stencil's read/write mix (8 reads
+    # per write: the MULT reads 768 B and writes 96 B per site in FP32): 1 GiB
+    # summed in 8 rows
+    col = torch.empty(n // 8, dtype=torch.float32, device=dev)
+    a8 = a.view(8, n // 8)
     for k in range(3):
-        torch.sum(a, out=s_out)
+        torch.sum(a8, dim=0, out=col)
     torch.cuda.synchronize()
     e0.record()
     for k in range(args.steps):
-        torch.sum(a, out=s_out)
+        torch.sum(a8, dim=0, out=col)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
-    read_gbs = 4 * n / (ms * 1e-3) / 1e9
-    res["read_1GiB"] = {"avg_us": round(ms * 1e3, 2), "GBs": round(read_gbs, 1), "bytes_read": 4 * n}
-    # each operator's rate also as a fraction of the two measured streams
+    mix_gbs = (4 * n + 4 * n // 8) / (ms * 1e-3) / 1e9
+    res["read8_write1_1GiB"] = {"avg_us": round(ms * 1e3, 2), "GBs": round(mix_gbs, 1), "bytes_read": 4 * n,
+                                "bytes_written": 4 * n // 8}
+    # each operator's rate also as a fraction of the two measured torch streams
     for k, v in res.items():
         if "algorithmic_GBs" in v:
             v["frac_copy"] = round(v["algorithmic_GBs"] / copy_gbs, 4)
-            v["frac_read_stream"] = round(v["algorithmic_GBs"] / read_gbs, 4)
+            v["frac_read8_write1_stream"] = round(v["algorithmic_GBs"] / mix_gbs, 4)
     print(json.dumps({"mode": "dslash", "lattice": list(dims), "kernels": res}), flush=True)
 
 
