@@ -409,6 +409,48 @@ def precisions_mode(args):
                       "source": "Z2", "forms": res, "oracle_threads": oracle.num_threads()}), flush=True)
 
 
+def tune_mode(args):
+    """The launch-shape tuner on 8^4 .. 32^3x64: its microseconds per stencil pair
+    (F^-1 H, then the D-hat half with its fused dot) at 64, 128 and 256 threads
+    per block in each precision, its choice, and the nested solve (FP32 inner,
+    Algorithm 1 outer, kappa 0.13, c_SW 1, Gaussian source, tol) at the tuned
+    size against 256 pinned."""
+    import torch
+
+    import paper_1709_08785_amd as wc
+    import synth
+
+    kappa, csw = 0.13, 1.0
+    out = {"mode": "tune", "kappa": kappa, "csw": csw, "tol": args.tol, "lattices": {}}
+    for dims in [(8, 8, 8, 8), (16, 16, 16, 16), (24, 24, 24, 48), (32, 32, 32, 64)]:
+        name = "x".join(map(str, dims))
+        lat = wc.Lattice(dims)
+        lat.load_links(torch.from_numpy(synth.random_links(dims, 0.3, 1070)).cuda())
+        lat.build_clover(kappa, csw)
+        row = {"tuner": {}}
+        for pname, prec in (("fp32", wc.FP32), ("fp16", wc.FP16), ("fp64", wc.FP64)):
+            r = lat.tune_block_size(prec)
+            row["tuner"][pname] = {"us_per_pair": {str(k): round(v, 2) for k, v in r["us_per_pair"].items()},
+                                   "threads": r["threads"]}
+        b = torch.from_numpy(synth.gaussian_source(dims, 2070)).cuda()
+        reps = 20 if dims[0] <= 16 else 3
+        for label, pin in (("pinned_256", 256), ("tuned", 0)):
+            lat.set_block_size(pin)
+            lat.solve(b, kappa, csw, args.tol)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for r in range(reps):
+                x, info = lat.solve(b, kappa, csw, args.tol)
+            torch.cuda.synchronize()
+            row[label] = {"ms": round((time.perf_counter() - t0) / reps * 1e3, 3), "threads": info["block_size"],
+                          "inner_iters": info["inner_iters_total"], "true_rel_residual": info["true_rel_residual"]}
+        row["speedup_tuned"] = round(row["pinned_256"]["ms"] / row["tuned"]["ms"], 3)
+        log("tune %s %s" % (name, json.dumps(row)))
+        out["lattices"][name] = row
+        lat.close()
+    print(json.dumps(out), flush=True)
+
+
 def host_info():
     """Model name and core counts of the host CPU (from /proc/cpuinfo)."""
     model = "unknown"
@@ -503,7 +545,8 @@ def oracle_mode(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--mode", choices=["solve", "dslash", "batch", "precisions", "inner", "oracle"], default="solve")
+    ap.add_argument("--mode", choices=["solve", "dslash", "batch", "precisions", "inner", "oracle", "tune"],
+                    default="solve")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
@@ -545,6 +588,9 @@ def main():
         return
     if args.mode == "oracle":
         oracle_mode(args)
+        return
+    if args.mode == "tune":
+        tune_mode(args)
         return
     t0 = time.perf_counter()
     U = synth.random_links(dims, 0.3, args.seed)
@@ -691,7 +737,8 @@ def main():
                                % ("x".join(map(str, dims)), args.kappa, args.csw, args.inner.upper(),
                                   args.inner_tol, args.tol),
                    "lattice": list(dims), "kappa": args.kappa, "csw": args.csw, "tol": args.tol,
-                   "inner": args.inner, "inner_tol": args.inner_tol, "link_recon": args.recon},
+                   "inner": args.inner, "inner_tol": args.inner_tol, "link_recon": args.recon,
+                   "threads_per_block": infos[-1]["block_size"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "small_config_8x8x8x8": small,

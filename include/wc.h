@@ -119,9 +119,33 @@ typedef struct {
     double true_rel_residual; /* ||b - D x|| / ||b|| in FP64 on the full lattice */
     double seconds;           /* wall time of the solve (host clock, after the final sync) */
     int persistent_calls;     /* inner calls that ran as one cooperative launch (persistent) */
+    int block_size;           /* threads per block of the solve's stencil and vector kernels */
 } wc_solve_info;
 
 void wc_solve_params_default(wc_solve_params *p);
+
+/* Launch shape of the solver's per-site kernels (the counterpart of the site
+   loop tiling of Sec. III-B).  Sites are stored in tiles of 64 (one tile per
+   wavefront); a workgroup covers 1, 2 or 4 tiles, i.e. 64, 128 or 256
+   threads.  Small lattices fill more compute units with small workgroups;
+   large ones prefer large.  Unless pinned, the size is tuned per inner
+   precision on the first solve of a lattice (wc_tune_block_size) and reused.
+   Results do not depend on it beyond the rounding order of the reductions.
+
+   wc_set_block_size: threads = 64, 128 or 256 pins the size for every
+   precision; 0 returns to tuning.  WC_EINVAL for other values.
+   wc_block_size: the size a solve with inner precision prec would use now
+   (pinned, else tuned), or 0 when it is not yet tuned.
+   wc_tune_block_size: times the inner loop's stencil pair (F^-1 H into the
+   odd parity, then the D-hat half with its fused dot; Sec. II-B eq. 8) on
+   zero vectors at 64, 128 and 256 threads and keeps the fastest, a smaller
+   size only if at least 3% faster.  us_per_pair[3] (may be NULL) receives
+   microseconds per pair for 64, 128, 256; *threads (may be NULL) the choice.
+   Needs links and clover (WC_ENOTREADY).  Allocates three vectors of the
+   precision for the duration of the call and synchronises the stream. */
+int wc_set_block_size(wc_lattice *lat, int threads);
+int wc_block_size(const wc_lattice *lat, int prec);
+int wc_tune_block_size(wc_lattice *lat, int prec, double us_per_pair[3], int *threads);
 
 /* Longest time (seconds, > 0 finite, or 0 for "no waiting allowed") a
    workgroup of the one-launch inner loop (wc_solve_params.persistent) waits

@@ -51,7 +51,7 @@ class SolveInfo(ctypes.Structure):
     _fields_ = [("outer_iters", ctypes.c_int), ("inner_iters_total", ctypes.c_int), ("inner_calls", ctypes.c_int),
                 ("restarts", ctypes.c_int), ("dslash_count", ctypes.c_long), ("status", ctypes.c_int),
                 ("eo_rel_residual", ctypes.c_double), ("true_rel_residual", ctypes.c_double),
-                ("seconds", ctypes.c_double), ("persistent_calls", ctypes.c_int)]
+                ("seconds", ctypes.c_double), ("persistent_calls", ctypes.c_int), ("block_size", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -100,6 +100,9 @@ def load_library():
         "wc_reset_kernel_stats": (I, [P]),
         "wc_last_error": (ctypes.c_char_p, []),
         "wc_set_barrier_timeout": (I, [D]),
+        "wc_set_block_size": (I, [P, I]),
+        "wc_block_size": (I, [P, I]),
+        "wc_tune_block_size": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(I)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -180,6 +183,22 @@ class Lattice:
         """Link storage of the FP32/FP16 stencils: 12 (two columns) or 8 (eight reals)."""
         self._sync_stream()
         _check(self.lib.wc_set_link_recon(self.h, int(recon)))
+
+    def set_block_size(self, threads: int):
+        """Pin the solver kernels' threads per block (64, 128, 256), or 0 to tune."""
+        _check(self.lib.wc_set_block_size(self.h, int(threads)))
+
+    def block_size(self, prec=FP32) -> int:
+        """Threads per block a solve in this inner precision would use (0: not yet tuned)."""
+        return int(self.lib.wc_block_size(self.h, _prec(prec)))
+
+    def tune_block_size(self, prec=FP32) -> dict:
+        """Time the inner loop's stencil pair at 64, 128, 256 threads per block and keep
+        the fastest; returns the microseconds per pair and the choice."""
+        us = (ctypes.c_double * 3)()
+        th = ctypes.c_int()
+        _check(self.lib.wc_tune_block_size(self.h, _prec(prec), us, ctypes.byref(th)))
+        return {"us_per_pair": {64: us[0], 128: us[1], 256: us[2]}, "threads": th.value}
 
     @property
     def link_recon(self) -> int:

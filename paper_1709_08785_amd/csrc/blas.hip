@@ -61,7 +61,7 @@ template <int OP, int P, int XP> __global__ __launch_bounds__(kBlock) void k_vec
     // captured chunk of iterations replays unchanged; the p update runs after
     // the iteration count has been advanced
     const int iter = c.iter_dev ? c.fl[F_ITERS] - (OP == V_INNER_C ? 1 : 0) : c.iter;
-    const int i = lb * kBlock + threadIdx.x;
+    const int i = lb * (int)blockDim.x + threadIdx.x;  // 64, 128 or 256 sites per block
     const bool active = i < Vh;
     double a[NA];
 #pragma unroll
@@ -379,7 +379,7 @@ template <int OP, int P, int XP> __global__ __launch_bounds__(kBlock) void k_vec
             SpinorIO<XP>::template store<kVNT>(c.a, Vh, i, xv);
         }
     }
-    if (N > 0) block_partials<NA>(a, c.partials, (Vh + kBlock - 1) / kBlock, lb);
+    if (N > 0) block_partials<NA>(a, c.partials, blocks_of(Vh, (int)blockDim.x), lb);
 }
 
 // ------------------------------------------------------------------ reduction stage 2
@@ -506,8 +506,6 @@ template <int N> __global__ __launch_bounds__(kBlock) void k_finalize(FinBatch B
     }
 }
 
-inline int nblk(int Vh) { return (Vh + kBlock - 1) / kBlock; }
-
 // algorithmic bytes of one op on one system (vectors read and written)
 double vec_bytes(int op, int prec, int xprec, int Vh) {
     const double S = (double)spinor_site_bytes(prec) * Vh, X = (double)spinor_site_bytes(xprec) * Vh,
@@ -535,16 +533,16 @@ double vec_bytes(int op, int prec, int xprec, int Vh) {
     return 0;
 }
 
-template <int OP, int P, int XP> void launch_op(hipStream_t s, const VecBatch &B, int blocks) {
-    hipLaunchKernelGGL((k_vec<OP, P, XP>), dim3(blocks), dim3(kBlock), 0, s, B);
+template <int OP, int P, int XP> void launch_op(hipStream_t s, const VecBatch &B, int blocks, int bs) {
+    hipLaunchKernelGGL((k_vec<OP, P, XP>), dim3(blocks), dim3(bs), 0, s, B);
 }
 
 // the inner-loop ops exist for every storage precision; x is FP32 for the
 // FP32 and FP16 inner loops and FP64 for the all-FP64 loop
-template <int OP> void dispatch_inner(hipStream_t s, const VecBatch &B, int blocks, int prec) {
-    if (prec == P64) launch_op<OP, P64, P64>(s, B, blocks);
-    else if (prec == P32) launch_op<OP, P32, P32>(s, B, blocks);
-    else launch_op<OP, P16, P32>(s, B, blocks);
+template <int OP> void dispatch_inner(hipStream_t s, const VecBatch &B, int blocks, int bs, int prec) {
+    if (prec == P64) launch_op<OP, P64, P64>(s, B, blocks, bs);
+    else if (prec == P32) launch_op<OP, P32, P32>(s, B, blocks, bs);
+    else launch_op<OP, P16, P32>(s, B, blocks, bs);
 }
 
 }  // namespace
@@ -573,10 +571,13 @@ int launch_vec_batch(hipStream_t s, wc_lattice *tlat, int op, int prec, const Ve
     B.h.interleave = 0;
     B.h.off[0] = 0;
     const int xprec = prec == P64 ? P64 : P32;
+    const int bs = launch_bs(calls[0].bs);
+    if (!valid_block_size(bs)) return wc_fail(WC_EINVAL, "block size must be 64, 128 or 256");
     double bytes = 0;
     for (int k = 0; k < n; k++) {
+        if (launch_bs(calls[k].bs) != bs) return wc_fail(WC_EINVAL, "batched vector calls must share the block size");
         B.c[k] = calls[k];
-        B.h.off[k + 1] = B.h.off[k] + nblk(calls[k].Vh);
+        B.h.off[k + 1] = B.h.off[k] + blocks_of(calls[k].Vh, bs);
         bytes += vec_bytes(op, prec, xprec, calls[k].Vh);
     }
     const int blocks = B.h.off[n];
@@ -590,24 +591,24 @@ int launch_vec_batch(hipStream_t s, wc_lattice *tlat, int op, int prec, const Ve
                                         vec_bytes(op, prec, xprec, calls[k].Vh)});
     }
     switch (op) {
-    case V_NORM2: launch_op<V_NORM2, P64, P64>(s, B, blocks); break;
-    case V_SUB_NORM: launch_op<V_SUB_NORM, P64, P64>(s, B, blocks); break;
-    case V_AXPY: launch_op<V_AXPY, P64, P64>(s, B, blocks); break;
-    case V_COPY: launch_op<V_COPY, P64, P64>(s, B, blocks); break;
-    case V_ZERO: launch_op<V_ZERO, P64, P64>(s, B, blocks); break;
-    case V_GAMMA5: launch_op<V_GAMMA5, P64, P64>(s, B, blocks); break;
-    case V_INNER_INIT: dispatch_inner<V_INNER_INIT>(s, B, blocks, prec); break;
-    case V_INNER_A: dispatch_inner<V_INNER_A>(s, B, blocks, prec); break;
-    case V_INNER_B: dispatch_inner<V_INNER_B>(s, B, blocks, prec); break;
-    case V_INNER_C: dispatch_inner<V_INNER_C>(s, B, blocks, prec); break;
-    case V_INNER_FIX: dispatch_inner<V_INNER_FIX>(s, B, blocks, prec); break;
-    case V_INNER_FINAL: dispatch_inner<V_INNER_FINAL>(s, B, blocks, prec); break;
-    case V_PIPE_INIT: dispatch_inner<V_PIPE_INIT>(s, B, blocks, prec); break;
-    case V_PIPE_A: dispatch_inner<V_PIPE_A>(s, B, blocks, prec); break;
-    case V_PIPE_B: dispatch_inner<V_PIPE_B>(s, B, blocks, prec); break;
-    case V_PIPE_FIX: dispatch_inner<V_PIPE_FIX>(s, B, blocks, prec); break;
-    case V_OUTER_A: launch_op<V_OUTER_A, P64, P64>(s, B, blocks); break;
-    case V_OUTER_B: launch_op<V_OUTER_B, P64, P64>(s, B, blocks); break;
+    case V_NORM2: launch_op<V_NORM2, P64, P64>(s, B, blocks, bs); break;
+    case V_SUB_NORM: launch_op<V_SUB_NORM, P64, P64>(s, B, blocks, bs); break;
+    case V_AXPY: launch_op<V_AXPY, P64, P64>(s, B, blocks, bs); break;
+    case V_COPY: launch_op<V_COPY, P64, P64>(s, B, blocks, bs); break;
+    case V_ZERO: launch_op<V_ZERO, P64, P64>(s, B, blocks, bs); break;
+    case V_GAMMA5: launch_op<V_GAMMA5, P64, P64>(s, B, blocks, bs); break;
+    case V_INNER_INIT: dispatch_inner<V_INNER_INIT>(s, B, blocks, bs, prec); break;
+    case V_INNER_A: dispatch_inner<V_INNER_A>(s, B, blocks, bs, prec); break;
+    case V_INNER_B: dispatch_inner<V_INNER_B>(s, B, blocks, bs, prec); break;
+    case V_INNER_C: dispatch_inner<V_INNER_C>(s, B, blocks, bs, prec); break;
+    case V_INNER_FIX: dispatch_inner<V_INNER_FIX>(s, B, blocks, bs, prec); break;
+    case V_INNER_FINAL: dispatch_inner<V_INNER_FINAL>(s, B, blocks, bs, prec); break;
+    case V_PIPE_INIT: dispatch_inner<V_PIPE_INIT>(s, B, blocks, bs, prec); break;
+    case V_PIPE_A: dispatch_inner<V_PIPE_A>(s, B, blocks, bs, prec); break;
+    case V_PIPE_B: dispatch_inner<V_PIPE_B>(s, B, blocks, bs, prec); break;
+    case V_PIPE_FIX: dispatch_inner<V_PIPE_FIX>(s, B, blocks, bs, prec); break;
+    case V_OUTER_A: launch_op<V_OUTER_A, P64, P64>(s, B, blocks, bs); break;
+    case V_OUTER_B: launch_op<V_OUTER_B, P64, P64>(s, B, blocks, bs); break;
     default: return wc_fail(WC_EINVAL, "unknown vector op");
     }
     WC_HIP(hipGetLastError());
@@ -621,7 +622,7 @@ int launch_vec_batch(hipStream_t s, wc_lattice *tlat, int op, int prec, const Ve
         const VecCall &c = calls[k];
         FinArgs &a = f[k];
         a = FinArgs{};
-        a.blocks = nblk(c.Vh);
+        a.blocks = blocks_of(c.Vh, bs);
         a.partials = c.partials;
         a.result = c.result;
         a.sc = c.sc;

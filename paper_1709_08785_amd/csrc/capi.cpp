@@ -287,7 +287,8 @@ extern "C" int wc_create_lattice(const int dims[4], void *stream, wc_lattice **o
     int rc = arena_alloc(lat->arena, 1, lat->stream);
     if (!rc) {
         arena_bind(lat->arena, 0, lat->sys);
-        rc = dev_alloc((void **)&lat->sys.partials, sizeof(double) * kMaxRed * (size_t)lat->nblocks);
+        rc = dev_alloc((void **)&lat->sys.partials,
+                       sizeof(double) * kMaxRed * (size_t)blocks_of(lat->Vh, kMinBlock));
         if (!rc) rc = dev_alloc((void **)&lat->sys.partials2, sizeof(double) * kMaxRed * (size_t)lat->nblocks);
         const size_t bar_bytes = sizeof(unsigned long long) * ((size_t)lat->nblocks + 2);
         if (!rc) rc = dev_alloc((void **)&lat->sys.bar, bar_bytes);
@@ -430,7 +431,8 @@ extern "C" int wc_solve_multi(int n, wc_lattice *const *lats, const void *const 
         for (int k = 0; k < n; k++) {
             arena_bind(bc->arena, k, bc->sys[k]);
             if (int rc = buf_get((void **)&bc->sys[k].partials, &bc->sys[k].partials_bytes,
-                                 sizeof(double) * kMaxRed * (size_t)lats[k]->nblocks, lead->stream)) {
+                                 sizeof(double) * kMaxRed * (size_t)blocks_of(lats[k]->Vh, kMinBlock),
+                                 lead->stream)) {
                 restore();
                 return rc;
             }
@@ -531,6 +533,7 @@ extern "C" int wc_set_link_recon(wc_lattice *lat, int recon) {
         if (int rc = build_recon8(lat)) return rc;
     }
     lat->recon = recon;
+    lat->bs_tuned[P32] = 0;  // the FP32 stencil changed: tune again
     lat->gen++;
     return WC_OK;
 }
@@ -601,6 +604,98 @@ static MultCall mult_call(int prec, int mode, int out_par, void *out, const void
     c.done = nullptr;
     return c;
 }
+
+// Time the inner loop's stencil pair (F_oo^-1 H_oe into the odd parity, then
+// the D-hat half with its fused dot) at each block size on zero vectors, and
+// keep the fastest; a smaller block must win by 3% to displace a larger one,
+// so that timing noise does not flip the choice on large lattices.
+int tune_block_size(wc_lattice *lat, int prec, double us[3], int *chosen) {
+    if (!lat->have_links || !lat->have_clover)
+        return wc_fail(WC_ENOTREADY, "block-size tuning needs links and clover");
+    const size_t sb = spinor_bytes(prec, lat->Vh);
+    char *buf = nullptr;
+    const size_t bytes = 3 * sb + 256;
+    if (int rc = dev_alloc((void **)&buf, bytes)) return rc;
+    int rc = WC_OK;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const bool timing = lat->timing;
+    const long dcount = lat->dslash_count;
+    lat->timing = false;
+    const int cand[3] = {64, 128, 256};
+    double t[3] = {0, 0, 0};
+    auto pair = [&](int bs) -> int {
+        MultCall c1 = mult_call(prec, M_HOPINV, 1, buf + sb, buf, nullptr, 0.0);
+        c1.bs = bs;
+        if (int r = launch_mult(lat, c1)) return r;
+        MultCall c2 = mult_call(prec, M_DHAT, 0, buf + 2 * sb, buf + sb, buf, -lat->kappa * lat->kappa);
+        c2.bs = bs;
+        c2.red = R_DOT;
+        c2.aux = buf;
+        c2.red_to = RedTarget{lat->sys.partials, (double *)(buf + 3 * sb)};
+        return launch_mult(lat, c2);
+    };
+    auto timed = [&](int bs, int reps, double *ms) -> int {
+        for (int w = 0; w < 2; w++)
+            if (int r = pair(bs)) return r;
+        WC_HIP(hipEventRecord(e0, lat->stream));
+        for (int r = 0; r < reps; r++)
+            if (int q = pair(bs)) return q;
+        WC_HIP(hipEventRecord(e1, lat->stream));
+        WC_HIP(hipEventSynchronize(e1));
+        float f = 0.f;
+        WC_HIP(hipEventElapsedTime(&f, e0, e1));
+        *ms = f / reps;
+        return WC_OK;
+    };
+    do {
+        if (hipMemsetAsync(buf, 0, bytes, lat->stream) != hipSuccess ||
+            hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+            rc = wc_fail(WC_EHIP, "block-size tuning: setting up buffers and events");
+            break;
+        }
+        // about 2 ms of pairs per candidate, between 4 and 64
+        double ms = 0;
+        if ((rc = timed(256, 2, &ms))) break;
+        const int reps = std::max(4, std::min(64, (int)(2.0 / std::max(ms, 1e-3))));
+        for (int c = 0; c < 3 && !rc; c++) rc = timed(cand[c], reps, &t[c]);
+    } while (false);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(lat->stream);
+    (void)hipFree(buf);
+    lat->timing = timing;
+    lat->dslash_count = dcount;
+    if (rc) return rc;
+    int best = 2;
+    for (int c = 1; c >= 0; c--)
+        if (t[c] < 0.97 * t[best]) best = c;
+    lat->bs_tuned[prec] = cand[best];
+    lat->gen++;  // captured graphs hold the old launch shape
+    if (us)
+        for (int c = 0; c < 3; c++) us[c] = t[c] * 1e3;
+    if (chosen) *chosen = cand[best];
+    return WC_OK;
+}
+
+extern "C" int wc_set_block_size(wc_lattice *lat, int threads) {
+    if (!lat) return wc_fail(WC_EINVAL, "null lattice");
+    if (threads != 0 && !valid_block_size(threads)) return wc_fail(WC_EINVAL, "block size must be 0, 64, 128 or 256");
+    if (threads != lat->bs_pin) lat->gen++;
+    lat->bs_pin = threads;
+    return WC_OK;
+}
+
+extern "C" int wc_block_size(const wc_lattice *lat, int prec) {
+    if (!lat || prec < 0 || prec > 2) return 0;
+    return lat->bs_pin ? lat->bs_pin : lat->bs_tuned[prec];
+}
+
+extern "C" int wc_tune_block_size(wc_lattice *lat, int prec, double us_per_pair[3], int *threads) {
+    if (!lat) return wc_fail(WC_EINVAL, "null lattice");
+    if (int rc = check_prec(prec)) return rc;
+    return tune_block_size(lat, prec, us_per_pair, threads);
+}
+
 
 extern "C" int wc_apply_D(wc_lattice *lat, void *out_dev, const void *in_dev, int prec) {
     if (!lat || !out_dev || !in_dev) return wc_fail(WC_EINVAL, "null argument");

@@ -167,7 +167,7 @@ __global__ __launch_bounds__(kBlock) void k_mult(MultBatch B) {
     batch_locate(B.h, xcd_block(blockIdx.x, gridDim.x), s, lb);
     const MultKArgs &a = B.d[s];
     if (a.done && *a.done) return;
-    const int i = lb * kBlock + threadIdx.x;
+    const int i = lb * (int)blockDim.x + threadIdx.x;  // 64, 128 or 256 sites per block
     const bool active = i < a.g.Vh;
     const int Vh = a.g.Vh;
     Spinor<R> out;
@@ -228,36 +228,37 @@ __global__ __launch_bounds__(kBlock) void k_mult(MultBatch B) {
     }
 }
 
-template <int P, int MODE, int RED, bool R8> void launch_nt(const MultBatch &B, int blocks, hipStream_t s) {
+template <int P, int MODE, int RED, bool R8> void launch_nt(const MultBatch &B, int blocks, int bs, hipStream_t s) {
     if (B.h.interleave)
-        hipLaunchKernelGGL((k_mult<P, MODE, RED, false, R8>), dim3(blocks), dim3(kBlock), 0, s, B);
+        hipLaunchKernelGGL((k_mult<P, MODE, RED, false, R8>), dim3(blocks), dim3(bs), 0, s, B);
     else
-        hipLaunchKernelGGL((k_mult<P, MODE, RED, true, R8>), dim3(blocks), dim3(kBlock), 0, s, B);
+        hipLaunchKernelGGL((k_mult<P, MODE, RED, true, R8>), dim3(blocks), dim3(bs), 0, s, B);
 }
 
 // reconstruct-8 instances exist for the FP32 stencil only
-template <int P, int MODE, int RED> void launch_one(const MultBatch &B, int blocks, hipStream_t s, bool r8) {
+template <int P, int MODE, int RED> void launch_one(const MultBatch &B, int blocks, int bs, hipStream_t s, bool r8) {
     if constexpr (P == P32) {
         if (r8) {
-            launch_nt<P, MODE, RED, true>(B, blocks, s);
+            launch_nt<P, MODE, RED, true>(B, blocks, bs, s);
             return;
         }
     }
-    launch_nt<P, MODE, RED, false>(B, blocks, s);
+    launch_nt<P, MODE, RED, false>(B, blocks, bs, s);
 }
 
-template <int P> void dispatch_mode(const MultBatch &B, int mode, int red, int blocks, hipStream_t s, bool r8) {
+template <int P>
+void dispatch_mode(const MultBatch &B, int mode, int red, int blocks, int bs, hipStream_t s, bool r8) {
     switch (mode) {
-    case M_HOPINV: launch_one<P, M_HOPINV, R_NONE>(B, blocks, s, r8); break;
+    case M_HOPINV: launch_one<P, M_HOPINV, R_NONE>(B, blocks, bs, s, r8); break;
     case M_DHAT:
-        if (red == R_DOT) launch_one<P, M_DHAT, R_DOT>(B, blocks, s, r8);
-        else if (red == R_DOTNORM) launch_one<P, M_DHAT, R_DOTNORM>(B, blocks, s, r8);
-        else launch_one<P, M_DHAT, R_NONE>(B, blocks, s, r8);
+        if (red == R_DOT) launch_one<P, M_DHAT, R_DOT>(B, blocks, bs, s, r8);
+        else if (red == R_DOTNORM) launch_one<P, M_DHAT, R_DOTNORM>(B, blocks, bs, s, r8);
+        else launch_one<P, M_DHAT, R_NONE>(B, blocks, bs, s, r8);
         break;
-    case M_DFULL: launch_one<P, M_DFULL, R_NONE>(B, blocks, s, r8); break;
-    case M_INVSRC: launch_one<P, M_INVSRC, R_NONE>(B, blocks, s, r8); break;
-    case M_HOP: launch_one<P, M_HOP, R_NONE>(B, blocks, s, r8); break;
-    case M_CLOV: launch_one<P, M_CLOV, R_NONE>(B, blocks, s, r8); break;
+    case M_DFULL: launch_one<P, M_DFULL, R_NONE>(B, blocks, bs, s, r8); break;
+    case M_INVSRC: launch_one<P, M_INVSRC, R_NONE>(B, blocks, bs, s, r8); break;
+    case M_HOP: launch_one<P, M_HOP, R_NONE>(B, blocks, bs, s, r8); break;
+    case M_CLOV: launch_one<P, M_CLOV, R_NONE>(B, blocks, bs, s, r8); break;
     }
 }
 
@@ -661,6 +662,8 @@ int launch_mult_batch(hipStream_t s, const MultCall *calls, int n, wc_lattice *t
     if (n <= 0) return WC_OK;
     if (n > kMaxSys) return wc_fail(WC_EINVAL, "too many systems in one batch");
     const MultCall &c0 = calls[0];
+    const int bs = launch_bs(c0.bs);
+    if (!valid_block_size(bs)) return wc_fail(WC_EINVAL, "block size must be 64, 128 or 256");
     MultBatch B;
     B.h.S = n;
     B.h.off[0] = 0;
@@ -672,6 +675,7 @@ int launch_mult_batch(hipStream_t s, const MultCall *calls, int n, wc_lattice *t
         wc_lattice *lat = c.lat;
         if (c.prec != c0.prec || c.mode != c0.mode || c.red != c0.red || c.out_par != c0.out_par)
             return wc_fail(WC_EINVAL, "batched stencil calls must share precision, mode, reduction and parity");
+        if (launch_bs(c.bs) != bs) return wc_fail(WC_EINVAL, "batched stencil calls must share the block size");
         same = same && (lat == c0.lat);
         MultKArgs &a = B.d[k];
         a.g = lat->g;
@@ -691,8 +695,8 @@ int launch_mult_batch(hipStream_t s, const MultCall *calls, int n, wc_lattice *t
         a.coef = c.coef;
         a.red = c.red_to;
         a.done = c.done;
-        a.nblk = lat->nblocks;
-        B.h.off[k + 1] = B.h.off[k] + lat->nblocks;
+        a.nblk = blocks_of(lat->Vh, bs);
+        B.h.off[k + 1] = B.h.off[k] + a.nblk;
         bytes += mult_spinor_bytes(c.prec, c.mode, c.red, c.aux == c.center, lat->Vh);
         bool seen = false;
         for (int j = 0; j < k; j++) seen = seen || (calls[j].lat == lat);
@@ -724,16 +728,16 @@ int launch_mult_batch(hipStream_t s, const MultCall *calls, int n, wc_lattice *t
             t.parts.push_back(op);
         }
     }
-    if (c0.prec == P64) dispatch_mode<P64>(B, c0.mode, c0.red, blocks, s, false);
-    else if (c0.prec == P32) dispatch_mode<P32>(B, c0.mode, c0.red, blocks, s, r8);
-    else dispatch_mode<P16>(B, c0.mode, c0.red, blocks, s, r8);
+    if (c0.prec == P64) dispatch_mode<P64>(B, c0.mode, c0.red, blocks, bs, s, false);
+    else if (c0.prec == P32) dispatch_mode<P32>(B, c0.mode, c0.red, blocks, bs, s, r8);
+    else dispatch_mode<P16>(B, c0.mode, c0.red, blocks, bs, s, r8);
     WC_HIP(hipGetLastError());
     if (tl->timing) timing_end(tl, t);
     if (c0.red != R_NONE && c0.mode == M_DHAT) {
         FinArgs f[kMaxSys];
         for (int k = 0; k < n; k++) {
             f[k] = FinArgs{};
-            f[k].blocks = calls[k].lat->nblocks;
+            f[k].blocks = blocks_of(calls[k].lat->Vh, bs);
             f[k].op = FIN_STORE;
             f[k].partials = calls[k].red_to.partials;
             f[k].result = calls[k].red_to.result;
@@ -773,7 +777,7 @@ int launch_inner_persistent(const PersistCall &c, hipStream_t s, bool *ran) {
     A.fl = c.fl;
     A.kappa2 = lat->kappa * lat->kappa;
     A.maxit = c.maxit;
-    A.nblk = lat->nblocks;
+    A.nblk = blocks_of(lat->Vh, kBlock);  // its own 256-thread layout
     // the runtime's barrier is the cheaper one for a handful of blocks only
     A.bar = A.nblk >= kOwnBarrierMinBlocks ? c.bar : nullptr;
     A.epoch = c.epoch;

@@ -42,6 +42,16 @@ enum DoneCode { DONE_NO = 0, DONE_FULL = 1, DONE_HALF = 2, DONE_BREAK = 4 };
 enum { NUM_LEVELS = 2 };  // 0 = inner loop, 1 = outer / FP64 loop
 constexpr int kMaxSys = 16;  // systems per batched launch
 constexpr int kMaxRed = 8;   // values one fused reduction may carry (partials are sized for it)
+// block sizes the solver's per-site kernels may run with (64-site tiles per
+// block: 1, 2 or 4); reduction partials are sized for the smallest
+constexpr int kMinBlock = 64;
+inline bool valid_block_size(int bs) { return bs == 64 || bs == 128 || bs == 256; }
+__host__ __device__ inline int blocks_of(int Vh, int bs) { return (Vh + bs - 1) / bs; }
+// block size of a launch given a call's field (0 = the default 256)
+inline int launch_bs(int bs) { return bs ? bs : 256; }
+// the block size that calls on lat in precision prec use now: pinned, else
+// tuned, else 256
+inline int lattice_bs(const wc_lattice *lat, int prec);
 constexpr float kRecon8MinN = 1e-6f;  // smallest |U01|^2 + |U02|^2 reconstruct-8 accepts
 
 // kinds of timed kernel launches
@@ -146,6 +156,10 @@ struct wc_lattice {
     int Vh;
     int nblocks;   // 256-thread blocks covering one parity
     hipStream_t stream = nullptr;
+    // threads per block of the solver's stencil and vector launches: pinned
+    // by the caller, else chosen per precision by the tuner (0 = not yet)
+    int bs_pin = 0;
+    int bs_tuned[3] = {0, 0, 0};
 
     // gauge links per precision: 8 slabs ([mu][parity]) of link_slab_bytes
     void *links[3] = {nullptr, nullptr, nullptr};
@@ -177,6 +191,12 @@ struct wc_lattice {
     std::vector<hipEvent_t> event_pool;
     long dslash_count = 0;
 };
+
+inline int lattice_bs(const wc_lattice *lat, int prec) {
+    if (lat->bs_pin) return lat->bs_pin;
+    const int t = lat->bs_tuned[prec];
+    return t ? t : 256;
+}
 
 // ---------------------------------------------------------------------------
 // error reporting (thread-local text behind wc_last_error)
@@ -268,13 +288,19 @@ struct MultCall {
     bool inverse;        // CLOV: use F^-1 instead of F
     RedTarget red_to;
     const int *done;     // skip this call when *done != 0
+    int bs;              // threads per block of the launch (64, 128 or 256; 0 = 256)
 };
 // timing_lat (default: the first call's lattice) receives the timing record
 int launch_mult_batch(hipStream_t s, const MultCall *calls, int n, wc_lattice *timing_lat = nullptr);
+// one call on lat; a call without a block size takes the lattice's
 inline int launch_mult(wc_lattice *lat, MultCall c) {
     c.lat = lat;
+    if (!c.bs) c.bs = lattice_bs(lat, c.prec);
     return launch_mult_batch(lat->stream, &c, 1);
 }
+// time the stencil pair of the inner loop at each block size and keep the
+// fastest for (lat, prec) (capi.cpp); us[3] and chosen may be null
+int tune_block_size(wc_lattice *lat, int prec, double us[3], int *chosen);
 
 // the inner loop of one system as a single cooperative launch (dslash.hip)
 struct PersistCall {
@@ -330,6 +356,7 @@ struct VecCall {
     int iter;          // iteration index, when not taken from the device
     int guard;         // skip when fl[F_DONE] != 0
     int iter_dev;      // take the iteration index from fl[F_ITERS] (inner loop)
+    int bs;            // threads per block of the launch (64, 128 or 256; 0 = 256)
 };
 // prec: storage precision of the inner vectors (the inner solution x is FP64
 // for an FP64 loop and FP32 otherwise).  timing_lat (may be null) receives the

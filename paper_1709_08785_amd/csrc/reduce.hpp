@@ -34,10 +34,11 @@ template <int N> __device__ __forceinline__ void block_fold(double (&v)[N], doub
     }
     __syncthreads();
     if (threadIdx.x == 0) {
+        const int nw = blockDim.x >> 6;  // 1, 2 or 4 waves
 #pragma unroll
         for (int k = 0; k < N; k++) {
             double s = 0.0;
-            for (int w = 0; w < kWaves; w++) s += sh[k][w];
+            for (int w = 0; w < nw; w++) s += sh[k][w];
             v[k] = s;
         }
     }

@@ -39,6 +39,7 @@ struct Run {
     bool use_graph;
     bool pipe;          // pipelined inner loop (two reduction phases per iteration)
     bool persistent;    // one cooperative launch per inner solve when the lattice allows
+    int bs;             // threads per block of every stencil and vector launch of the solve
     int iprec;
     double itol;
     int imaxit, omaxit, fixed_work, check_every;
@@ -68,6 +69,7 @@ MultCall mc(Run &R, int k, int prec, int mode, int out_par, void *out, const voi
     c.in = in;
     c.center = center;
     c.coef = coef;
+    c.bs = R.bs;
     return c;
 }
 
@@ -86,6 +88,7 @@ VecCall vc(Run &R, int k, int lvl, void *a, void *b = nullptr, void *c = nullptr
     v.fl = s.st->fl(lvl);
     v.partials = s.st->partials;
     v.tol2 = R.tol2_in[k];
+    v.bs = R.bs;
     return v;
 }
 
@@ -228,6 +231,7 @@ int inner_chunk_graph(Run &R, const std::vector<int> &act, int n) {
     mix((unsigned long long)R.iprec);
     mix((unsigned long long)n);
     mix((unsigned long long)R.pipe);
+    mix((unsigned long long)R.bs);
     for (int k : act) {
         mix((unsigned long long)k);
         mix((unsigned long long)(uintptr_t)S_(R, k).lat);
@@ -642,6 +646,18 @@ int solve_systems(std::vector<SolveSys> &sys, Arena &arena, double tol, const wc
     R.use_graph = P.use_graph != 0;
     R.pipe = P.inner_method == WC_INNER_PIPELINED;
     R.persistent = P.persistent != 0;
+    // block size: each lattice's pinned or tuned value for the inner
+    // precision (tuned now if neither); a batch over several lattices runs
+    // with the largest lattice's, which dominates its cost
+    {
+        wc_lattice *big = sys[0].lat;
+        for (auto &s : sys) {
+            if (!s.lat->bs_pin && !s.lat->bs_tuned[P.inner_prec])
+                if (int rc = tune_block_size(s.lat, P.inner_prec, nullptr, nullptr)) return rc;
+            if (s.lat->Vh > big->Vh) big = s.lat;
+        }
+        R.bs = lattice_bs(big, P.inner_prec);
+    }
     R.iprec = P.inner_prec;
     R.itol = P.inner_tol > 0.0 ? P.inner_tol : (P.inner_prec == WC_FP16 ? 1e-3 : 1e-6);
     R.imaxit = P.inner_maxit;
@@ -768,6 +784,7 @@ int solve_systems(std::vector<SolveSys> &sys, Arena &arena, double tol, const wc
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     for (int k = 0; k < S; k++) {
         sys[k].info.seconds = secs;
+        sys[k].info.block_size = R.bs;
         sys[k].info.dslash_count = R.dslash[k];
         sys[k].info.status = sys[k].status;
     }

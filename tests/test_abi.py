@@ -111,3 +111,16 @@ def test_params_and_info_layout_match_header(tmp_path):
     assert p.outer == 1
     with pytest.raises(TypeError):
         wc.Lattice.default_params(not_a_parameter=1)
+
+
+def test_binding_methods_are_callable_on_a_lattice():
+    # the binding's Lattice methods take the arguments their docstrings name;
+    # properties are reserved for read-only state
+    import inspect
+
+    import paper_1709_08785_amd as wc
+    for name in ("set_block_size", "block_size", "tune_block_size", "set_link_recon", "solve", "solve_batch"):
+        f = inspect.getattr_static(wc.Lattice, name)
+        assert inspect.isfunction(f), name
+    assert list(inspect.signature(wc.Lattice.set_block_size).parameters) == ["self", "threads"]
+    assert isinstance(inspect.getattr_static(wc.Lattice, "link_recon"), property)
