@@ -46,6 +46,9 @@ def test_persistent_solve_matches_oracle(dims, kappa, inner):
     U = synth.random_links(dims, 0.3, 1030)
     lat = wc.Lattice(dims)
     lat.load_links(dev(U))
+    # the launched loop with the one-launch kernel's 256-thread layout sums its
+    # reductions in the same order, so the iteration counts compare
+    lat.set_block_size(256)
     b = synth.gaussian_source(dims, 2030)
     x, info = lat.solve(dev(b), kappa, 1.0, 1e-12, inner_prec=inner, persistent=1)
     say(info)
@@ -81,6 +84,7 @@ def test_persistent_iteration_cap_and_fallback():
     U = synth.random_links(dims, 0.3, 1032)
     lat = wc.Lattice(dims)
     lat.load_links(dev(U))
+    lat.set_block_size(256)
     b = dev(synth.gaussian_source(dims, 2032))
     x, info = lat.solve(b, kappa, 1.0, 1e-12, persistent=1, inner_maxit=3, outer_maxit=2, raise_on_error=False)
     x2, info2 = lat.solve(b, kappa, 1.0, 1e-12, persistent=0, inner_maxit=3, outer_maxit=2, raise_on_error=False)
@@ -111,6 +115,7 @@ def test_persistent_own_barrier_matches_oracle(dims):
     U = synth.random_links(dims, 0.3, 1034)
     lat = wc.Lattice(dims)
     lat.load_links(dev(U))
+    lat.set_block_size(256)
     b = synth.gaussian_source(dims, 2034)
     x, info = lat.solve(dev(b), kappa, 1.0, 1e-12, persistent=1)
     say(info)
