@@ -60,6 +60,25 @@ def traffic_for(kernel: str, launches_bytes: float):
     return k.get("hbm_bytes_per_launch")
 
 
+# the paper's Table 1 flop counts per even site: MULT 2232 and D-hat 4512, so
+# the second half of D-hat (MULT plus the xpay) 2280; axpy 96, dot 96, norm 48.
+# One BiCGStab iteration (Algorithms 1 and 2 alike): two D-hat, three dots,
+# three norms and six axpy-like updates.
+T1_MULT, T1_DHAT = 2232, 4512
+T1_ITER = 2 * T1_DHAT + 3 * 96 + 3 * 48 + 6 * 96
+
+
+def table1_gflops(kname, Vh, avg_us):
+    """GFLOPS of one stencil launch at the Table 1 count, or None for other kernels."""
+    if kname.startswith("mult_hopinv"):
+        f = T1_MULT
+    elif kname.startswith("mult_dhat"):
+        f = T1_DHAT - T1_MULT
+    else:
+        return None
+    return round(f * Vh / (avg_us * 1e-6) / 1e9, 1)
+
+
 def cpu_baseline(U, b, dims, kappa, csw, budget_s=20.0):
     """The FP64 oracle (plain C, OpenMP) applying the full D on the same lattice."""
     import numpy as np
@@ -174,10 +193,12 @@ def dslash_mode(args, dims):
         st = lat.kernel_stats()
         for kname, v in st.items():
             if v["launches"]:
+                avg_us = v["ms"] / v["launches"] * 1e3
                 res[kname + ("_recon8" if recon == 8 else "")] = {
-                              "launches": v["launches"], "avg_us": round(v["ms"] / v["launches"] * 1e3, 2),
+                              "launches": v["launches"], "avg_us": round(avg_us, 2),
                               "algorithmic_GBs": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1),
                               "frac_hbm": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                              "GFLOPS_table1": table1_gflops(kname, lat.volume // 2, avg_us),
                               "bytes_per_launch": v["bytes"] / v["launches"]}
         lat.reset_kernel_stats()
         del eo, out
@@ -656,8 +677,12 @@ def main():
         "algorithmic_bytes_per_launch": per_launch_bytes,
     }
     kern = {k: {"launches": v["launches"], "avg_us": round(v["ms"] / v["launches"] * 1e3, 2),
-                "GBs": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1)}
+                "GBs": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1),
+                "GFLOPS_table1": table1_gflops(k, lat.volume // 2, v["ms"] / v["launches"] * 1e3)}
             for k, v in stats.items() if v["launches"] > 0}
+    # the whole step at the Table 1 counts: every inner and outer iteration
+    # costs two D-hat and the BLAS-1 of one BiCGStab iteration per even site
+    step_flops = T1_ITER * (lat.volume // 2) * (infos[-1]["inner_iters_total"] + infos[-1]["outer_iters"])
 
     # the all-FP64 arm on the same system
     fp64 = None
@@ -749,6 +774,7 @@ def main():
                                "dc_fp32_inner_recon8": dc["fp32_inner_recon8"]["seconds"] if dc else None,
                                "dc_fp16_inner": dc["fp16_inner"]["seconds"] if dc else None},
         "speedup_mixed_vs_fp64": round(fp64["seconds"] / (ms_per_step / 1e3), 3) if fp64 else None,
+        "solve_GFLOPS_table1": round(step_flops / (ms_per_step * 1e-3) / 1e9, 1),
         "fp64_arm": fp64,
         "fp16_inner_arm": fp16,
         "recon8_arms": recon8,
