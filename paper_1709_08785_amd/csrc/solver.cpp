@@ -331,7 +331,14 @@ int inner_solve(Run &R, const std::vector<int> &act, int src_id, int v_id) {
         c.fl = s.st->fl(L);
         c.maxit = maxit;
         c.bar = s.st->bar;
-        c.epoch = ++s.st->bar_epoch;
+        if (++s.st->bar_epoch == 0) {
+            // the call counter wrapped: clear the words so the new tags exceed them
+            const size_t words = (size_t)s.lat->nblocks + 2;  // as allocated with the lattice
+            if (hipMemsetAsync(s.st->bar, 0, words * sizeof(unsigned long long), R.stream) != hipSuccess)
+                return wc_fail(WC_EHIP, "clearing the grid barrier words");
+            s.st->bar_epoch = 1;
+        }
+        c.epoch = s.st->bar_epoch;
         bool ran = false;
         if (int rc = launch_inner_persistent(c, R.stream, &ran)) return rc;
         if (ran) {
