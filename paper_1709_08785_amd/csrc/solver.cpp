@@ -659,8 +659,11 @@ int solve_systems(std::vector<SolveSys> &sys, Arena &arena, double tol, const wc
     {
         wc_lattice *big = sys[0].lat;
         for (auto &s : sys) {
-            if (!s.lat->bs_pin && !s.lat->bs_tuned[P.inner_prec])
-                if (int rc = tune_block_size(s.lat, P.inner_prec, nullptr, nullptr)) return rc;
+            if (!s.lat->bs_pin && !s.lat->bs_tuned[P.inner_prec]) {
+                const int rc = tune_block_size(s.lat, P.inner_prec, nullptr, nullptr);
+                if (rc == WC_ENOMEM) s.lat->bs_tuned[P.inner_prec] = 256;  // no room to time: the default
+                else if (rc) return rc;
+            }
             if (s.lat->Vh > big->Vh) big = s.lat;
         }
         R.bs = lattice_bs(big, P.inner_prec);
