@@ -173,7 +173,7 @@ def dslash_mode(args, dims):
     psid = torch.from_numpy(psi).to(dev)
     res = {}
     for name, prec, recon in [("fp32", wc.FP32, 12), ("fp16", wc.FP16, 12), ("fp64", wc.FP64, 12),
-                              ("fp32", wc.FP32, 8)]:
+                              ("fp32", wc.FP32, 8), ("fp32", wc.FP32, 18)]:
         lat.set_link_recon(recon)
         eo = lat.pack(psid, prec)
         out = lat.new_eo(prec, 1)
@@ -194,7 +194,7 @@ def dslash_mode(args, dims):
         for kname, v in st.items():
             if v["launches"]:
                 avg_us = v["ms"] / v["launches"] * 1e3
-                res[kname + ("_recon8" if recon == 8 else "")] = {
+                res[kname + ("" if recon == 12 else "_recon%d" % recon)] = {
                               "launches": v["launches"], "avg_us": round(avg_us, 2),
                               "algorithmic_GBs": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1),
                               "frac_hbm": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
@@ -577,7 +577,7 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--inner-tol", type=float, default=1e-6)
     ap.add_argument("--inner", type=str, default="fp32")
-    ap.add_argument("--recon", type=int, default=12, choices=[12, 8])
+    ap.add_argument("--recon", type=int, default=12, choices=[12, 8, 18])
     ap.add_argument("--no-fp64-arm", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=1002)

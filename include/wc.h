@@ -165,15 +165,25 @@ int wc_set_stream(wc_lattice *lat, void *stream);
 /* Copy gauge links (canonical complex128 layout, device pointer) into the internal
    FP64, FP32 and FP16 copies.  FP32 and FP16 keep the first two columns of each
    matrix and rebuild the third as conj(col0 x col1) (SU(3) reconstruction,
-   Sec. III-A); this is exact only for special-unitary links.  Invalidates the
-   clover term. */
+   Sec. III-A); this is exact only for special-unitary links.  The call
+   measures, in FP64, the largest |third column - conj(col0 x col1)| entry over
+   all links (wc_link_su3_error; it synchronises the stream).  Above 1e-5 the
+   links are not SU(3) to single precision: the lattice then switches the FP32
+   stencil to full links (wc_set_link_recon 18) and refuses FP16 stencil work
+   (WC_EINVAL); a later load of SU(3) links returns it to 12 unless the caller
+   chose the form.  Invalidates the clover term. */
 int wc_load_links(wc_lattice *lat, const void *U_dev);
+/* The reconstruction error measured by the last wc_load_links (0 before any; -1
+   for a null lattice). */
+double wc_link_su3_error(const wc_lattice *lat);
 
 /* Choose how the FP32 stencil stores links (Sec. III-A: each MULT reads every
    link once, so links are 44% of its bytes): recon = 12 (default, two columns,
-   48 B) or 8 (eight reals, 32 B: U01, U02, the smaller in modulus of U10 and
+   48 B), 8 (eight reals, 32 B: U01, U02, the smaller in modulus of U10 and
    U20, and the phases of U00 and of the other one; the remaining entries follow
-   from unitarity and det U = 1, exact up to a few FP32 rounding steps).  FP64
+   from unitarity and det U = 1, exact up to a few FP32 rounding steps) or 18
+   (the full matrix, 72 B: for links that are not SU(3); 12 and 8 are refused
+   with WC_EINVAL for such links).  FP64
    always keeps full matrices; FP16 always keeps two columns (rebuilding from
    eight half-precision reals loses too many of its bits).  recon = 8 builds the
    extra copy from the loaded links and returns WC_EINVAL, leaving the setting
@@ -184,7 +194,7 @@ int wc_load_links(wc_lattice *lat, const void *U_dev);
    later FP32 apply and solve on this lattice; one batched solve needs the same
    setting on all its lattices. */
 int wc_set_link_recon(wc_lattice *lat, int recon);
-/* The current setting (12 or 8); 0 for a null lattice. */
+/* The current setting (12, 8 or 18); 0 for a null lattice. */
 int wc_link_recon(const wc_lattice *lat);
 
 /* Build the clover term F (Sec. II-A) from the loaded links in FP64, split into

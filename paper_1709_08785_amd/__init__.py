@@ -101,6 +101,7 @@ def load_library():
         "wc_last_error": (ctypes.c_char_p, []),
         "wc_set_barrier_timeout": (I, [D]),
         "wc_set_block_size": (I, [P, I]),
+        "wc_link_su3_error": (D, [P]),
         "wc_block_size": (I, [P, I]),
         "wc_tune_block_size": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(I)]),
     }
@@ -180,9 +181,14 @@ class Lattice:
             self._links_key = key
 
     def set_link_recon(self, recon: int):
-        """Link storage of the FP32/FP16 stencils: 12 (two columns) or 8 (eight reals)."""
+        """Link storage of the FP32 stencil: 12 (two columns), 8 (eight reals) or 18 (full)."""
         self._sync_stream()
         _check(self.lib.wc_set_link_recon(self.h, int(recon)))
+
+    @property
+    def link_su3_error(self) -> float:
+        """Largest |third column - conj(col0 x col1)| of the loaded links (FP64)."""
+        return float(self.lib.wc_link_su3_error(self.h))
 
     def set_block_size(self, threads: int):
         """Pin the solver kernels' threads per block (64, 128, 256), or 0 to tune."""

@@ -244,7 +244,9 @@ static void free_all(wc_lattice *lat) {
         if (lat->clovinv[p]) (void)hipFree(lat->clovinv[p]);
     }
     if (lat->links8) (void)hipFree(lat->links8);
+    if (lat->links18) (void)hipFree(lat->links18);
     if (lat->recon_min) (void)hipFree(lat->recon_min);
+    if (lat->recon_err) (void)hipFree(lat->recon_err);
     for (int k = 0; k < LW_COUNT; k++)
         if (lat->lwork[k]) (void)hipFree(lat->lwork[k]);
     free_work(lat->swork);
@@ -334,6 +336,8 @@ extern "C" void wc_solve_params_default(wc_solve_params *p) {
     p->persistent = 0;
 }
 
+static int check_links_for(const wc_lattice *lat, int prec);
+
 static int check_params(const wc_solve_params &P, double tol) {
     if (!(tol > 0.0) || !(tol < 1.0)) return wc_fail(WC_EINVAL, "tol must lie in (0, 1)");
     if (P.inner_prec < 0 || P.inner_prec > 2) return wc_fail(WC_EINVAL, "bad inner precision");
@@ -374,6 +378,7 @@ extern "C" int wc_solve(wc_lattice *lat, const void *b_dev, double kappa, double
     wc_solve_params_default(&P);
     if (pin) P = *pin;
     if (int rc = check_params(P, tol)) return rc;
+    if (int rc = check_links_for(lat, P.inner_prec)) return rc;
     if (int rc = prepare_lattice(lat, kappa, csw)) return rc;
     if (int rc = ensure_work(lat, lat->swork, P.inner_prec, P.inner_method == WC_INNER_PIPELINED, lat->arena)) return rc;
     std::vector<SolveSys> sys(1);
@@ -405,6 +410,7 @@ extern "C" int wc_solve_multi(int n, wc_lattice *const *lats, const void *const 
                 return wc_fail(WC_EINVAL, "systems on one lattice must share kappa and csw");
         if (lats[k]->recon != lats[0]->recon)
             return wc_fail(WC_EINVAL, "lattices of one batched solve must share the link reconstruction");
+        if (int rc = check_links_for(lats[k], P.inner_prec)) return rc;
         if (int rc = prepare_lattice(lats[k], kappa[k], csw[k])) return rc;
     }
     wc_lattice *lead = lats[0];
@@ -502,6 +508,24 @@ static int build_recon8(wc_lattice *lat) {
     return WC_OK;
 }
 
+// the full FP32 copies of the current links
+static int build_full32(wc_lattice *lat) {
+    if (!lat->links18) {
+        int rc = dev_alloc(&lat->links18, 8 * link18_slab_bytes(lat->Vh));
+        if (rc) return rc;
+    }
+    return launch_links_full32(lat);
+}
+
+static void set_recon(wc_lattice *lat, int recon, bool automatic) {
+    if (recon != lat->recon) {
+        lat->recon = recon;
+        lat->bs_tuned[P32] = 0;  // the FP32 stencil changed: tune again
+        lat->gen++;
+    }
+    lat->recon_auto = automatic;
+}
+
 extern "C" int wc_load_links(wc_lattice *lat, const void *U_dev) {
     if (!lat || !U_dev) return wc_fail(WC_EINVAL, "null lattice or link pointer");
     for (int p = 0; p < 3; p++) {
@@ -510,15 +534,33 @@ extern "C" int wc_load_links(wc_lattice *lat, const void *U_dev) {
             if (rc) return rc;
         }
     }
-    int rc = launch_load_links(lat, U_dev);
+    if (!lat->recon_err) {
+        int rc = dev_alloc((void **)&lat->recon_err, sizeof(unsigned));
+        if (rc) return rc;
+    }
+    WC_HIP(hipMemsetAsync(lat->recon_err, 0, sizeof(unsigned), lat->stream));
+    int rc = launch_load_links(lat, U_dev, lat->recon_err);
     if (rc) return rc;
+    unsigned bits = 0;
+    WC_HIP(hipMemcpyAsync(&bits, lat->recon_err, sizeof(bits), hipMemcpyDeviceToHost, lat->stream));
+    WC_HIP(hipStreamSynchronize(lat->stream));
+    std::memcpy(&lat->su3_err, &bits, sizeof(bits));
     lat->gen++;
     lat->have_links = true;
     lat->have_clover = false;
+    if (lat->su3_err > kSU3MaxErr) {
+        // not SU(3) to single precision: no two-column form holds, so the
+        // FP32 stencil reads the links in full (FP16 is refused)
+        if (int r = build_full32(lat)) return r;
+        if (lat->recon != 18) set_recon(lat, 18, true);
+        return WC_OK;
+    }
+    if (lat->recon_auto) set_recon(lat, 12, false);  // SU(3) again: back to the default
+    if (lat->recon == 18) return build_full32(lat);
     if (lat->recon == 8) {
         // keep the reconstruct-8 copies in step; links they cannot hold switch it off
         rc = build_recon8(lat);
-        if (rc) lat->recon = 12;
+        if (rc) set_recon(lat, 12, false);
         return rc;
     }
     return WC_OK;
@@ -526,17 +568,27 @@ extern "C" int wc_load_links(wc_lattice *lat, const void *U_dev) {
 
 extern "C" int wc_set_link_recon(wc_lattice *lat, int recon) {
     if (!lat) return wc_fail(WC_EINVAL, "null lattice");
-    if (recon != 12 && recon != 8) return wc_fail(WC_EINVAL, "link reconstruction must be 12 or 8");
-    if (recon == lat->recon) return WC_OK;
+    if (recon != 12 && recon != 8 && recon != 18) return wc_fail(WC_EINVAL, "link form must be 12, 8 or 18");
+    if (recon != 18 && lat->have_links && lat->su3_err > kSU3MaxErr)
+        return wc_fail(WC_EINVAL, "the loaded links are not SU(3) to single precision (largest third-column error " +
+                                      std::to_string(lat->su3_err) + "); only the full form 18 holds them");
+    if (recon == lat->recon) {
+        lat->recon_auto = false;
+        return WC_OK;
+    }
     if (recon == 8) {
         if (!lat->have_links) return wc_fail(WC_ENOTREADY, "wc_set_link_recon(8) before wc_load_links");
         if (int rc = build_recon8(lat)) return rc;
     }
-    lat->recon = recon;
-    lat->bs_tuned[P32] = 0;  // the FP32 stencil changed: tune again
-    lat->gen++;
+    if (recon == 18) {
+        if (!lat->have_links) return wc_fail(WC_ENOTREADY, "wc_set_link_recon(18) before wc_load_links");
+        if (int rc = build_full32(lat)) return rc;
+    }
+    set_recon(lat, recon, false);
     return WC_OK;
 }
+
+extern "C" double wc_link_su3_error(const wc_lattice *lat) { return lat ? (double)lat->su3_err : -1.0; }
 
 extern "C" int wc_link_recon(const wc_lattice *lat) { return lat ? lat->recon : 0; }
 
@@ -566,6 +618,14 @@ extern "C" int wc_build_clover(wc_lattice *lat, double kappa, double csw) {
 
 static int check_prec(int prec) {
     if (prec < 0 || prec > 2) return wc_fail(WC_EINVAL, "precision must be WC_FP64, WC_FP32 or WC_FP16");
+    return WC_OK;
+}
+
+// the FP16 stencil keeps two link columns, valid for SU(3) links only
+static int check_links_for(const wc_lattice *lat, int prec) {
+    if (prec == WC_FP16 && lat->have_links && lat->su3_err > kSU3MaxErr)
+        return wc_fail(WC_EINVAL, "the loaded links are not SU(3) to single precision (largest third-column error " +
+                                      std::to_string(lat->su3_err) + "); the FP16 stencil keeps two columns");
     return WC_OK;
 }
 
@@ -720,6 +780,7 @@ extern "C" int wc_apply_mult(wc_lattice *lat, void *out, const void *in, int out
     if (int rc = check_prec(prec)) return rc;
     if (out_parity != 0 && out_parity != 1) return wc_fail(WC_EINVAL, "out_parity must be 0 or 1");
     if (int rc = check_ready(lat)) return rc;
+    if (int rc = check_links_for(lat, prec)) return rc;
     MultCall c = mult_call(prec, M_HOPINV, out_parity, out, in, nullptr, 0.0);
     return launch_mult(lat, c);
 }
@@ -729,6 +790,7 @@ extern "C" int wc_apply_Dee_oo(wc_lattice *lat, void *out_e, const void *in_e, i
     if (int rc = check_prec(prec)) return rc;
     if (out_e == in_e) return wc_fail(WC_EINVAL, "wc_apply_Dee_oo cannot work in place");
     if (int rc = check_ready(lat)) return rc;
+    if (int rc = check_links_for(lat, prec)) return rc;
     void *tmp;
     if (int rc = lwork(lat, LW_APPLY_TMP, spinor_bytes(prec, lat->Vh), &tmp)) return rc;
     MultCall c1 = mult_call(prec, M_HOPINV, 1, tmp, in_e, nullptr, 0.0);

@@ -168,6 +168,7 @@ typedef float nt_f4 __attribute__((ext_vector_type(4)));
 typedef double nt_d2 __attribute__((ext_vector_type(2)));
 typedef unsigned int nt_u4 __attribute__((ext_vector_type(4)));
 typedef unsigned int nt_u2 __attribute__((ext_vector_type(2)));
+typedef float nt_f2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ float4 ld_stream(const float4 *p) {
     nt_f4 v = __builtin_nontemporal_load((const nt_f4 *)p);
     return make_float4(v.x, v.y, v.z, v.w);
@@ -183,6 +184,10 @@ __device__ __forceinline__ uint4 ld_stream(const uint4 *p) {
 __device__ __forceinline__ uint2 ld_stream(const uint2 *p) {
     nt_u2 v = __builtin_nontemporal_load((const nt_u2 *)p);
     return make_uint2(v.x, v.y);
+}
+__device__ __forceinline__ float2 ld_stream(const float2 *p) {
+    nt_f2 v = __builtin_nontemporal_load((const nt_f2 *)p);
+    return make_float2(v.x, v.y);
 }
 __device__ __forceinline__ float ld_stream(const float *p) { return __builtin_nontemporal_load(p); }
 __device__ __forceinline__ void st_stream(float4 *p, float4 v) {
@@ -438,15 +443,44 @@ struct Link8IO {
     }
 };
 
-// the link accessor a stencil instance uses: R8 selects reconstruct-8 (FP32 only)
-template <int P, bool R8> struct LinkLoad {
+// ---------------------------------------------------------------------------
+// links stored in full (18 reals), FP32: for links that are not SU(3) to FP32
+// accuracy, where neither reconstruction holds.  Row-major entries 0..7 in
+// four float4 planes, entry 8 in a float2 plane                 (72 B/site)
+// ---------------------------------------------------------------------------
+WC_HD size_t link18_slab_bytes(int Vh) { return (size_t)pad_sites(Vh) * 72; }
+
+struct Link18IO {
+    template <bool NT = true> __device__ static Mat3<float> load(const void *slab, int Vh, int i) {
+        Mat3<float> u;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const float4 a = ld_op<NT>(tp<float4, 72>(slab, i, 16 * k));
+            u.m[2 * k] = {a.x, a.y};
+            u.m[2 * k + 1] = {a.z, a.w};
+        }
+        const float2 b = ld_op<NT>(tp<float2, 72>(slab, i, 64));
+        u.m[8] = {b.x, b.y};
+        return u;
+    }
+};
+
+// the link accessor a stencil instance uses: LR is the link form, 12 (two
+// columns, the third rebuilt), 8 (reconstruct-8) or 18 (full); the last two
+// exist for the FP32 stencil only
+template <int P, int LR> struct LinkLoad {
     template <bool NT> __device__ static Mat3<typename Real<P>::T> load(const void *slab, int Vh, int i) {
         return LinkIO<P>::template load<NT>(slab, Vh, i);
     }
 };
-template <> struct LinkLoad<P32, true> {
+template <> struct LinkLoad<P32, 8> {
     template <bool NT> __device__ static Mat3<float> load(const void *slab, int Vh, int i) {
         return Link8IO::template load<NT>(slab, Vh, i);
+    }
+};
+template <> struct LinkLoad<P32, 18> {
+    template <bool NT> __device__ static Mat3<float> load(const void *slab, int Vh, int i) {
+        return Link18IO::template load<NT>(slab, Vh, i);
     }
 };
 

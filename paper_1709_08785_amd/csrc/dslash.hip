@@ -132,20 +132,20 @@ __device__ __forceinline__ void hop_one(const void *in, int Vh, int n, const Mat
     }
 }
 
-template <int P, int MU, bool NT, bool R8>
+template <int P, int MU, bool NT, int LR>
 __device__ __forceinline__ void hop_dir(const MultKArgs &a, const SiteCoord &c, int i,
                                         Spinor<typename Real<P>::T> &acc) {
     using R = typename Real<P>::T;
     const int Vh = a.g.Vh;
     {
         const int nf = eo_neighbour(a.g, c, MU, +1);
-        const Mat3<R> U = LinkLoad<P, R8>::template load<NT>(a.links + (size_t)(2 * MU + a.out_par) * a.link_slab, Vh, i);
+        const Mat3<R> U = LinkLoad<P, LR>::template load<NT>(a.links + (size_t)(2 * MU + a.out_par) * a.link_slab, Vh, i);
         hop_one<P, MU, true>(a.in, Vh, nf, U, acc);
     }
     {
         const int nb = eo_neighbour(a.g, c, MU, -1);
         const Mat3<R> U =
-            LinkLoad<P, R8>::template load<NT>(a.links + (size_t)(2 * MU + 1 - a.out_par) * a.link_slab, Vh, nb);
+            LinkLoad<P, LR>::template load<NT>(a.links + (size_t)(2 * MU + 1 - a.out_par) * a.link_slab, Vh, nb);
         hop_one<P, MU, false>(a.in, Vh, nb, U, acc);
     }
 }
@@ -160,7 +160,7 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 // NT: links and clover read once per launch (one system) use non-temporal
 // loads; a launch that serves several systems on one lattice reads them
 // through the cache so that the blocks of the other systems hit in L2
-template <int P, int MODE, int RED, bool NT, bool R8>
+template <int P, int MODE, int RED, bool NT, int LR>
 __global__ __launch_bounds__(kBlock) void k_mult(MultBatch B) {
     using R = typename Real<P>::T;
     int s, lb;
@@ -177,10 +177,10 @@ __global__ __launch_bounds__(kBlock) void k_mult(MultBatch B) {
         for (int k = 0; k < 12; k++) acc.c[k] = {R(0), R(0)};
         if (MODE != M_CLOV) {
             const SiteCoord c = eo_coords(a.g, i, a.out_par);
-            hop_dir<P, 0, NT, R8>(a, c, i, acc);
-            hop_dir<P, 1, NT, R8>(a, c, i, acc);
-            hop_dir<P, 2, NT, R8>(a, c, i, acc);
-            hop_dir<P, 3, NT, R8>(a, c, i, acc);
+            hop_dir<P, 0, NT, LR>(a, c, i, acc);
+            hop_dir<P, 1, NT, LR>(a, c, i, acc);
+            hop_dir<P, 2, NT, LR>(a, c, i, acc);
+            hop_dir<P, 3, NT, LR>(a, c, i, acc);
         }
         const R coef = (R)a.coef;
         if (MODE == M_HOPINV) {
@@ -228,37 +228,41 @@ __global__ __launch_bounds__(kBlock) void k_mult(MultBatch B) {
     }
 }
 
-template <int P, int MODE, int RED, bool R8> void launch_nt(const MultBatch &B, int blocks, int bs, hipStream_t s) {
+template <int P, int MODE, int RED, int LR> void launch_nt(const MultBatch &B, int blocks, int bs, hipStream_t s) {
     if (B.h.interleave)
-        hipLaunchKernelGGL((k_mult<P, MODE, RED, false, R8>), dim3(blocks), dim3(bs), 0, s, B);
+        hipLaunchKernelGGL((k_mult<P, MODE, RED, false, LR>), dim3(blocks), dim3(bs), 0, s, B);
     else
-        hipLaunchKernelGGL((k_mult<P, MODE, RED, true, R8>), dim3(blocks), dim3(bs), 0, s, B);
+        hipLaunchKernelGGL((k_mult<P, MODE, RED, true, LR>), dim3(blocks), dim3(bs), 0, s, B);
 }
 
-// reconstruct-8 instances exist for the FP32 stencil only
-template <int P, int MODE, int RED> void launch_one(const MultBatch &B, int blocks, int bs, hipStream_t s, bool r8) {
+// reconstruct-8 and full-link instances exist for the FP32 stencil only
+template <int P, int MODE, int RED> void launch_one(const MultBatch &B, int blocks, int bs, hipStream_t s, int lr) {
     if constexpr (P == P32) {
-        if (r8) {
-            launch_nt<P, MODE, RED, true>(B, blocks, bs, s);
+        if (lr == 8) {
+            launch_nt<P, MODE, RED, 8>(B, blocks, bs, s);
+            return;
+        }
+        if (lr == 18) {
+            launch_nt<P, MODE, RED, 18>(B, blocks, bs, s);
             return;
         }
     }
-    launch_nt<P, MODE, RED, false>(B, blocks, bs, s);
+    launch_nt<P, MODE, RED, 12>(B, blocks, bs, s);
 }
 
 template <int P>
-void dispatch_mode(const MultBatch &B, int mode, int red, int blocks, int bs, hipStream_t s, bool r8) {
+void dispatch_mode(const MultBatch &B, int mode, int red, int blocks, int bs, hipStream_t s, int lr) {
     switch (mode) {
-    case M_HOPINV: launch_one<P, M_HOPINV, R_NONE>(B, blocks, bs, s, r8); break;
+    case M_HOPINV: launch_one<P, M_HOPINV, R_NONE>(B, blocks, bs, s, lr); break;
     case M_DHAT:
-        if (red == R_DOT) launch_one<P, M_DHAT, R_DOT>(B, blocks, bs, s, r8);
-        else if (red == R_DOTNORM) launch_one<P, M_DHAT, R_DOTNORM>(B, blocks, bs, s, r8);
-        else launch_one<P, M_DHAT, R_NONE>(B, blocks, bs, s, r8);
+        if (red == R_DOT) launch_one<P, M_DHAT, R_DOT>(B, blocks, bs, s, lr);
+        else if (red == R_DOTNORM) launch_one<P, M_DHAT, R_DOTNORM>(B, blocks, bs, s, lr);
+        else launch_one<P, M_DHAT, R_NONE>(B, blocks, bs, s, lr);
         break;
-    case M_DFULL: launch_one<P, M_DFULL, R_NONE>(B, blocks, bs, s, r8); break;
-    case M_INVSRC: launch_one<P, M_INVSRC, R_NONE>(B, blocks, bs, s, r8); break;
-    case M_HOP: launch_one<P, M_HOP, R_NONE>(B, blocks, bs, s, r8); break;
-    case M_CLOV: launch_one<P, M_CLOV, R_NONE>(B, blocks, bs, s, r8); break;
+    case M_DFULL: launch_one<P, M_DFULL, R_NONE>(B, blocks, bs, s, lr); break;
+    case M_INVSRC: launch_one<P, M_INVSRC, R_NONE>(B, blocks, bs, s, lr); break;
+    case M_HOP: launch_one<P, M_HOP, R_NONE>(B, blocks, bs, s, lr); break;
+    case M_CLOV: launch_one<P, M_CLOV, R_NONE>(B, blocks, bs, s, lr); break;
     }
 }
 
@@ -273,9 +277,10 @@ double mult_spinor_bytes(int prec, int mode, int red, bool aux_is_centre, int Vh
     if (red != R_NONE && !aux_is_centre) b += S;                         // aux vector, unless the centre
     return b;
 }
-double mult_operator_bytes(int prec, int mode, bool r8, int Vh) {
+double mult_operator_bytes(int prec, int mode, int lr, int Vh) {
     double b = 0;
-    if (mode != M_CLOV) b += 8 * (double)(r8 ? 32 : link_site_bytes(prec)) * Vh;
+    const int lb = lr == 8 ? 32 : lr == 18 ? 72 : link_site_bytes(prec);
+    if (mode != M_CLOV) b += 8 * (double)lb * Vh;
     if (mode != M_HOP) b += (double)clover_site_bytes(prec) * Vh;
     return b;
 }
@@ -413,7 +418,7 @@ template <int N> __device__ __forceinline__ void sum_partials(const double *part
 }
 
 // out = F^-1 H in (one parity), the MULT of the launched path
-template <int P, bool R8>
+template <int P, int LR>
 __device__ __forceinline__ Spinor<typename Real<P>::T> mult_site(const PersistArgs &A, const void *in, int out_par,
                                                                      const void *clov, int i) {
     using R = typename Real<P>::T;
@@ -427,10 +432,10 @@ __device__ __forceinline__ Spinor<typename Real<P>::T> mult_site(const PersistAr
 #pragma unroll
     for (int k = 0; k < 12; k++) acc.c[k] = {R(0), R(0)};
     const SiteCoord c = eo_coords(A.g, i, out_par);
-    hop_dir<P, 0, false, R8>(a, c, i, acc);
-    hop_dir<P, 1, false, R8>(a, c, i, acc);
-    hop_dir<P, 2, false, R8>(a, c, i, acc);
-    hop_dir<P, 3, false, R8>(a, c, i, acc);
+    hop_dir<P, 0, false, LR>(a, c, i, acc);
+    hop_dir<P, 1, false, LR>(a, c, i, acc);
+    hop_dir<P, 2, false, LR>(a, c, i, acc);
+    hop_dir<P, 3, false, LR>(a, c, i, acc);
     clover_apply<P, R, false>(clov, A.g.Vh, i, acc, out);
     return out;
 }
@@ -445,7 +450,7 @@ template <class R> __device__ __forceinline__ cx<R> to_r(cx<double> a) { return 
 // single instance keeps the register allocation that of one stencil launch;
 // the scalars every thread needs (rho, alpha) stay in registers, the ones
 // only the final write-out needs sit in LDS.
-template <int P, bool R8, bool OWN>
+template <int P, int LR, bool OWN>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(P == P64 ? 1 : 2))) void k_inner_persistent(PersistArgs A) {
     using R = typename Real<P>::T;
     constexpr int XP = P == P64 ? P64 : P32;
@@ -470,7 +475,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(P == P64
         const bool second = stage >= 2;
         const void *v = second ? A.r : A.p;  // p, or s (held in r)
         Spinor<R> h;
-        if (active) h = mult_site<P, R8>(A, mult ? v : A.tmp, mult ? 1 : 0, mult ? A.clov_o : A.clov_e, i);
+        if (active) h = mult_site<P, LR>(A, mult ? v : A.tmp, mult ? 1 : 0, mult ? A.clov_o : A.clov_e, i);
         if (mult) {
             if (active) SpinorIO<P>::store(A.tmp, Vh, i, h);
             if (!grid_barrier<OWN>(A, tag, lb)) {
@@ -669,7 +674,7 @@ int launch_mult_batch(hipStream_t s, const MultCall *calls, int n, wc_lattice *t
     B.h.off[0] = 0;
     bool same = true;
     double bytes = 0;
-    const bool r8 = c0.prec == P32 && c0.lat->recon == 8;
+    const int lr = c0.prec == P32 ? c0.lat->recon : 12;  // link form of the FP32 stencil
     for (int k = 0; k < n; k++) {
         const MultCall &c = calls[k];
         wc_lattice *lat = c.lat;
@@ -684,10 +689,10 @@ int launch_mult_batch(hipStream_t s, const MultCall *calls, int n, wc_lattice *t
         a.in = c.in;
         a.center = c.center;
         a.aux = c.aux;
-        if ((c.prec == P32 && lat->recon == 8) != r8)
+        if ((c.prec == P32 ? lat->recon : 12) != lr)
             return wc_fail(WC_EINVAL, "batched stencil calls must share the link reconstruction");
-        a.links = (const char *)(r8 ? lat->links8 : lat->links[c.prec]);
-        a.link_slab = r8 ? link8_slab_bytes(lat->Vh) : link_slab_bytes(c.prec, lat->Vh);
+        a.links = (const char *)link_base(lat, c.prec);
+        a.link_slab = link_slab_for(lat, c.prec);
         const bool use_inv = (c.mode == M_HOPINV || c.mode == M_DHAT || c.mode == M_INVSRC ||
                               (c.mode == M_CLOV && c.inverse));
         const char *cb = (const char *)(use_inv ? lat->clovinv[c.prec] : lat->clov[c.prec]);
@@ -700,7 +705,7 @@ int launch_mult_batch(hipStream_t s, const MultCall *calls, int n, wc_lattice *t
         bytes += mult_spinor_bytes(c.prec, c.mode, c.red, c.aux == c.center, lat->Vh);
         bool seen = false;
         for (int j = 0; j < k; j++) seen = seen || (calls[j].lat == lat);
-        if (!seen) bytes += mult_operator_bytes(c.prec, c.mode, r8, lat->Vh);
+        if (!seen) bytes += mult_operator_bytes(c.prec, c.mode, lr, lat->Vh);
         if (c.mode != M_CLOV) lat->dslash_count++;
     }
     B.h.interleave = (same && n > 1) ? 1 : 0;
@@ -722,15 +727,15 @@ int launch_mult_batch(hipStream_t s, const MultCall *calls, int n, wc_lattice *t
             bool seen = false;
             for (int j = 0; j < k; j++) seen = seen || (calls[j].lat == c.lat);
             if (seen) continue;
-            TimedPart op{{}, mult_operator_bytes(c.prec, c.mode, r8, c.lat->Vh)};
+            TimedPart op{{}, mult_operator_bytes(c.prec, c.mode, lr, c.lat->Vh)};
             for (int j = k; j < n; j++)
                 if (calls[j].lat == c.lat) op.owners.push_back(calls[j].done);
             t.parts.push_back(op);
         }
     }
-    if (c0.prec == P64) dispatch_mode<P64>(B, c0.mode, c0.red, blocks, bs, s, false);
-    else if (c0.prec == P32) dispatch_mode<P32>(B, c0.mode, c0.red, blocks, bs, s, r8);
-    else dispatch_mode<P16>(B, c0.mode, c0.red, blocks, bs, s, r8);
+    if (c0.prec == P64) dispatch_mode<P64>(B, c0.mode, c0.red, blocks, bs, s, 12);
+    else if (c0.prec == P32) dispatch_mode<P32>(B, c0.mode, c0.red, blocks, bs, s, lr);
+    else dispatch_mode<P16>(B, c0.mode, c0.red, blocks, bs, s, 12);
     WC_HIP(hipGetLastError());
     if (tl->timing) timing_end(tl, t);
     if (c0.red != R_NONE && c0.mode == M_DHAT) {
@@ -756,11 +761,11 @@ double g_barrier_timeout_s = 2.0;
 int launch_inner_persistent(const PersistCall &c, hipStream_t s, bool *ran) {
     *ran = false;
     wc_lattice *lat = c.lat;
-    const bool r8 = c.prec == P32 && lat->recon == 8;
+    const int lr = c.prec == P32 ? lat->recon : 12;
     PersistArgs A;
     A.g = lat->g;
-    A.links = (const char *)(r8 ? lat->links8 : lat->links[c.prec]);
-    A.link_slab = r8 ? link8_slab_bytes(lat->Vh) : link_slab_bytes(c.prec, lat->Vh);
+    A.links = (const char *)link_base(lat, c.prec);
+    A.link_slab = link_slab_for(lat, c.prec);
     const char *ci = (const char *)lat->clovinv[c.prec];
     A.clov_e = ci;
     A.clov_o = ci + clover_slab_bytes(c.prec, lat->Vh);
@@ -783,14 +788,16 @@ int launch_inner_persistent(const PersistCall &c, hipStream_t s, bool *ran) {
     A.epoch = c.epoch;
     A.tag0 = (unsigned long long)c.epoch << 32;
     const bool own = A.bar != nullptr;
-    const void *fn = c.prec == P64 ? (own ? (const void *)k_inner_persistent<P64, false, true>
-                                          : (const void *)k_inner_persistent<P64, false, false>)
-                     : c.prec == P16 ? (own ? (const void *)k_inner_persistent<P16, false, true>
-                                            : (const void *)k_inner_persistent<P16, false, false>)
-                     : r8 ? (own ? (const void *)k_inner_persistent<P32, true, true>
-                                 : (const void *)k_inner_persistent<P32, true, false>)
-                          : (own ? (const void *)k_inner_persistent<P32, false, true>
-                                 : (const void *)k_inner_persistent<P32, false, false>);
+    const void *fn = c.prec == P64 ? (own ? (const void *)k_inner_persistent<P64, 12, true>
+                                          : (const void *)k_inner_persistent<P64, 12, false>)
+                     : c.prec == P16 ? (own ? (const void *)k_inner_persistent<P16, 12, true>
+                                            : (const void *)k_inner_persistent<P16, 12, false>)
+                     : lr == 8 ? (own ? (const void *)k_inner_persistent<P32, 8, true>
+                                      : (const void *)k_inner_persistent<P32, 8, false>)
+                     : lr == 18 ? (own ? (const void *)k_inner_persistent<P32, 18, true>
+                                       : (const void *)k_inner_persistent<P32, 18, false>)
+                                : (own ? (const void *)k_inner_persistent<P32, 12, true>
+                                       : (const void *)k_inner_persistent<P32, 12, false>);
     int dev = 0, cus = 0, per_cu = 0, coop = 0, clock_khz = 0;
     WC_HIP(hipGetDevice(&dev));
     WC_HIP(hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev));

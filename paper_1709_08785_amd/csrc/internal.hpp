@@ -53,6 +53,10 @@ inline int launch_bs(int bs) { return bs ? bs : 256; }
 // tuned, else 256
 inline int lattice_bs(const wc_lattice *lat, int prec);
 constexpr float kRecon8MinN = 1e-6f;  // smallest |U01|^2 + |U02|^2 reconstruct-8 accepts
+// largest |third column - conj(col0 x col1)| over the links for which the
+// two-column forms (FP32 reconstruct-12 and -8, FP16) are accepted; above it
+// the links are not SU(3) to single precision and FP32 keeps them in full
+constexpr float kSU3MaxErr = 1e-5f;
 
 // kinds of timed kernel launches
 enum KernelSlot {
@@ -166,8 +170,13 @@ struct wc_lattice {
     // reconstruct-8 FP32 copy (8 slabs of link8_slab_bytes), built on request;
     // recon = 8 makes the FP32 stencils read it
     void *links8 = nullptr;
+    // full FP32 copy (8 slabs of link18_slab_bytes): recon = 18
+    void *links18 = nullptr;
     int recon = 12;
+    bool recon_auto = false;        // 18 chosen by wc_load_links for links that are not SU(3)
     unsigned *recon_min = nullptr;  // device word: smallest N as FP32 bits
+    unsigned *recon_err = nullptr;  // device word: largest reconstruct-12 error as FP32 bits
+    float su3_err = 0.f;            // that error for the loaded links (0 before any)
     // clover F and F^-1 per precision: 2 slabs ([parity]) of clover_slab_bytes
     void *clov[3] = {nullptr, nullptr, nullptr};
     void *clovinv[3] = {nullptr, nullptr, nullptr};
@@ -191,6 +200,18 @@ struct wc_lattice {
     std::vector<hipEvent_t> event_pool;
     long dslash_count = 0;
 };
+
+// the link copy a stencil in precision prec reads, and its slab size
+inline const void *link_base(const wc_lattice *lat, int prec) {
+    if (prec == P32 && lat->recon == 8) return lat->links8;
+    if (prec == P32 && lat->recon == 18) return lat->links18;
+    return lat->links[prec];
+}
+inline size_t link_slab_for(const wc_lattice *lat, int prec) {
+    if (prec == P32 && lat->recon == 8) return link8_slab_bytes(lat->Vh);
+    if (prec == P32 && lat->recon == 18) return link18_slab_bytes(lat->Vh);
+    return link_slab_bytes(prec, lat->Vh);
+}
 
 inline int lattice_bs(const wc_lattice *lat, int prec) {
     if (lat->bs_pin) return lat->bs_pin;
@@ -368,8 +389,11 @@ int launch_vec_batch(hipStream_t s, wc_lattice *timing_lat, int op, int prec, co
 // ---------------------------------------------------------------------------
 int launch_pack_spinor(wc_lattice *lat, int prec, void *eo_out, const void *canon_in);
 int launch_unpack_spinor(wc_lattice *lat, int prec, void *canon_out, const void *eo_in);
-int launch_load_links(wc_lattice *lat, const void *U);
+// converts U to the per-precision copies and posts the largest
+// reconstruct-12 error into *err_bits (FP32 bits, atomic max)
+int launch_load_links(wc_lattice *lat, const void *U, unsigned *err_bits);
 int launch_links_recon8(wc_lattice *lat, unsigned *min_bits);
+int launch_links_full32(wc_lattice *lat);  // links18 from the FP64 copy
 int launch_build_clover(wc_lattice *lat, double kappa, double csw);
 int launch_link_grad(wc_lattice *lat, const void *lam_eo, const void *x_eo, void *G, void *Nbuf, double kappa,
                      double csw, bool clover);
