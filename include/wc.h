@@ -170,8 +170,8 @@ int wc_set_stream(wc_lattice *lat, void *stream);
    all links (wc_link_su3_error; it synchronises the stream).  Above 1e-5 the
    links are not SU(3) to single precision: the lattice then switches the FP32
    stencil to full links (wc_set_link_recon 18) and refuses FP16 stencil work
-   (WC_EINVAL); a later load of SU(3) links returns it to 12 unless the caller
-   chose the form.  Invalidates the clover term. */
+   (WC_EINVAL); a later load of SU(3) links returns it to the form the caller
+   last chose (12 by default).  Invalidates the clover term. */
 int wc_load_links(wc_lattice *lat, const void *U_dev);
 /* The reconstruction error measured by the last wc_load_links (0 before any; -1
    for a null lattice). */

@@ -198,7 +198,7 @@ static int collect_stats(wc_lattice *lat, SlotStats *st) {
 
 extern "C" int wc_set_barrier_timeout(double seconds) {
     if (!(seconds >= 0.0) || !std::isfinite(seconds)) return wc_fail(WC_EINVAL, "barrier timeout must be >= 0 and finite");
-    g_barrier_timeout_s = seconds;
+    g_barrier_timeout_s.store(seconds);
     return WC_OK;
 }
 
@@ -555,12 +555,15 @@ extern "C" int wc_load_links(wc_lattice *lat, const void *U_dev) {
         if (lat->recon != 18) set_recon(lat, 18, true);
         return WC_OK;
     }
-    if (lat->recon_auto) set_recon(lat, 12, false);  // SU(3) again: back to the default
+    if (lat->recon_auto) set_recon(lat, lat->recon_user, false);  // SU(3) again: the caller's form
     if (lat->recon == 18) return build_full32(lat);
     if (lat->recon == 8) {
         // keep the reconstruct-8 copies in step; links they cannot hold switch it off
         rc = build_recon8(lat);
-        if (rc) set_recon(lat, 12, false);
+        if (rc) {
+            set_recon(lat, 12, false);
+            lat->recon_user = 12;
+        }
         return rc;
     }
     return WC_OK;
@@ -574,6 +577,7 @@ extern "C" int wc_set_link_recon(wc_lattice *lat, int recon) {
                                       std::to_string(lat->su3_err) + "); only the full form 18 holds them");
     if (recon == lat->recon) {
         lat->recon_auto = false;
+        lat->recon_user = recon;
         return WC_OK;
     }
     if (recon == 8) {
@@ -585,6 +589,7 @@ extern "C" int wc_set_link_recon(wc_lattice *lat, int recon) {
         if (int rc = build_full32(lat)) return rc;
     }
     set_recon(lat, recon, false);
+    lat->recon_user = recon;
     return WC_OK;
 }
 

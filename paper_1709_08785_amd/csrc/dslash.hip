@@ -753,7 +753,7 @@ int launch_mult_batch(hipStream_t s, const MultCall *calls, int n, wc_lattice *t
     return WC_OK;
 }
 
-double g_barrier_timeout_s = 2.0;
+std::atomic<double> g_barrier_timeout_s{2.0};
 
 // The inner loop as one cooperative launch; *ran = false (and WC_OK) when the
 // lattice is too large for all its workgroups to be resident at once, so the
@@ -801,7 +801,7 @@ int launch_inner_persistent(const PersistCall &c, hipStream_t s, bool *ran) {
     int dev = 0, cus = 0, per_cu = 0, coop = 0, clock_khz = 0;
     WC_HIP(hipGetDevice(&dev));
     WC_HIP(hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev));
-    A.limit = (long long)(g_barrier_timeout_s * 1e3 * clock_khz);
+    A.limit = (long long)(g_barrier_timeout_s.load() * 1e3 * clock_khz);
     WC_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
     WC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     WC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, 0));

@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <string>
 #include <vector>
 
@@ -174,6 +175,7 @@ struct wc_lattice {
     void *links18 = nullptr;
     int recon = 12;
     bool recon_auto = false;        // 18 chosen by wc_load_links for links that are not SU(3)
+    int recon_user = 12;            // the form last chosen by the caller, restored for SU(3) links
     unsigned *recon_min = nullptr;  // device word: smallest N as FP32 bits
     unsigned *recon_err = nullptr;  // device word: largest reconstruct-12 error as FP32 bits
     float su3_err = 0.f;            // that error for the loaded links (0 before any)
@@ -337,7 +339,7 @@ struct PersistCall {
 };
 // longest a block of the one-launch loop waits at a grid barrier before the
 // call gives up (seconds)
-extern double g_barrier_timeout_s;
+extern std::atomic<double> g_barrier_timeout_s;
 int launch_inner_persistent(const PersistCall &c, hipStream_t s, bool *ran);
 
 // ---------------------------------------------------------------------------

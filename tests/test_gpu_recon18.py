@@ -118,3 +118,16 @@ def test_chosen_full_form_survives_reload():
     lat.load_links(dev(synth.random_links(dims, 0.3, 1100)))
     assert lat.link_recon == 18  # the caller's choice, not the automatic one
     lat.close()
+
+
+def test_callers_form_restored_after_links_off_su3():
+    dims = (4, 4, 4, 8)
+    U = synth.random_links(dims, 0.3, 1101)
+    lat = wc.Lattice(dims)
+    lat.load_links(dev(U))
+    lat.set_link_recon(8)
+    lat.load_links(dev(off_su3(U, 0.02, 3101)))
+    assert lat.link_recon == 18
+    lat.load_links(dev(U))
+    assert lat.link_recon == 8
+    lat.close()
