@@ -1,0 +1,36 @@
+"""Host-side parts of the benchmark contract: more than one GPU is refused
+with a message before anything touches a device, and the Table 1 flop
+bookkeeping and roofline helpers give the paper's counts."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_table1_counts():
+    # Table 1: MULT 2232 and D-hat 4512 flops per site; axpy 96, dot 96, norm 48
+    assert bench.T1_MULT == 2232 and bench.T1_DHAT == 4512
+    assert bench.T1_ITER == 2 * 4512 + 3 * 96 + 3 * 48 + 6 * 96 == 10032
+    # 1M sites at 1 ms: 2.232 TFLOPS for a MULT, 2.28 for the D-hat half
+    assert bench.table1_gflops("mult_hopinv_fp32", 10 ** 6, 1000.0) == 2232.0
+    assert bench.table1_gflops("mult_dhat_fp16", 10 ** 6, 1000.0) == 2280.0
+    assert bench.table1_gflops("blas", 10 ** 6, 1000.0) is None
+
+
+def test_traffic_is_null_for_other_sources(tmp_path, monkeypatch):
+    # HBM bytes from the stored counters are used only while the kernel
+    # sources hash to the value they were taken on
+    monkeypatch.setattr(bench, "source_hash", lambda: "0000000000000000")
+    assert bench.traffic_for("mult_dhat_fp32", 1.0) is None
