@@ -148,3 +148,21 @@ def test_persistent_barrier_timeout_fails_cleanly():
     x, info = lat.solve(b, kappa, 1.0, 1e-10, persistent=1)
     assert info["persistent_calls"] > 0 and info["true_rel_residual"] < 1e-10
     lat.close()
+
+
+def test_persistent_own_barrier_is_deterministic():
+    # 256 workgroups on the kernel's own barrier: the reductions have a fixed
+    # order, so repeated solves must agree bit for bit; a barrier that let a
+    # block read a stale partial or neighbour would show as a differing run
+    dims, kappa = (16, 16, 16, 32), 0.13
+    U = synth.random_links(dims, 0.3, 1036)
+    lat = wc.Lattice(dims)
+    lat.load_links(dev(U))
+    b = dev(synth.gaussian_source(dims, 2036))
+    x0, i0 = lat.solve(b, kappa, 1.0, 1e-10, persistent=1)
+    assert i0["persistent_calls"] > 0
+    for rep in range(20):
+        x, info = lat.solve(b, kappa, 1.0, 1e-10, persistent=1)
+        assert torch.equal(x, x0), rep
+        assert info["inner_iters_total"] == i0["inner_iters_total"], rep
+    lat.close()
