@@ -131,3 +131,34 @@ def test_callers_form_restored_after_links_off_su3():
     lat.load_links(dev(U))
     assert lat.link_recon == 8
     lat.close()
+
+
+def test_full_links_in_one_launch_loop_and_batches():
+    # links off SU(3) (so the lattice reads them in full) through the
+    # one-launch inner loop and a batched solve, both against the oracle
+    dims, kappa = (8, 8, 8, 8), 0.12
+    U = off_su3(synth.random_links(dims, 0.3, 1102), 0.02, 3102)
+    lat = wc.Lattice(dims)
+    lat.load_links(dev(U))
+    assert lat.link_recon == 18
+    F = oracle.clover_field(U, dims, kappa, 1.0)
+    b = synth.gaussian_source(dims, 2102)
+    x, info = lat.solve(dev(b), kappa, 1.0, 1e-12, persistent=1)
+    say(info)
+    assert info["persistent_calls"] == info["inner_calls"] > 0
+    x_ref, _, _ = oracle.solve(U, F, kappa, b, tol=1e-13)
+    assert rel(host(x), x_ref) < 1e-10
+    bs = [dev(synth.gaussian_source(dims, 2103 + k)) for k in range(3)]
+    xs, infos = lat.solve_batch(bs, kappa, 1.0, 1e-10)
+    for k in range(3):
+        r, bn = oracle.residual(U, kappa, 1.0, host(bs[k]), host(xs[k]))
+        assert r / bn < 1e-10, k
+    # a batch over lattices with different link forms is refused
+    lat2 = wc.Lattice(dims)
+    lat2.load_links(dev(synth.random_links(dims, 0.3, 1103)))
+    assert lat2.link_recon == 12
+    with pytest.raises(wc.WCError) as e:
+        wc.solve_multi([lat, lat2], [bs[0], bs[1]], [kappa] * 2, [1.0] * 2, 1e-10)
+    assert e.value.code == -1
+    lat.close()
+    lat2.close()
