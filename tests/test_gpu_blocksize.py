@@ -191,3 +191,19 @@ def test_first_solve_tunes_and_pin_overrides():
     lat.set_block_size(0)
     assert lat.block_size(wc.FP16) in (64, 128, 256)
     lat.close()
+
+
+@pytest.mark.parametrize("recon", [8, 18])
+@pytest.mark.parametrize("bs", [64, 128])
+def test_small_blocks_with_other_link_forms(bs, recon):
+    dims, kappa = RAGGED, 0.13
+    say("block size", bs, "link form", recon)
+    lat, U = lattice(dims, 1071)
+    lat.set_link_recon(recon)
+    lat.set_block_size(bs)
+    b = synth.gaussian_source(dims, 2071)
+    x, info = lat.solve(dev(b), kappa, 1.0, 1e-12)
+    assert info["block_size"] == bs
+    r, bn = oracle.residual(U, kappa, 1.0, b, host(x))
+    assert r / bn < 1e-12
+    lat.close()

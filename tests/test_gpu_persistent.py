@@ -104,25 +104,26 @@ def test_persistent_iteration_cap_and_fallback():
     lat.close()
 
 
-@pytest.mark.parametrize("dims", [(16, 16, 16, 16), (16, 16, 16, 32)])
-def test_persistent_own_barrier_matches_oracle(dims):
+@pytest.mark.parametrize("dims,inner", [((16, 16, 16, 16), wc.FP32), ((16, 16, 16, 32), wc.FP32),
+                                        ((16, 16, 16, 16), wc.FP16), ((16, 16, 16, 16), wc.FP64)])
+def test_persistent_own_barrier_matches_oracle(dims, inner):
     # 128 and 256 workgroups: the kernel's own grid barrier (per-block arrival
     # words, one cache write-back and invalidate per block) instead of the
     # runtime's; the solution must agree with the launched loop's and pass the
     # oracle's FP64 true residual
     kappa = 0.13
-    say("persistent, own barrier", dims)
+    say("persistent, own barrier", dims, inner)
     U = synth.random_links(dims, 0.3, 1034)
     lat = wc.Lattice(dims)
     lat.load_links(dev(U))
     lat.set_block_size(256)
     b = synth.gaussian_source(dims, 2034)
-    x, info = lat.solve(dev(b), kappa, 1.0, 1e-12, persistent=1)
+    x, info = lat.solve(dev(b), kappa, 1.0, 1e-12, inner_prec=inner, persistent=1)
     say(info)
     assert info["persistent_calls"] == info["inner_calls"] > 0
     r, bn = oracle.residual(U, kappa, 1.0, b, host(x))
     assert r / bn < 1e-12
-    x2, info2 = lat.solve(dev(b), kappa, 1.0, 1e-12, persistent=0)
+    x2, info2 = lat.solve(dev(b), kappa, 1.0, 1e-12, inner_prec=inner, persistent=0)
     assert rel(host(x), host(x2)) < 1e-10
     assert abs(info["inner_iters_total"] - info2["inner_iters_total"]) <= max(2, 0.05 * info2["inner_iters_total"])
     lat.close()
