@@ -29,10 +29,14 @@
  *   spinors  psi[t][z][y][x][alpha][a], spin alpha = 0..3, colour a = 0..2.
  *
  * Internal even-odd ("EO") layout: one parity of a spinor field holds V/2
- * sites, site n = x + Lx (y + Ly (z + Lz t)) stored at index n >> 1 of its
- * parity, structure-of-arrays.  wc_spinor_bytes() gives the size of one
- * parity in a given precision; a two-parity EO field stores the even half
- * first, then the odd half.
+ * sites, site n = x + Lx (y + Ly (z + Lz t)) stored at index i = n >> 1 of
+ * its parity.  The parity is cut into tiles of 64 consecutive sites; a tile
+ * holds its sites' data plane after plane, a plane being one group of 4 to
+ * 16 bytes per site stored for all 64 sites contiguously, and the last tile
+ * is padded.  wc_spinor_bytes() gives the
+ * padded size of one parity in a given precision; a two-parity EO field
+ * stores the even half first, then the odd half.  EO fields are meant to be
+ * produced and read by wc_pack_spinor / wc_unpack_spinor.
  *
  * Ownership: every pointer passed in is owned by the caller.  Field pointers
  * are device pointers unless stated otherwise.  wc_load_links copies the
