@@ -187,9 +187,9 @@ double wc_link_su3_error(const wc_lattice *lat);
    U20, and the phases of U00 and of the other one; the remaining entries follow
    from unitarity and det U = 1, exact up to a few FP32 rounding steps) or 18
    (the full matrix, 72 B: for links that are not SU(3); 12 and 8 are refused
-   with WC_EINVAL for such links).  FP64
-   always keeps full matrices; FP16 always keeps two columns (rebuilding from
-   eight half-precision reals loses too many of its bits).  recon = 8 builds the
+   with WC_EINVAL for such links).  FP64 always keeps full matrices; FP16 always
+   keeps two columns (rebuilding from eight half-precision reals loses too many
+   of its bits), so FP16 stencil work needs SU(3) links.  recon = 8 builds the
    extra copy from the loaded links and returns WC_EINVAL, leaving the setting
    unchanged, if some link has |U01|^2 + |U02|^2 < 1e-6 (unit links, for
    instance); WC_ENOTREADY before wc_load_links.  A later wc_load_links rebuilds
@@ -220,7 +220,8 @@ int wc_apply_D(wc_lattice *lat, void *out_dev, const void *in_dev, int prec);
 
 /* MULT of Sec. II-B: out_p = H-tilde_{p,1-p} in_{1-p} = F_pp^-1 H_{p,1-p} in_{1-p}
    (eq. 9).  in and out are single-parity EO fields of precision prec; out_parity
-   is 0 (even, H-tilde_eo) or 1 (odd, H-tilde_oe). */
+   is 0 (even, H-tilde_eo) or 1 (odd, H-tilde_oe).  WC_EINVAL for WC_FP16 on links
+   that are not SU(3), as for wc_apply_Dee_oo. */
 int wc_apply_mult(wc_lattice *lat, void *out, const void *in, int out_parity, int prec);
 
 /* The even-odd preconditioned operator D-hat_ee = 1 - kappa^2 H-tilde_eo H-tilde_oe
@@ -238,7 +239,8 @@ int wc_apply_clover(wc_lattice *lat, void *out, const void *in, int parity, int 
    Rebuilds the clover when (kappa, csw) differ from the built pair.  p may be NULL
    (defaults).  x is also the initial guess when x0_is_guess != 0 (else ignored).
    info may be NULL.  Returns WC_ENOCONV with the best iterate in x when the caps
-   are reached. */
+   are reached, and WC_EINVAL for an FP16 inner solve on links that are not SU(3)
+   (wc_load_links). */
 int wc_solve(wc_lattice *lat, const void *b_dev, double kappa, double csw, double tol,
              const wc_solve_params *p, void *x_dev, int x0_is_guess, wc_solve_info *info);
 
