@@ -136,6 +136,25 @@ constexpr int kTile = 64;
 
 WC_HD int pad_sites(int Vh) { return (Vh + kTile - 1) / kTile * kTile; }
 
+// logical block of hardware block b, which runs on XCD b mod 8.  The logical
+// blocks are cut into windows of 8 chunks of kXcdChunk consecutive blocks,
+// and XCD x takes chunk x of every window, in order: all XCDs sweep one
+// front, y and z neighbours stay within an XCD's chunk (its L2), and a t
+// neighbour that is read again two t-slices later is still in the
+// memory-side cache.  Blocks past the last whole window are split into one
+// slab per XCD; a ragged tail keeps its own index.
+constexpr int kXcdChunk = 16;
+WC_HD int xcd_block(int b, int nb) {
+    const int win = 8 * kXcdChunk;
+    const int full = nb / win * win;
+    if (b < full) {
+        const int k = b >> 3;
+        return ((k / kXcdChunk) * 8 + (b & 7)) * kXcdChunk + k % kXcdChunk;
+    }
+    const int rb = b - full, per = (nb - full) >> 3;
+    return full + ((rb < (per << 3)) ? (rb & 7) * per + (rb >> 3) : rb);
+}
+
 // bytes per site of each field kind
 WC_HD size_t spinor_site_bytes(int prec) { return prec == P64 ? 192 : prec == P32 ? 96 : 52; }
 WC_HD size_t link_site_bytes(int prec) { return prec == P64 ? 144 : prec == P32 ? 48 : 24; }

@@ -150,25 +150,6 @@ __device__ __forceinline__ void hop_dir(const MultKArgs &a, const SiteCoord &c, 
     }
 }
 
-// logical block of hardware block b, which runs on XCD b mod 8.  The logical
-// blocks are cut into windows of 8 chunks of kXcdChunk consecutive blocks,
-// and XCD x takes chunk x of every window, in order: all XCDs sweep one
-// front, y and z neighbours stay within an XCD's chunk (its L2), and a t
-// neighbour that is read again two t-slices later is still in the
-// memory-side cache.  Blocks past the last whole window are split into one
-// slab per XCD; a ragged tail keeps its own index.
-constexpr int kXcdChunk = 16;
-__device__ __forceinline__ int xcd_block(int b, int nb) {
-    const int win = 8 * kXcdChunk;
-    const int full = nb / win * win;
-    if (b < full) {
-        const int k = b >> 3;
-        return ((k / kXcdChunk) * 8 + (b & 7)) * kXcdChunk + k % kXcdChunk;
-    }
-    const int rb = b - full, per = (nb - full) >> 3;
-    return full + ((rb < (per << 3)) ? (rb & 7) * per + (rb >> 3) : rb);
-}
-
 // NT: links and clover read once per launch (one system) use non-temporal
 // loads; a launch that serves several systems on one lattice reads them
 // through the cache so that the blocks of the other systems hit in L2

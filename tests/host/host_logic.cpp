@@ -1,0 +1,62 @@
+// Host-side checks of the index arithmetic the kernels share (compiled for the
+// host only from the library's own header):
+//   - xcd_block maps the hardware blocks of a launch one-to-one onto its
+//     logical blocks, for any block count;
+//   - the tiled EO addressing (tile_off) covers every padded slab exactly once
+//     for each field's plane list, and blocks_of covers every site.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <vector>
+
+#include "internal.hpp"
+
+static int check_cover(int Vh, size_t sb, const std::vector<std::pair<size_t, size_t>> &planes) {
+    const size_t bytes = (size_t)pad_sites(Vh) * sb;
+    std::vector<unsigned char> hit(bytes, 0);
+    for (int i = 0; i < pad_sites(Vh); i++)
+        for (auto &p : planes) {
+            const size_t o = tile_off(i, sb, p.first, p.second);
+            for (size_t k = 0; k < p.second; k++)
+                if (o + k >= bytes || hit[o + k]++) return 1;
+        }
+    for (size_t k = 0; k < bytes; k++)
+        if (hit[k] != 1) return 1;
+    return 0;
+}
+
+int main() {
+    const int nbs[] = {1, 7, 8, 9, 127, 128, 129, 255, 256, 257, 1296, 4096, 20736, 20737, 65537};
+    for (int nb : nbs) {
+        std::vector<int> seen(nb, 0);
+        for (int b = 0; b < nb; b++) {
+            const int l = xcd_block(b, nb);
+            if (l < 0 || l >= nb || seen[l]++) {
+                printf("xcd_block not one-to-one: nb %d b %d -> %d\n", nb, b, l);
+                return 1;
+            }
+        }
+    }
+    for (int Vh : {1, 63, 64, 65, 1080, 2048, 4097}) {
+        for (int bs : {64, 128, 256})
+            if ((long)blocks_of(Vh, bs) * bs < Vh || (long)(blocks_of(Vh, bs) - 1) * bs >= Vh) {
+                printf("blocks_of wrong: Vh %d bs %d\n", Vh, bs);
+                return 1;
+            }
+        // spinors: FP32 6 x 16 B, FP64 12 x 16 B, FP16 3 x 16 B + 4 B scale
+        std::vector<std::pair<size_t, size_t>> s32, s64, s16, l18;
+        for (int k = 0; k < 6; k++) s32.push_back({16 * k, 16});
+        for (int k = 0; k < 12; k++) s64.push_back({16 * k, 16});
+        for (int k = 0; k < 3; k++) s16.push_back({16 * k, 16});
+        s16.push_back({48, 4});
+        for (int k = 0; k < 4; k++) l18.push_back({16 * k, 16});
+        l18.push_back({64, 8});
+        if (check_cover(Vh, 96, s32) || check_cover(Vh, 192, s64) || check_cover(Vh, 52, s16) ||
+            check_cover(Vh, 72, l18)) {
+            printf("tiled addressing does not cover the slab once: Vh %d\n", Vh);
+            return 1;
+        }
+    }
+    printf("ok\n");
+    return 0;
+}
