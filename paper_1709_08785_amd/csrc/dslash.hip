@@ -327,7 +327,8 @@ __device__ __forceinline__ void st_agent(unsigned long long *p, unsigned long lo
 // writes the L2 back (release) and, on the way out, invalidates the caches
 // (acquire) before its block reads again.  Each block posts its arrival in a
 // word of its own (no contended atomics); one wave of block 0 gathers them
-// and posts the release.  Tags only grow, so no word is ever reset.  Every
+// and posts the release.  Tags grow from barrier to barrier and from call to
+// call (the host clears the words when its call counter wraps).  Every
 // wait is bounded in wall-clock time: a wait that runs out posts the abort
 // word, every other waiter sees it, and the function returns false in every
 // block, so the kernel always ends.

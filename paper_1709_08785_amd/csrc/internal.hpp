@@ -95,7 +95,7 @@ struct TimedLaunch {
 struct SysState {
     double *scalars = nullptr;     // [NUM_LEVELS][S_COUNT]
     int *flags = nullptr;          // [NUM_LEVELS][F_COUNT]
-    double *partials = nullptr;    // [8][blocks of the system's lattice]
+    double *partials = nullptr;    // [kMaxRed][blocks]: room for the 64-thread block count of the lattice
     size_t partials_bytes = 0;
     double *partials2 = nullptr;   // a second set, for the one-launch inner loop (single-system state only)
     unsigned long long *bar = nullptr;  // its grid barrier: [blocks] arrivals, release, abort (zeroed once)
@@ -330,7 +330,7 @@ struct PersistCall {
     wc_lattice *lat;
     int prec;
     void *r, *rt, *p, *q, *t, *tmp, *x;
-    double *part0, *part1;  // two partial buffers of kMaxRed x nblocks doubles
+    double *part0, *part1;  // two partial buffers, at least kMaxRed x nblocks doubles each
     double *sc;
     int *fl;
     int maxit;
