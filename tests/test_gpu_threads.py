@@ -71,3 +71,22 @@ def test_two_threads_solve_concurrently():
             assert np.array_equal(xc, xa), (k, i)
             r, bn = oracle.residual(U, 0.13, 1.0, b, xc)
             assert r / bn < 1e-10, (k, i)
+
+
+def test_one_lattice_on_alternating_streams():
+    # the binding rebinds the lattice to torch's current stream on every call;
+    # graphs recorded while one stream was current replay on the other
+    dims, U, b = case(0)
+    lat = wc.Lattice(dims)
+    lat.load_links(torch.from_numpy(U).cuda())
+    bd = torch.from_numpy(b).cuda()
+    x0, _ = lat.solve(bd, 0.13, 1.0, 1e-10)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    for rep in range(2):
+        for s in (s1, s2):
+            s.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(s):
+                x, info = lat.solve(bd, 0.13, 1.0, 1e-10)
+                s.synchronize()
+            assert torch.equal(x, x0), rep
+    lat.close()
