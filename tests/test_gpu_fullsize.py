@@ -63,11 +63,12 @@ def test_solve_32x32x32x64_oracle_residual(c2, inner):
     assert abs(r / bn - info["true_rel_residual"]) < 1e-12
 
 
-def test_apply_D_recon8_sampled_sites_32x32x32x64(c2):
+@pytest.mark.parametrize("recon", [8, 18])
+def test_apply_D_other_link_forms_sampled_sites_32x32x32x64(c2, recon):
     dims, lat, U, Ud = c2
-    say("apply_D sampled, reconstruct-8")
+    say("apply_D sampled, link form", recon)
     psi = synth.gaussian_source(dims, 2002)
-    lat.set_link_recon(8)
+    lat.set_link_recon(recon)
     try:
         out = lat.apply_D(torch.from_numpy(psi).cuda(), wc.FP32).cpu().numpy().reshape(-1, 4, 3)
     finally:
