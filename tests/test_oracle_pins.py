@@ -3,9 +3,9 @@
 None of these tests compares the oracle with itself: each expected value is a
 closed form worked out by hand (free-field momentum-space operator, constant
 abelian flux), a symmetry of the operator (gamma5-hermiticity, gauge and
-translation covariance), an independent library route (dense LU), or
-arithmetic printed in the paper (Table 1 flop counts, the byte model of
-Sec. IV-B).
+translation covariance), or an independent library route (dense LU).  The
+numbers the paper prints (Tables 1 and 2, the byte model of Sec. IV-B) are
+fixtures under tests/golden/, checked in test_paper_tables.py.
 """
 import numpy as np
 import pytest
@@ -398,24 +398,3 @@ def test_apply_D_sites_matches_whole_lattice():
     sites = [0, 1, 5, 17, 100, 767]
     part = oracle.apply_D_sites(U, kappa, csw, psi, sites)
     assert np.abs(part - full[sites]).max() < 1e-14
-
-
-# ---------------------------------------------------------------------------
-# arithmetic printed in the paper (Table 1; Sec. IV-B byte model)
-# ---------------------------------------------------------------------------
-
-def test_table1_flop_identities():
-    mult, dhat, axpy, dot, norm = 2232, 4512, 96, 96, 48
-    assert dhat == 2 * mult + norm          # two MULTs plus the xpay
-    assert axpy == 12 * (6 + 2)             # 12 complex: complex mul (6) + add (2)
-    assert dot == 12 * 8
-    assert norm == 12 * 4
-
-
-def test_byte_model_arithmetic():
-    assert round(180 * 8 / 2232, 3) == 0.645        # 180 complex in SP
-    assert round(672 / 2232, 3) == 0.301
-    assert round(115.2 / 0.301) == 383
-    assert round(475 / 0.301) == 1578 and round(490 / 0.301) == 1628
-    assert round(115.2 / 0.645) == 179
-    assert round(475 / 0.645) == 736 and round(490 / 0.645) == 760
