@@ -22,6 +22,10 @@ Functions and the passage each one follows:
 * ``link_grad``       gradient of -Re<lam, D[U] x> with respect to the links
                       (the chain rule through eqs. 3-4 and the clover term)
 * ``gamma5``, ``adjoint_solve``  D^-dagger = g5 D^-1 g5 (gamma5-hermiticity)
+* ``fp32_storage``, ``fp16_storage``  what a spinor reads back as after storage
+                      in single precision (Sec. III-A) or in the FP16 storage
+                      format with a per-site scale (a reading: the paper's
+                      method stores single and double precision only)
 """
 from __future__ import annotations
 
@@ -324,3 +328,35 @@ def link_grad(U, lam, x, kappa: float, csw: float, include_clover: bool = True) 
     _load().or_link_grad(_p(_dims(dims)), _p(U), _p(lam), _p(x), float(kappa), float(csw),
                          int(bool(include_clover)), _p(G))
     return G
+
+
+# ---------------------------------------------------------------------------
+# storage formats of the low-precision copies
+# ---------------------------------------------------------------------------
+
+def fp32_storage(psi) -> np.ndarray:
+    """psi after a round trip through single precision: every real rounded to
+    the nearest FP32, ties to even (the SP copies of Sec. III-A)."""
+    return np.asarray(psi, dtype=np.complex128).astype(np.complex64).astype(np.complex128)
+
+
+def fp16_storage(psi) -> np.ndarray:
+    """psi after a round trip through the FP16 storage format (a reading; the
+    paper stores single and double precision only).
+
+    Encoding of one site, all steps in FP32 with round-to-nearest-even:
+    the 24 reals are rounded to FP32; the scale s is the largest of their
+    magnitudes; each real is multiplied by r = 1/s (r = 0 when s = 0) and
+    rounded to the nearest FP16.  Decoding multiplies each FP16 value, read as
+    FP32, by s.  The encoded values lie in [-1, 1]; small ones may become FP16
+    subnormals, which are kept.
+    """
+    v = np.asarray(psi, dtype=np.complex128).astype(np.complex64)
+    re = np.stack([v.real, v.imag], axis=-1).astype(np.float32)      # [..., 4, 3, 2]
+    sites = re.reshape(re.shape[:-3] + (24,))
+    s = np.abs(sites).max(axis=-1, keepdims=True).astype(np.float32)
+    with np.errstate(divide="ignore"):
+        r = np.where(s > 0, np.float32(1.0) / s, np.float32(0.0)).astype(np.float32)
+    h = (sites * r).astype(np.float32).astype(np.float16)
+    dec = (h.astype(np.float32) * s).astype(np.float32).reshape(re.shape)
+    return (dec[..., 0].astype(np.float64) + 1j * dec[..., 1].astype(np.float64))

@@ -51,6 +51,19 @@ def test_apply_D_sampled_sites_32x32x32x64(c2, prec, tol):
     assert err < tol
 
 
+@pytest.mark.parametrize("prec", [wc.FP32, wc.FP16])
+def test_pack_unpack_bit_exact_32x32x32x64(c2, prec):
+    # every site of the full lattice reads back as the oracle's storage model
+    dims, lat, U, Ud = c2
+    say("pack/unpack 32^3x64", prec)
+    psi = synth.gaussian_source(dims, 2003)
+    back = lat.unpack(lat.pack(torch.from_numpy(psi).cuda(), prec), prec).cpu().numpy()
+    want = (oracle.fp32_storage if prec == wc.FP32 else oracle.fp16_storage)(psi)
+    bad = int(np.count_nonzero(back != want))
+    say("mismatched reals", bad)
+    assert bad == 0
+
+
 @pytest.mark.parametrize("inner", [wc.FP32, wc.FP16])
 def test_solve_32x32x32x64_oracle_residual(c2, inner):
     dims, lat, U, Ud = c2

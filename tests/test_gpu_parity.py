@@ -75,17 +75,39 @@ DIMS = [(4, 6, 8, 10), (2, 2, 2, 2), (6, 4, 2, 8), (8, 8, 8, 8)]
 PRECS = [wc.FP64, wc.FP32, wc.FP16]
 
 
+def storage_cases(dims, seed):
+    """A Gaussian field whose first sites hold the storage formats' special
+    cases: a zero site; FP16 ties, a value just above a tie and FP16
+    subnormals (scale 8); and sites scaled by 1e-30 and 1e30."""
+    psi = synth.gaussian_source(dims, seed)
+    f = psi.reshape(-1, 12)
+    f[0] = 0
+    vals = 8.0 * np.array([1.0, 0.5 + 2 ** -12, 0.5 + 3 * 2 ** -12, 0.5 + 2 ** -12 + 2 ** -20,
+                           2 ** -20, 0.75 * 2 ** -24, 0.25 * 2 ** -24, -1.0] + [0.0] * 16)
+    f[1] = vals[0::2] + 1j * vals[1::2]
+    f[2] *= 1e-30
+    f[3] *= 1e30
+    return psi
+
+
+STORED = {wc.FP64: lambda a: a, wc.FP32: oracle.fp32_storage, wc.FP16: oracle.fp16_storage}
+
+
+def assert_bits_equal(got, want):
+    bad = np.argwhere(got != want)
+    assert bad.size == 0, (len(bad), [(tuple(i), got[tuple(i)], want[tuple(i)]) for i in bad[:4]])
+
+
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("dims", DIMS[:3])
 def test_pack_unpack_roundtrip(dims, prec):
+    # the stored copy reads back bit for bit as the oracle's storage model:
+    # FP64 unchanged, FP32 rounded to nearest even, FP16 with the per-site scale
     say("pack", dims, prec)
     lat, U, F, Finv = setup_case(dims)
-    psi = synth.gaussian_source(dims, 5)
+    psi = storage_cases(dims, 5)
     back = host(lat.unpack(lat.pack(dev(psi), prec), prec))
-    if prec == wc.FP64:
-        assert np.array_equal(back, psi)
-    else:
-        assert rel(back, psi) < (1e-7 if prec == wc.FP32 else 6e-4)
+    assert_bits_equal(back, STORED[prec](psi))
 
 
 @pytest.mark.parametrize("prec", [wc.FP64, wc.FP32])

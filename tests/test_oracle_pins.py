@@ -398,3 +398,73 @@ def test_apply_D_sites_matches_whole_lattice():
     sites = [0, 1, 5, 17, 100, 767]
     part = oracle.apply_D_sites(U, kappa, csw, psi, sites)
     assert np.abs(part - full[sites]).max() < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# storage formats: single precision (Sec. III-A) and the FP16 format with a
+# per-site scale (a reading), pinned by rounding facts worked out by hand
+# ---------------------------------------------------------------------------
+
+def _site(vals):
+    """One-site 2x2x2x2 spinor field whose site 0 holds the given reals
+    (re, im interleaved, spin-major then colour) and every other site zero."""
+    psi = np.zeros((2, 2, 2, 2, 4, 3), dtype=complex)
+    v = np.zeros(24)
+    v[:len(vals)] = vals
+    psi[0, 0, 0, 0] = (v[0::2] + 1j * v[1::2]).reshape(4, 3)
+    return psi
+
+
+def _reals(psi):
+    s = psi[0, 0, 0, 0].reshape(12)
+    return np.stack([s.real, s.imag], axis=-1).reshape(24)
+
+
+def test_fp32_storage_rounds_to_nearest_even():
+    one = 1.0
+    # 1 + 2^-24 lies halfway between 1 and 1 + 2^-23: ties to even gives 1;
+    # 1 + 3 * 2^-24 lies halfway between 1 + 2^-23 and 1 + 2^-22: gives 1 + 2^-22
+    got = _reals(oracle.fp32_storage(_site([one + 2 ** -24, one + 3 * 2 ** -24, 1.0 / 3.0])))
+    assert got[0] == 1.0 and got[1] == 1.0 + 2 ** -22
+    assert abs(got[2] - 1.0 / 3.0) <= 2 ** -26 and got[2] != 1.0 / 3.0
+
+
+def test_fp16_storage_exact_cases():
+    # scale a power of two and values k/1024 * s: every step is exact
+    vals = [4.0 * k / 1024 for k in (1024, -1024, 1, -3, 511, 777, 0, -1000)]
+    assert np.array_equal(_reals(oracle.fp16_storage(_site(vals)))[:8], vals)
+    # a site of zeros stays zero (scale 0); the other 15 sites are zero sites
+    out = oracle.fp16_storage(_site(vals))
+    assert np.count_nonzero(out.reshape(16, 12)[1:]) == 0
+
+
+def test_fp16_storage_ties_to_even_and_subnormals():
+    # scale 1: the FP16 spacing in [0.5, 1) is 2^-11
+    vals = [1.0,
+            0.5 + 2 ** -12,          # tie between 0.5 (even) and 0.5 + 2^-11: 0.5
+            0.5 + 3 * 2 ** -12,      # tie between 0.5 + 2^-11 and 0.5 + 2^-10 (even)
+            0.5 + 2 ** -12 + 2 ** -20,   # just above the tie: rounds up
+            2 ** -20,                # FP16 subnormal (spacing 2^-24), exact
+            0.75 * 2 ** -24,         # rounds to the smallest subnormal 2^-24
+            0.25 * 2 ** -24]         # rounds to zero
+    got = _reals(oracle.fp16_storage(_site(vals)))[:7]
+    assert list(got) == [1.0, 0.5, 0.5 + 2 ** -10, 0.5 + 2 ** -11, 2 ** -20, 2 ** -24, 0.0]
+
+
+def test_fp16_storage_error_bound_and_scale_component():
+    # per site: |decoded - v| <= s (2^-12 + 2^-22), half the FP16 spacing in
+    # [0.5, 1) plus the FP32 roundings; and the largest component
+    # decodes to itself exactly (v r rounds to +-1 in FP16, then 1 * s = s)
+    psi = synth.gaussian_source((4, 4, 4, 4), 31) * 1e3
+    v32 = oracle.fp32_storage(psi).reshape(-1, 12)
+    dec = oracle.fp16_storage(psi).reshape(-1, 12)
+    r = lambda a: np.stack([a.real, a.imag], axis=-1).reshape(-1, 24)
+    v, d = r(v32), r(dec)
+    s = np.abs(v).max(axis=1)
+    err = np.abs(d - v).max(axis=1)
+    assert np.all(err <= s * (2 ** -12 + 2 ** -22))
+    k = np.abs(v).argmax(axis=1)
+    rows = np.arange(len(k))
+    assert np.array_equal(d[rows, k], v[rows, k])
+    # the bound is nearly attained somewhere: the format is not a finer one
+    assert (err / s).max() > 0.9 * 2 ** -12
