@@ -209,8 +209,12 @@ int wc_build_clover(wc_lattice *lat, double kappa, double csw);
 /* Bytes of one parity of a spinor field in the internal EO layout of precision prec. */
 size_t wc_spinor_bytes(const wc_lattice *lat, int prec);
 
-/* Canonical complex128 spinor -> two-parity EO field of precision prec (FP16 stores
-   one FP32 scale per site, the largest magnitude of its 24 reals), and back. */
+/* Canonical complex128 spinor -> two-parity EO field of precision prec, and back.
+   FP32 rounds every real to nearest even.  FP16 works per site in FP32: the
+   scale s is the largest magnitude of the site's 24 reals, each real times
+   1/s is rounded to nearest even FP16 (subnormals kept; a zero site stores
+   zeros and s = 0), and unpacking returns h * s.  Both are exact functions of
+   the input, so a round trip is reproducible bit for bit. */
 int wc_pack_spinor(wc_lattice *lat, void *eo_out, const void *canon_in, int prec);
 int wc_unpack_spinor(wc_lattice *lat, void *canon_out, const void *eo_in, int prec);
 
