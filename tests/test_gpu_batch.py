@@ -141,6 +141,35 @@ def test_multi_mixed_kappa_and_shared_lattice():
         assert r / bn < 1e-11, k
 
 
+def test_multi_uneven_full_size_residual():
+    # the uneven set the batch benchmark times (16^4 + 24^3x48 + 32^3x64, its
+    # seeds): every system meets the oracle's true residual on its whole
+    # lattice and agrees with its single solve to rounding
+    kappa, csw = 0.135, 1.0
+    dims_list = [(16, 16, 16, 16), (24, 24, 24, 48), (32, 32, 32, 64)]
+    say("multi uneven full size", dims_list)
+    lats, Us, bs = [], [], []
+    for i, dims in enumerate(dims_list):
+        U = synth.random_links(dims, 0.3, 1004 + 10 * i)
+        lat = wc.Lattice(dims)
+        lat.load_links(dev(U))
+        lats.append(lat)
+        Us.append(U)
+        bs.append(synth.gaussian_source(dims, 2004 + 10 * i))
+    xs, infos = wc.solve_multi(lats, [dev(b) for b in bs], [kappa] * 3, [csw] * 3, 1e-10)
+    for i, dims in enumerate(dims_list):
+        say(dims, infos[i])
+        r, bn = oracle.residual(Us[i], kappa, csw, bs[i], host(xs[i]))
+        say("oracle residual", dims, r / bn)
+        assert r / bn < 1e-10, dims
+        assert abs(r / bn - infos[i]["true_rel_residual"]) < 1e-12, dims
+        x1, _ = lats[i].solve(dev(bs[i]), kappa, csw, 1e-10)
+        assert rel(host(xs[i]), host(x1)) < 1e-9, dims
+    for lat in lats:
+        lat.close()
+    torch.cuda.empty_cache()
+
+
 def test_batch_full_size_point_sources_residual():
     # the 12 point sources on the 32^3 x 64 lattice, kappa 0.135: oracle true residual
     dims = (32, 32, 32, 64)
