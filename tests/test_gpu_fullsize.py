@@ -123,6 +123,26 @@ def c3():
     lat.close()
 
 
+@pytest.mark.parametrize("prec,tol", [(wc.FP64, 1e-13), (wc.FP32, 1e-5)])
+def test_apply_D_sampled_sites_48x48x48x96(c3, prec, tol):
+    # the precision-comparison lattice: random sites, both ends of the site
+    # order and of each parity slab, and the last x and t slices
+    dims, lat, U, b = c3
+    kappa, csw = 0.1355, 1.0
+    lat.build_clover(kappa, csw)
+    say("apply_D sampled 48^3x96", prec)
+    psi = synth.gaussian_source(dims, 2013)
+    out = lat.apply_D(torch.from_numpy(psi).cuda(), prec).cpu().numpy().reshape(-1, 4, 3)
+    V = int(np.prod(dims))
+    g = synth.rng(13)
+    sites = np.concatenate([g.integers(0, V, 4000), [0, 1, V // 2 - 1, V // 2, V - 2, V - 1, dims[0] - 1,
+                                                     V - dims[0] * dims[1] * dims[2]]])
+    ref = oracle.apply_D_sites(U, kappa, csw, psi, sites)
+    err = np.linalg.norm(out[sites] - ref) / np.linalg.norm(ref)
+    say("rel err", err)
+    assert err < tol
+
+
 def test_solve_48x48x48x96_fp16_oracle_residual(c3):
     dims, lat, U, b = c3
     kappa, csw = 0.1355, 1.0
