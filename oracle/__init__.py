@@ -16,7 +16,8 @@ Functions and the passage each one follows:
 * ``apply_D``         D = F - kappa H (Sec. II-A, eq. 3)
 * ``solve``           x = D^-1 b by plain BiCGStab on the full D, checked on
                       the true residual; ``dense_solve`` by LU for tiny lattices
-* ``bhat_e``, ``dhat_ee``, ``x_o``  even-odd Schur pieces (Sec. II-B, eqs. 5-9)
+* ``bhat_e``, ``dhat_ee``, ``x_o``  even-odd Schur pieces (Sec. II-B, eqs. 5-9);
+                      ``dhat_ee_sites`` the same D-hat_ee at listed even sites
 * ``free_solve_fft``  D^-1 b for unit links by Fourier transform (eqs. 3-4
                       with U = 1 and F = 1)
 * ``link_grad``       gradient of -Re<lam, D[U] x> with respect to the links
@@ -68,6 +69,8 @@ def _load():
         lib.or_apply_D.argtypes = [P, P, P, D, P, P]
         lib.or_apply_D_sites.argtypes = [P, P, D, D, P, P, ctypes.c_long, P]
         lib.or_residual.argtypes = [P, P, D, D, P, P, P, P]
+        lib.or_dhat_ee_sites.argtypes = [P, P, D, D, P, P, ctypes.c_long, P]
+        lib.or_dhat_ee_sites.restype = ctypes.c_long
         lib.or_bicgstab.argtypes = [P, P, P, D, P, P, D, ctypes.c_int, P, P]
         lib.or_bicgstab.restype = ctypes.c_int
         lib.or_link_grad.argtypes = [P, P, P, P, D, D, ctypes.c_int, P]
@@ -254,6 +257,24 @@ def dhat_ee(U, Finv, kappa: float, xe) -> np.ndarray:
     """D-hat_ee x_e = x_e - kappa^2 H-tilde_eo H-tilde_oe x_e (Sec. II-B, eq. 8, typo read as H_eo H_oe)."""
     xe = restrict(xe, 0)
     return xe - kappa * kappa * htilde(U, Finv, htilde(U, Finv, xe, 1), 0)
+
+
+def dhat_ee_sites(U, kappa: float, csw: float, xe, sites) -> np.ndarray:
+    """(D-hat_ee xe)(n) at even lexicographic sites ``sites`` (Sec. II-B, eq. 8,
+    same reading as ``dhat_ee``); clover blocks built and inverted on the fly,
+    so it serves lattices whose whole clover field would not fit."""
+    dims = dims_of_spinor(xe)
+    s = np.ascontiguousarray(np.asarray(sites, dtype=np.int64))
+    par = parity(dims).reshape(-1)[s]
+    if np.any(par != 0):
+        raise ValueError("dhat_ee_sites takes even sites only")
+    U, xe = _c(U), _c(xe)
+    out = np.empty((s.size, 4, 3), dtype=np.complex128)
+    bad = _load().or_dhat_ee_sites(_p(_dims(dims)), _p(U), float(kappa), float(csw), _p(xe),
+                                   _p(s), ctypes.c_long(s.size), _p(out))
+    if bad:
+        raise ArithmeticError("%d singular clover matrices" % bad)
+    return out
 
 
 def bhat_e(U, Finv, kappa: float, b) -> np.ndarray:

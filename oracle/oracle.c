@@ -308,40 +308,45 @@ void or_site_apply(const int *L, const cplx *M, const cplx *in, cplx *out)
     }
 }
 
-/* inverse of every 12x12 site matrix: Gauss-Jordan elimination with partial pivoting.
-   Returns the number of singular sites (0 on success). */
+/* inverse of one 12x12 matrix by Gauss-Jordan elimination with partial
+   pivoting; returns 0 when the matrix is singular, 1 otherwise */
+static int invert12(const cplx *M, cplx *Minv)
+{
+    cplx a[12][24];
+    for (int i = 0; i < 12; i++)
+        for (int j = 0; j < 12; j++) {
+            a[i][j] = M[12 * i + j];
+            a[i][12 + j] = (i == j) ? 1.0 : 0.0;
+        }
+    for (int col = 0; col < 12; col++) {
+        int piv = col;
+        for (int r = col + 1; r < 12; r++)
+            if (cabs(a[r][col]) > cabs(a[piv][col])) piv = r;
+        if (cabs(a[piv][col]) == 0.0) return 0;
+        if (piv != col)
+            for (int j = 0; j < 24; j++) { cplx t = a[col][j]; a[col][j] = a[piv][j]; a[piv][j] = t; }
+        cplx d = 1.0 / a[col][col];
+        for (int j = 0; j < 24; j++) a[col][j] *= d;
+        for (int r = 0; r < 12; r++) {
+            if (r == col) continue;
+            cplx f = a[r][col];
+            if (f == 0) continue;
+            for (int j = 0; j < 24; j++) a[r][j] -= f * a[col][j];
+        }
+    }
+    for (int i = 0; i < 12; i++)
+        for (int j = 0; j < 12; j++) Minv[12 * i + j] = a[i][12 + j];
+    return 1;
+}
+
+/* inverse of every 12x12 site matrix.  Returns the number of singular sites
+   (0 on success). */
 long or_site_invert(const int *L, const cplx *M, cplx *Minv)
 {
     long V = volume(L), bad = 0;
 #pragma omp parallel for schedule(static) reduction(+ : bad)
-    for (long n = 0; n < V; n++) {
-        cplx a[12][24];
-        for (int i = 0; i < 12; i++)
-            for (int j = 0; j < 12; j++) {
-                a[i][j] = M[n * 144 + 12 * i + j];
-                a[i][12 + j] = (i == j) ? 1.0 : 0.0;
-            }
-        int ok = 1;
-        for (int col = 0; col < 12 && ok; col++) {
-            int piv = col;
-            for (int r = col + 1; r < 12; r++)
-                if (cabs(a[r][col]) > cabs(a[piv][col])) piv = r;
-            if (cabs(a[piv][col]) == 0.0) { ok = 0; break; }
-            if (piv != col)
-                for (int j = 0; j < 24; j++) { cplx t = a[col][j]; a[col][j] = a[piv][j]; a[piv][j] = t; }
-            cplx d = 1.0 / a[col][col];
-            for (int j = 0; j < 24; j++) a[col][j] *= d;
-            for (int r = 0; r < 12; r++) {
-                if (r == col) continue;
-                cplx f = a[r][col];
-                if (f == 0) continue;
-                for (int j = 0; j < 24; j++) a[r][j] -= f * a[col][j];
-            }
-        }
-        if (!ok) { bad++; continue; }
-        for (int i = 0; i < 12; i++)
-            for (int j = 0; j < 12; j++) Minv[n * 144 + 12 * i + j] = a[i][12 + j];
-    }
+    for (long n = 0; n < V; n++)
+        if (!invert12(M + n * 144, Minv + n * 144)) bad++;
     return bad;
 }
 
@@ -383,6 +388,64 @@ void or_apply_D_sites(const int *L, const cplx *U, double kappa, double csw, con
             out[s * 12 + i] = a - kappa * h[i];
         }
     }
+}
+
+/* (D-hat_ee xe)(n) = xe(n) - kappa^2 [F_ee^-1 H_eo F_oo^-1 H_oe xe](n) (Sec. II-B,
+   eq. 8, read with H_oe as the inner factor) at a list of even sites only, for
+   checks of lattices where whole clover fields would not fit.  xe is a
+   full-lattice field; only its even sites are read.  The clover blocks of the
+   listed sites and of their odd neighbours are built and inverted on the fly.
+   Returns the number of singular clover matrices met (0 on success). */
+long or_dhat_ee_sites(const int *L, const cplx *U, double kappa, double csw, const cplx *xe,
+                      const long *sites, long nsites, cplx *out)
+{
+    long V = volume(L), bad = 0;
+    /* odd neighbours of the listed sites, each once */
+    char *mark = calloc((size_t)V, 1);
+    long *odd = malloc(sizeof(long) * 8 * (nsites > 0 ? nsites : 1));
+    long nodd = 0;
+    for (long s = 0; s < nsites; s++) {
+        int c[4];
+        coords(L, sites[s], c);
+        for (int mu = 0; mu < 4; mu++)
+            for (int sg = -1; sg <= 1; sg += 2) {
+                long m = shifted(L, c, mu, sg);
+                if (!mark[m]) { mark[m] = 1; odd[nodd++] = m; }
+            }
+    }
+    /* y(m) = F_oo^-1(m) (H_oe xe)(m) at those odd sites, zero elsewhere; H_oe
+       at an odd site reads only its even neighbours */
+    cplx *y = calloc((size_t)V * 12, sizeof(cplx));
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : bad)
+    for (long k = 0; k < nodd; k++) {
+        long m = odd[k];
+        cplx h[12], F[144], Fi[144];
+        hop_site(L, U, xe, m, h);
+        clover_site(L, U, kappa, csw, m, F);
+        if (!invert12(F, Fi)) { bad++; continue; }
+        for (int i = 0; i < 12; i++) {
+            cplx a = 0;
+            for (int j = 0; j < 12; j++) a += Fi[12 * i + j] * h[j];
+            y[m * 12 + i] = a;
+        }
+    }
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : bad)
+    for (long s = 0; s < nsites; s++) {
+        long n = sites[s];
+        cplx h[12], F[144], Fi[144];
+        hop_site(L, U, y, n, h);
+        clover_site(L, U, kappa, csw, n, F);
+        if (!invert12(F, Fi)) { bad++; continue; }
+        for (int i = 0; i < 12; i++) {
+            cplx a = 0;
+            for (int j = 0; j < 12; j++) a += Fi[12 * i + j] * h[j];
+            out[s * 12 + i] = xe[n * 12 + i] - kappa * kappa * a;
+        }
+    }
+    free(y);
+    free(odd);
+    free(mark);
+    return bad;
 }
 
 /* ||b - D x||^2 and ||b||^2 over the whole lattice, F built on the fly.

@@ -60,6 +60,8 @@ MUTANTS = {
     "x_o_sign": ("py", "restrict(site_apply(Finv, b), 1) + kappa * htilde", "restrict(site_apply(Finv, b), 1) - kappa * htilde"),
     "parity_without_t": ("py", "return (x + y + z + t) & 1", "return (x + y + z) & 1"),
     "free_momentum_sin_sign": ("py", "- 2j * np.sin(p[mu])", "+ 2j * np.sin(p[mu])"),
+    "dhat_sites_kappa_not_squared": ("c", "out[s * 12 + i] = xe[n * 12 + i] - kappa * kappa * a;",
+                                     "out[s * 12 + i] = xe[n * 12 + i] - kappa * a;"),
     # storage format
     "fp16_scale_per_spin": ("py", "sites = re.reshape(re.shape[:-3] + (24,))", "sites = re.reshape(re.shape[:-2] + (6,))"),
 }

@@ -400,6 +400,25 @@ def test_apply_D_sites_matches_whole_lattice():
     assert np.abs(part - full[sites]).max() < 1e-14
 
 
+@pytest.mark.parametrize("dims", [(4, 6, 8, 10), (6, 4, 2, 8)])
+def test_dhat_ee_sites_matches_whole_lattice(dims):
+    # the site-by-site D-hat_ee against the whole-lattice one (pinned by the
+    # free-field eigenvalues and the even-odd reconstruction) at every even site
+    kappa, csw = 0.13, 1.0
+    U = synth.random_links(dims, 0.3, 123)
+    Finv = oracle.site_invert(oracle.clover_field(U, dims, kappa, csw))
+    xe = oracle.restrict(synth.gaussian_source(dims, 124), 0)
+    full = oracle.dhat_ee(U, Finv, kappa, xe).reshape(-1, 4, 3)
+    even = np.flatnonzero(oracle.parity(dims).reshape(-1) == 0)
+    part = oracle.dhat_ee_sites(U, kappa, csw, xe, even[::-1])
+    assert np.abs(part - full[even[::-1]]).max() < 1e-13 * np.abs(full).max()
+    # odd sites of the input are not read; odd output sites are refused
+    noisy = xe + oracle.restrict(synth.gaussian_source(dims, 125), 1)
+    assert np.abs(oracle.dhat_ee_sites(U, kappa, csw, noisy, even) - full[even]).max() < 1e-13 * np.abs(full).max()
+    with pytest.raises(ValueError):
+        oracle.dhat_ee_sites(U, kappa, csw, xe, [int(np.flatnonzero(oracle.parity(dims).reshape(-1))[0])])
+
+
 # ---------------------------------------------------------------------------
 # storage formats: single precision (Sec. III-A) and the FP16 format with a
 # per-site scale (a reading), pinned by rounding facts worked out by hand
