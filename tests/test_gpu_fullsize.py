@@ -64,6 +64,29 @@ def test_pack_unpack_bit_exact_32x32x32x64(c2, prec):
     assert bad == 0
 
 
+@pytest.mark.parametrize("prec,tol", [(wc.FP64, 1e-13), (wc.FP32, 1e-5), (wc.FP16, 2e-3)])
+def test_dhat_ee_sampled_even_sites_32x32x32x64(c2, prec, tol):
+    # D-hat_ee, the inner loop's operator, at the benchmark's lattice and
+    # launch shape against the oracle's site-by-site D-hat_ee (eq. 8)
+    dims, lat, U, Ud = c2
+    kappa, csw = 0.135, 1.0
+    say("D-hat_ee sampled", prec)
+    psi = oracle.restrict(synth.gaussian_source(dims, 2004), 0)
+    eo_in = lat.pack(torch.from_numpy(psi).cuda(), prec)
+    eo_out = lat.new_eo(prec, 2)
+    lat.apply_Dee_oo(lat.parity_view(eo_out, 0, prec), lat.parity_view(eo_in, 0, prec), prec)
+    out = lat.unpack(eo_out, prec).cpu().numpy().reshape(-1, 4, 3)
+    even = oracle.parity(dims).reshape(-1) == 0
+    V = int(np.prod(dims))
+    g = synth.rng(10)
+    cand = np.concatenate([g.integers(0, V, 6000), [0, 1, 2, V // 2, V - 2, V - 1, dims[0] - 2, dims[0] - 1]])
+    sites = np.unique(cand[even[cand]])
+    ref = oracle.dhat_ee_sites(U, kappa, csw, psi, sites)
+    err = np.linalg.norm(out[sites] - ref) / np.linalg.norm(ref)
+    say(len(sites), "even sites, rel err", err)
+    assert err < tol
+
+
 @pytest.mark.parametrize("inner", [wc.FP32, wc.FP16])
 def test_solve_32x32x32x64_oracle_residual(c2, inner):
     dims, lat, U, Ud = c2
