@@ -17,7 +17,8 @@ Functions and the passage each one follows:
 * ``solve``           x = D^-1 b by plain BiCGStab on the full D, checked on
                       the true residual; ``dense_solve`` by LU for tiny lattices
 * ``bhat_e``, ``dhat_ee``, ``x_o``  even-odd Schur pieces (Sec. II-B, eqs. 5-9);
-                      ``dhat_ee_sites`` the same D-hat_ee at listed even sites
+                      ``htilde_sites``, ``dhat_ee_sites`` MULT and D-hat_ee at
+                      listed sites
 * ``free_solve_fft``  D^-1 b for unit links by Fourier transform (eqs. 3-4
                       with U = 1 and F = 1)
 * ``link_grad``       gradient of -Re<lam, D[U] x> with respect to the links
@@ -71,6 +72,8 @@ def _load():
         lib.or_residual.argtypes = [P, P, D, D, P, P, P, P]
         lib.or_dhat_ee_sites.argtypes = [P, P, D, D, P, P, ctypes.c_long, P]
         lib.or_dhat_ee_sites.restype = ctypes.c_long
+        lib.or_htilde_sites.argtypes = [P, P, D, D, P, P, ctypes.c_long, P]
+        lib.or_htilde_sites.restype = ctypes.c_long
         lib.or_bicgstab.argtypes = [P, P, P, D, P, P, D, ctypes.c_int, P, P]
         lib.or_bicgstab.restype = ctypes.c_int
         lib.or_link_grad.argtypes = [P, P, P, P, D, D, ctypes.c_int, P]
@@ -257,6 +260,21 @@ def dhat_ee(U, Finv, kappa: float, xe) -> np.ndarray:
     """D-hat_ee x_e = x_e - kappa^2 H-tilde_eo H-tilde_oe x_e (Sec. II-B, eq. 8, typo read as H_eo H_oe)."""
     xe = restrict(xe, 0)
     return xe - kappa * kappa * htilde(U, Finv, htilde(U, Finv, xe, 1), 0)
+
+
+def htilde_sites(U, kappa: float, csw: float, psi, sites) -> np.ndarray:
+    """MULT F(n)^-1 (H psi)(n) at lexicographic sites ``sites`` (Sec. II-B, eq. 9);
+    only the neighbours of each site, of the other parity, are read.  Clover
+    blocks are built and inverted on the fly."""
+    dims = dims_of_spinor(psi)
+    s = np.ascontiguousarray(np.asarray(sites, dtype=np.int64))
+    U, psi = _c(U), _c(psi)
+    out = np.empty((s.size, 4, 3), dtype=np.complex128)
+    bad = _load().or_htilde_sites(_p(_dims(dims)), _p(U), float(kappa), float(csw), _p(psi),
+                                  _p(s), ctypes.c_long(s.size), _p(out))
+    if bad:
+        raise ArithmeticError("%d singular clover matrices" % bad)
+    return out
 
 
 def dhat_ee_sites(U, kappa: float, csw: float, xe, sites) -> np.ndarray:

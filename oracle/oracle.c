@@ -390,6 +390,29 @@ void or_apply_D_sites(const int *L, const cplx *U, double kappa, double csw, con
     }
 }
 
+/* MULT at a list of sites (Sec. II-B, eq. 9): out(n) = F(n)^-1 (H in)(n), with
+   F(n) built and inverted on the fly.  H at n reads only the neighbours, all
+   of the other parity.  Returns the number of singular clover matrices. */
+long or_htilde_sites(const int *L, const cplx *U, double kappa, double csw, const cplx *in,
+                     const long *sites, long nsites, cplx *out)
+{
+    long bad = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : bad)
+    for (long s = 0; s < nsites; s++) {
+        long n = sites[s];
+        cplx h[12], F[144], Fi[144];
+        hop_site(L, U, in, n, h);
+        clover_site(L, U, kappa, csw, n, F);
+        if (!invert12(F, Fi)) { bad++; continue; }
+        for (int i = 0; i < 12; i++) {
+            cplx a = 0;
+            for (int j = 0; j < 12; j++) a += Fi[12 * i + j] * h[j];
+            out[s * 12 + i] = a;
+        }
+    }
+    return bad;
+}
+
 /* (D-hat_ee xe)(n) = xe(n) - kappa^2 [F_ee^-1 H_eo F_oo^-1 H_oe xe](n) (Sec. II-B,
    eq. 8, read with H_oe as the inner factor) at a list of even sites only, for
    checks of lattices where whole clover fields would not fit.  xe is a

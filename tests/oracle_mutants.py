@@ -62,6 +62,9 @@ MUTANTS = {
     "free_momentum_sin_sign": ("py", "- 2j * np.sin(p[mu])", "+ 2j * np.sin(p[mu])"),
     "dhat_sites_kappa_not_squared": ("c", "out[s * 12 + i] = xe[n * 12 + i] - kappa * kappa * a;",
                                      "out[s * 12 + i] = xe[n * 12 + i] - kappa * a;"),
+    "htilde_sites_without_clover_inverse": ("c", "for (int j = 0; j < 12; j++) a += Fi[12 * i + j] * h[j];\n"
+                                                 "            out[s * 12 + i] = a;",
+                                            "a = h[i];\n            out[s * 12 + i] = a;"),
     # storage format
     "fp16_scale_per_spin": ("py", "sites = re.reshape(re.shape[:-3] + (24,))", "sites = re.reshape(re.shape[:-2] + (6,))"),
 }

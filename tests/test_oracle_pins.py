@@ -401,6 +401,24 @@ def test_apply_D_sites_matches_whole_lattice():
 
 
 @pytest.mark.parametrize("dims", [(4, 6, 8, 10), (6, 4, 2, 8)])
+def test_htilde_sites_matches_whole_lattice(dims):
+    # site-by-site MULT against the whole-lattice one, both output parities
+    kappa, csw = 0.13, 1.0
+    U = synth.random_links(dims, 0.3, 126)
+    Finv = oracle.site_invert(oracle.clover_field(U, dims, kappa, csw))
+    psi = synth.gaussian_source(dims, 127)
+    par = oracle.parity(dims).reshape(-1)
+    for p in (0, 1):
+        full = oracle.htilde(U, Finv, psi, p).reshape(-1, 4, 3)
+        sites = np.flatnonzero(par == p)[::-1]
+        part = oracle.htilde_sites(U, kappa, csw, oracle.restrict(psi, 1 - p), sites)
+        assert np.abs(part - full[sites]).max() < 1e-13 * np.abs(full).max(), p
+        # the sites' own parity is not read
+        part = oracle.htilde_sites(U, kappa, csw, psi, sites)
+        assert np.abs(part - full[sites]).max() < 1e-13 * np.abs(full).max(), p
+
+
+@pytest.mark.parametrize("dims", [(4, 6, 8, 10), (6, 4, 2, 8)])
 def test_dhat_ee_sites_matches_whole_lattice(dims):
     # the site-by-site D-hat_ee against the whole-lattice one (pinned by the
     # free-field eigenvalues and the even-odd reconstruction) at every even site
