@@ -87,6 +87,29 @@ def test_dhat_ee_sampled_even_sites_32x32x32x64(c2, prec, tol):
     assert err < tol
 
 
+@pytest.mark.parametrize("prec,tol", [(wc.FP64, 1e-13), (wc.FP32, 1e-5), (wc.FP16, 2e-3)])
+def test_mult_sampled_sites_both_parities_32x32x32x64(c2, prec, tol):
+    # MULT = F^-1 H into each parity, against the oracle's site-by-site MULT
+    dims, lat, U, Ud = c2
+    kappa, csw = 0.135, 1.0
+    psi = synth.gaussian_source(dims, 2005)
+    eo_in = lat.pack(torch.from_numpy(psi).cuda(), prec)
+    par = oracle.parity(dims).reshape(-1)
+    V = int(np.prod(dims))
+    g = synth.rng(12)
+    cand = np.concatenate([g.integers(0, V, 6000), [0, 1, 2, V // 2, V - 2, V - 1, dims[0] - 2, dims[0] - 1]])
+    for p in (0, 1):
+        say("MULT sampled", prec, "into parity", p)
+        eo_out = lat.new_eo(prec, 2)
+        lat.apply_mult(lat.parity_view(eo_out, p, prec), lat.parity_view(eo_in, 1 - p, prec), p, prec)
+        out = lat.unpack(eo_out, prec).cpu().numpy().reshape(-1, 4, 3)
+        sites = np.unique(cand[par[cand] == p])
+        ref = oracle.htilde_sites(U, kappa, csw, psi, sites)
+        err = np.linalg.norm(out[sites] - ref) / np.linalg.norm(ref)
+        say(len(sites), "sites, rel err", err)
+        assert err < tol, p
+
+
 @pytest.mark.parametrize("inner", [wc.FP32, wc.FP16])
 def test_solve_32x32x32x64_oracle_residual(c2, inner):
     dims, lat, U, Ud = c2
