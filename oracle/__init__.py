@@ -17,8 +17,8 @@ Functions and the passage each one follows:
 * ``solve``           x = D^-1 b by plain BiCGStab on the full D, checked on
                       the true residual; ``dense_solve`` by LU for tiny lattices
 * ``bhat_e``, ``dhat_ee``, ``x_o``  even-odd Schur pieces (Sec. II-B, eqs. 5-9);
-                      ``htilde_sites``, ``dhat_ee_sites`` MULT and D-hat_ee at
-                      listed sites
+                      ``clover_sites``, ``htilde_sites``, ``dhat_ee_sites``
+                      F or F^-1, MULT and D-hat_ee at listed sites
 * ``free_solve_fft``  D^-1 b for unit links by Fourier transform (eqs. 3-4
                       with U = 1 and F = 1)
 * ``link_grad``       gradient of -Re<lam, D[U] x> with respect to the links
@@ -74,6 +74,8 @@ def _load():
         lib.or_dhat_ee_sites.restype = ctypes.c_long
         lib.or_htilde_sites.argtypes = [P, P, D, D, P, P, ctypes.c_long, P]
         lib.or_htilde_sites.restype = ctypes.c_long
+        lib.or_clover_sites.argtypes = [P, P, D, D, P, P, ctypes.c_long, ctypes.c_int, P]
+        lib.or_clover_sites.restype = ctypes.c_long
         lib.or_bicgstab.argtypes = [P, P, P, D, P, P, D, ctypes.c_int, P, P]
         lib.or_bicgstab.restype = ctypes.c_int
         lib.or_link_grad.argtypes = [P, P, P, P, D, D, ctypes.c_int, P]
@@ -260,6 +262,20 @@ def dhat_ee(U, Finv, kappa: float, xe) -> np.ndarray:
     """D-hat_ee x_e = x_e - kappa^2 H-tilde_eo H-tilde_oe x_e (Sec. II-B, eq. 8, typo read as H_eo H_oe)."""
     xe = restrict(xe, 0)
     return xe - kappa * kappa * htilde(U, Finv, htilde(U, Finv, xe, 1), 0)
+
+
+def clover_sites(U, kappa: float, csw: float, psi, sites, inverse: bool = False) -> np.ndarray:
+    """F(n) psi(n), or F(n)^-1 psi(n), at lexicographic sites ``sites``
+    (Sec. II-A; Sec. II-B for the inverse), F built from the links on the fly."""
+    dims = dims_of_spinor(psi)
+    s = np.ascontiguousarray(np.asarray(sites, dtype=np.int64))
+    U, psi = _c(U), _c(psi)
+    out = np.empty((s.size, 4, 3), dtype=np.complex128)
+    bad = _load().or_clover_sites(_p(_dims(dims)), _p(U), float(kappa), float(csw), _p(psi),
+                                  _p(s), ctypes.c_long(s.size), int(bool(inverse)), _p(out))
+    if bad:
+        raise ArithmeticError("%d singular clover matrices" % bad)
+    return out
 
 
 def htilde_sites(U, kappa: float, csw: float, psi, sites) -> np.ndarray:

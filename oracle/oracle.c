@@ -390,6 +390,32 @@ void or_apply_D_sites(const int *L, const cplx *U, double kappa, double csw, con
     }
 }
 
+/* F(n) in(n), or F(n)^-1 in(n) when inverse is set, at a list of sites, with
+   F(n) built from the links on the fly (Sec. II-A).  Returns the number of
+   singular clover matrices. */
+long or_clover_sites(const int *L, const cplx *U, double kappa, double csw, const cplx *in,
+                     const long *sites, long nsites, int inverse, cplx *out)
+{
+    long bad = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : bad)
+    for (long s = 0; s < nsites; s++) {
+        long n = sites[s];
+        cplx F[144], Fi[144];
+        const cplx *M = F;
+        clover_site(L, U, kappa, csw, n, F);
+        if (inverse) {
+            if (!invert12(F, Fi)) { bad++; continue; }
+            M = Fi;
+        }
+        for (int i = 0; i < 12; i++) {
+            cplx a = 0;
+            for (int j = 0; j < 12; j++) a += M[12 * i + j] * in[n * 12 + j];
+            out[s * 12 + i] = a;
+        }
+    }
+    return bad;
+}
+
 /* MULT at a list of sites (Sec. II-B, eq. 9): out(n) = F(n)^-1 (H in)(n), with
    F(n) built and inverted on the fly.  H at n reads only the neighbours, all
    of the other parity.  Returns the number of singular clover matrices. */

@@ -65,6 +65,8 @@ MUTANTS = {
     "htilde_sites_without_clover_inverse": ("c", "for (int j = 0; j < 12; j++) a += Fi[12 * i + j] * h[j];\n"
                                                  "            out[s * 12 + i] = a;",
                                             "a = h[i];\n            out[s * 12 + i] = a;"),
+    "clover_sites_inverse_ignored": ("c", "        if (inverse) {\n            if (!invert12(F, Fi))",
+                                     "        if (0) {\n            if (!invert12(F, Fi))"),
     # storage format
     "fp16_scale_per_spin": ("py", "sites = re.reshape(re.shape[:-3] + (24,))", "sites = re.reshape(re.shape[:-2] + (6,))"),
 }
