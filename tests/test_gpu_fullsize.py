@@ -87,6 +87,30 @@ def test_dhat_ee_sampled_even_sites_32x32x32x64(c2, prec, tol):
     assert err < tol
 
 
+@pytest.mark.parametrize("prec,tol", [(wc.FP64, 1e-13), (wc.FP32, 1e-5), (wc.FP16, 3e-3)])
+def test_clover_and_inverse_sampled_sites_32x32x32x64(c2, prec, tol):
+    # the stored clover blocks F and F^-1 of each parity against the oracle's F
+    # built site by site from the links
+    dims, lat, U, Ud = c2
+    kappa, csw = 0.135, 1.0
+    psi = synth.gaussian_source(dims, 2006)
+    eo_in = lat.pack(torch.from_numpy(psi).cuda(), prec)
+    par = oracle.parity(dims).reshape(-1)
+    V = int(np.prod(dims))
+    g = synth.rng(14)
+    cand = np.concatenate([g.integers(0, V, 4000), [0, 1, V - 2, V - 1]])
+    for inverse in (0, 1):
+        for p in (0, 1):
+            eo_out = lat.new_eo(prec, 2)
+            lat.apply_clover(lat.parity_view(eo_out, p, prec), lat.parity_view(eo_in, p, prec), p, inverse, prec)
+            out = lat.unpack(eo_out, prec).cpu().numpy().reshape(-1, 4, 3)
+            sites = np.unique(cand[par[cand] == p])
+            ref = oracle.clover_sites(U, kappa, csw, psi, sites, bool(inverse))
+            err = np.linalg.norm(out[sites] - ref) / np.linalg.norm(ref)
+            say("clover", prec, "inverse", inverse, "parity", p, "rel err", err)
+            assert err < tol, (inverse, p)
+
+
 @pytest.mark.parametrize("prec,tol", [(wc.FP64, 1e-13), (wc.FP32, 1e-5), (wc.FP16, 2e-3)])
 def test_mult_sampled_sites_both_parities_32x32x32x64(c2, prec, tol):
     # MULT = F^-1 H into each parity, against the oracle's site-by-site MULT
