@@ -213,6 +213,28 @@ def test_apply_D_sampled_sites_48x48x48x96(c3, prec, tol):
     assert err < tol
 
 
+@pytest.mark.parametrize("prec,tol", [(wc.FP32, 1e-5), (wc.FP16, 2e-3)])
+def test_dhat_ee_sampled_even_sites_48x48x48x96(c3, prec, tol):
+    dims, lat, U, b = c3
+    kappa, csw = 0.1355, 1.0
+    lat.build_clover(kappa, csw)
+    say("D-hat_ee sampled 48^3x96", prec)
+    psi = oracle.restrict(synth.gaussian_source(dims, 2014), 0)
+    eo_in = lat.pack(torch.from_numpy(psi).cuda(), prec)
+    eo_out = lat.new_eo(prec, 2)
+    lat.apply_Dee_oo(lat.parity_view(eo_out, 0, prec), lat.parity_view(eo_in, 0, prec), prec)
+    out = lat.unpack(eo_out, prec).cpu().numpy().reshape(-1, 4, 3)
+    even = oracle.parity(dims).reshape(-1) == 0
+    V = int(np.prod(dims))
+    g = synth.rng(15)
+    cand = np.concatenate([g.integers(0, V, 4000), [0, 2, V // 2, V - 2, V - 1, dims[0] - 2, dims[0] - 1]])
+    sites = np.unique(cand[even[cand]])
+    ref = oracle.dhat_ee_sites(U, kappa, csw, psi, sites)
+    err = np.linalg.norm(out[sites] - ref) / np.linalg.norm(ref)
+    say(len(sites), "even sites, rel err", err)
+    assert err < tol
+
+
 def test_solve_48x48x48x96_fp16_oracle_residual(c3):
     dims, lat, U, b = c3
     kappa, csw = 0.1355, 1.0
