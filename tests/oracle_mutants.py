@@ -67,6 +67,9 @@ MUTANTS = {
                                             "a = h[i];\n            out[s * 12 + i] = a;"),
     "clover_sites_inverse_ignored": ("c", "        if (inverse) {\n            if (!invert12(F, Fi))",
                                      "        if (0) {\n            if (!invert12(F, Fi))"),
+    # true residual of the full system
+    "residual_zero": ("c", "r += creal(d) * creal(d) + cimag(d) * cimag(d);", "r += 0.0 * creal(d);"),
+    "residual_drops_imag": ("c", "r += creal(d) * creal(d) + cimag(d) * cimag(d);", "r += creal(d) * creal(d);"),
     # storage format
     "fp16_scale_per_spin": ("py", "sites = re.reshape(re.shape[:-3] + (24,))", "sites = re.reshape(re.shape[:-2] + (6,))"),
 }

@@ -377,6 +377,56 @@ def test_pure_gauge_fft_solve_and_residual():
     assert rel(xs, x) < 1e-12
 
 
+# ---------------------------------------------------------------------------
+# the true residual ||b - D x|| (used to judge every full-size solve), pinned
+# from both sides: exact values, not only "small for a solution"
+# ---------------------------------------------------------------------------
+
+def test_residual_of_zero_is_norm_b():
+    # x = 0 leaves r = b: both returned norms equal ||b|| (numpy's norm)
+    dims = (4, 4, 4, 6)
+    U = synth.random_links(dims, 0.3, 111)
+    b = synth.gaussian_source(dims, 112)
+    r, bn = oracle.residual(U, 0.13, 1.0, b, np.zeros_like(b))
+    nb = np.linalg.norm(b.reshape(-1))
+    assert abs(r - nb) <= 1e-14 * nb and abs(bn - nb) <= 1e-14 * nb
+
+
+def test_residual_free_field_plane_waves_closed_form():
+    # unit links (F = 1): x = e^{ipn} u, b = e^{ipn} w gives b - D x = e^{ipn} (w - D(p) u),
+    # so ||b - D x||^2 = V ||w - D(p) u||^2 with D(p) built from the hand-typed gammas.
+    # u and w are complex, so a residual that drops imaginary parts is caught.
+    dims = DIMS_NC
+    kappa = 0.13
+    g = synth.rng(113)
+    U = synth.unit_links(dims)
+    V = int(np.prod(dims))
+    for k in [(1, 2, 3, 4), (0, 1, 0, 3), (3, 5, 7, 9)]:
+        u = g.standard_normal((4, 3)) + 1j * g.standard_normal((4, 3))
+        w = g.standard_normal((4, 3)) + 1j * g.standard_normal((4, 3))
+        x, p = _plane_wave(dims, k, u)
+        b, _ = _plane_wave(dims, k, w)
+        expect = np.sqrt(V) * np.linalg.norm(w - _Dp_hand(p, kappa) @ u)
+        r, bn = oracle.residual(U, kappa, 1.0, b, x)
+        assert abs(r - expect) <= 1e-13 * expect
+        assert abs(bn - np.sqrt(V) * np.linalg.norm(w)) <= 1e-13 * bn
+
+
+def test_residual_of_a_non_solution_matches_apply_D():
+    # random links with the clover term on, random x that solves nothing: the
+    # residual equals ||b - D x|| from the pinned whole-lattice operator
+    dims = (4, 6, 4, 4)
+    kappa, csw = 0.13, 1.0
+    U = synth.random_links(dims, 0.3, 114)
+    F = oracle.clover_field(U, dims, kappa, csw)
+    b = synth.gaussian_source(dims, 115)
+    x = synth.gaussian_source(dims, 116)
+    expect = np.linalg.norm((b - oracle.apply_D(U, F, kappa, x)).reshape(-1))
+    r, bn = oracle.residual(U, kappa, csw, b, x)
+    assert abs(r - expect) <= 1e-14 * expect
+    assert abs(bn - np.linalg.norm(b.reshape(-1))) <= 1e-14 * bn
+
+
 def test_special_cases_kappa0_csw0():
     dims = (4, 4, 4, 4)
     U = synth.random_links(dims, 0.3, 111)
