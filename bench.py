@@ -42,9 +42,10 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_for(kernel: str, launches_bytes: float):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources."""
+def traffic_for(kernel: str, dims, recon: int):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (profiles/traffic.json), if one was taken on the current kernel
+    sources for this lattice and FP32 link form; None otherwise."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -52,12 +53,12 @@ def traffic_for(kernel: str, launches_bytes: float):
         d = json.load(open(path))
     except Exception:
         return None
-    if d.get("source_hash") != source_hash():
-        return None
-    k = d.get("kernels", {}).get(kernel)
-    if not k:
-        return None
-    return k.get("hbm_bytes_per_launch")
+    h = source_hash()
+    for e in d.get("entries", []):
+        if (e.get("source_hash") == h and e.get("kernel") == kernel and list(e.get("lattice", [])) == list(dims)
+                and int(e.get("link_recon", 12)) == int(recon)):
+            return e.get("hbm_bytes_per_launch")
+    return None
 
 
 # the paper's Table 1 flop counts per even site: MULT 2232 and D-hat 4512, so
@@ -164,11 +165,13 @@ def dslash_mode(args, dims):
     import paper_1709_08785_amd as wc
     import synth
 
-    U = synth.random_links(dims, 0.3, args.seed)
-    psi = synth.gaussian_source(dims, args.seed + 1000)
     dev = torch.device("cuda:0")
+    # the links' exponential evaluated on the GPU (same draws as the host form)
+    Ud = synth.random_links_torch(dims, 0.3, args.seed, device=dev)
+    psi = synth.gaussian_source(dims, args.seed + 1000)
     lat = wc.Lattice(dims, device=dev)
-    lat.load_links(torch.from_numpy(U).to(dev))
+    lat.load_links(Ud)
+    del Ud
     lat.build_clover(args.kappa, args.csw)
     psid = torch.from_numpy(psi).to(dev)
     res = {}
@@ -664,7 +667,7 @@ def main():
     per_launch_bytes = dom["bytes"] / dom["launches"]
     avg_ms = dom["ms"] / dom["launches"]
     achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9
-    hbm = traffic_for(dom_name, per_launch_bytes)
+    hbm = traffic_for(dom_name, dims, args.recon)
     roofline = {
         "bound": "hbm",
         "kernel": dom_name,

@@ -151,6 +151,21 @@ int wc_set_block_size(wc_lattice *lat, int threads);
 int wc_block_size(const wc_lattice *lat, int prec);
 int wc_tune_block_size(wc_lattice *lat, int prec, double us_per_pair[3], int *threads);
 
+/* The multi-system stencil of batched solves (wc_solve_batch, and systems of
+   wc_solve_multi that share a lattice): many solutions per gauge field (Sec.
+   II-A) apply the same operator, so the inner loop's MULTs (F^-1 H of eq. 9 and
+   the second half of D-hat_ee, eq. 8) of all systems on one lattice run in one
+   launch in which each thread takes one site for systems_per_thread systems:
+   it computes the neighbour indices and rebuilds each link once, loads each
+   clover block once, and applies them to every system's spinors.
+   wc_set_multi_rhs: systems_per_thread = 2 or 4 (default 4), or 0 for one
+   system per thread (each system's sites in workgroups of their own, the
+   operator shared through the cache).  WC_EINVAL for other values.  Results
+   agree with single solves to rounding.  wc_multi_rhs: the setting, or -1 for
+   a null lattice. */
+int wc_set_multi_rhs(wc_lattice *lat, int systems_per_thread);
+int wc_multi_rhs(const wc_lattice *lat);
+
 /* Longest time (seconds, > 0 finite, or 0 for "no waiting allowed") a
    workgroup of the one-launch inner loop (wc_solve_params.persistent) waits
    at a grid barrier before the call gives up with WC_EHIP.  Process-wide;
@@ -175,7 +190,9 @@ int wc_set_stream(wc_lattice *lat, void *stream);
    links are not SU(3) to single precision: the lattice then switches the FP32
    stencil to full links (wc_set_link_recon 18) and refuses FP16 stencil work
    (WC_EINVAL); a later load of SU(3) links returns it to the form the caller
-   last chose (12 by default).  Invalidates the clover term. */
+   last chose (12 by default).  Invalidates the clover term.  Links with a
+   non-finite entry are refused with WC_EINVAL, and the lattice then has no
+   links until a successful load. */
 int wc_load_links(wc_lattice *lat, const void *U_dev);
 /* The reconstruction error measured by the last wc_load_links (0 before any; -1
    for a null lattice). */
@@ -202,8 +219,16 @@ int wc_set_link_recon(wc_lattice *lat, int recon);
 int wc_link_recon(const wc_lattice *lat);
 
 /* Build the clover term F (Sec. II-A) from the loaded links in FP64, split into
-   its two 6x6 Hermitian chiral blocks (Sec. III-A), invert them in FP64, and keep
-   FP64, FP32 and FP16 copies of F and F^-1.  WC_ENOTREADY before wc_load_links. */
+   its two 6x6 Hermitian chiral blocks (Sec. III-A), invert them in FP64 (the
+   inverses F_ee^-1, F_oo^-1 of Sec. II-B, eqs. 6-9), and keep FP64, FP32 and
+   FP16 copies of F and F^-1.  kappa and csw must be finite and >= 0 (WC_EINVAL).
+   There is no global bound on kappa csw: each 6x6 block is inverted by
+   elimination without row exchanges, whose pivots are all real and positive
+   exactly when the block is positive definite, and the call returns WC_EINVAL,
+   naming the number of offending blocks, when some pivot is non-positive or
+   not finite (the lattice then has no clover term until a successful build).
+   Synchronises the stream (the count is read back).  WC_ENOTREADY before
+   wc_load_links. */
 int wc_build_clover(wc_lattice *lat, double kappa, double csw);
 
 /* Bytes of one parity of a spinor field in the internal EO layout of precision prec. */
@@ -233,8 +258,25 @@ int wc_apply_mult(wc_lattice *lat, void *out, const void *in, int out_parity, in
    of precision prec: out_e = D-hat_ee in_e.  Uses the kappa of the built clover. */
 int wc_apply_Dee_oo(wc_lattice *lat, void *out_e, const void *in_e, int prec);
 
-/* Site-diagonal clover: out_p = F_pp in_p (inverse = 0) or F_pp^-1 in_p (inverse = 1)
-   on single-parity EO fields of precision prec. */
+/* Batched forms of wc_apply_mult and wc_apply_Dee_oo: n fields (1 <= n <= 16)
+   on this lattice, out[k] = MULT in[k] (eq. 9) resp. out_e[k] = D-hat_ee in_e[k]
+   (eq. 8), in one launch per MULT (many solutions per gauge field, Sec. II-A).
+   With the multi-system stencil on (wc_set_multi_rhs) and prec WC_FP32 or
+   WC_FP16, each thread applies one site's links and clover blocks to several
+   of the fields; otherwise the fields' workgroups are interleaved.  Arguments
+   as for the single forms; out, in (out_e, in_e) are host arrays of n device
+   pointers.  The D-hat_ee form keeps n single-parity temporaries of the
+   precision in the lattice until it is destroyed. */
+int wc_apply_mult_batch(wc_lattice *lat, int n, void *const *out, const void *const *in, int out_parity, int prec);
+int wc_apply_Dee_oo_batch(wc_lattice *lat, int n, void *const *out_e, const void *const *in_e, int prec);
+
+/* Site-diagonal clover term of parity p: out_p = F_pp in_p (inverse = 0) or
+   F_pp^-1 in_p (inverse = 1), F being the site-diagonal term of eq. 3 (Sec. II-A)
+   and F_ee, F_oo its even and odd blocks in the even-odd form of Sec. II-B
+   (eqs. 5-9).  in and out are single-parity EO fields of precision prec
+   (wc_spinor_bytes each), device memory owned by the caller; they may be the
+   same buffer.  Asynchronous on the lattice's stream.  WC_EINVAL for a null
+   pointer, a bad precision or parity; WC_ENOTREADY without links and clover. */
 int wc_apply_clover(wc_lattice *lat, void *out, const void *in, int parity, int inverse, int prec);
 
 /* Solve D x = b (eq. 1) for canonical complex128 b, x (device pointers) with the
@@ -258,7 +300,10 @@ int wc_solve(wc_lattice *lat, const void *b_dev, double kappa, double csw, doubl
    clover run back to back on one XCD, so those operands are fetched from HBM about
    once for all n.
    wc_solve_multi: system k on lattice lats[k] (lattices of different sizes allowed;
-   systems on one lattice must share kappa and csw), all work on lats[0]'s stream.
+   systems on one lattice must share kappa and csw), all work on lats[0]'s stream:
+   work queued earlier on the other lattices' streams is waited for (an event per
+   stream), and clover rebuilds for a new (kappa, csw) also run on lats[0]'s
+   stream.  The call has finished all its work when it returns.
    info (n entries) may be NULL.  Returns WC_OK when every system met tol, else the
    first failing system's status; x0 guesses are not taken. */
 int wc_solve_batch(wc_lattice *lat, int n, const void *const *b_dev, void *const *x_dev, double kappa,

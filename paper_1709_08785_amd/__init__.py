@@ -12,8 +12,10 @@ tensors (``uint8``) in the library's structure-of-arrays layout.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 
 import torch
 
@@ -104,6 +106,10 @@ def load_library():
         "wc_link_su3_error": (D, [P]),
         "wc_block_size": (I, [P, I]),
         "wc_tune_block_size": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(I)]),
+        "wc_set_multi_rhs": (I, [P, I]),
+        "wc_apply_mult_batch": (I, [P, I, ctypes.POINTER(P), ctypes.POINTER(P), I, I]),
+        "wc_apply_Dee_oo_batch": (I, [P, I, ctypes.POINTER(P), ctypes.POINTER(P), I]),
+        "wc_multi_rhs": (I, [P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -132,6 +138,23 @@ def _ptr(t: torch.Tensor):
     return ctypes.c_void_p(t.data_ptr())
 
 
+# every open lattice, so that all of them are destroyed while the HIP runtime
+# is still fully up: interpreter exit runs these atexit hooks before tearing
+# down modules, whereas a lattice left to garbage collection at the very end
+# could release its streams, graphs and device memory after the runtime (or a
+# profiler attached to it) has begun to unload
+_open_lattices = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all_lattices():
+    for lat in list(_open_lattices):
+        try:
+            lat.close()
+        except Exception:
+            pass
+
+
 class Lattice:
     """A lattice of extents dims = (Lx, Ly, Lz, Lt) with its links and clover term on the GPU."""
 
@@ -144,6 +167,7 @@ class Lattice:
         with torch.cuda.device(self.device):
             _check(self.lib.wc_create_lattice(arr, self._stream(), ctypes.byref(h)))
         self.h = h
+        _open_lattices.add(self)
         lx, ly, lz, lt = self.dims
         self.volume = lx * ly * lz * lt
         self.spinor_shape = (lt, lz, ly, lx, 4, 3)
@@ -159,6 +183,7 @@ class Lattice:
         if getattr(self, "h", None):
             self.lib.wc_destroy_lattice(self.h)
             self.h = None
+        _open_lattices.discard(self)
 
     def __del__(self):
         try:
@@ -205,6 +230,14 @@ class Lattice:
         th = ctypes.c_int()
         _check(self.lib.wc_tune_block_size(self.h, _prec(prec), us, ctypes.byref(th)))
         return {"us_per_pair": {64: us[0], 128: us[1], 256: us[2]}, "threads": th.value}
+
+    def set_multi_rhs(self, systems_per_thread: int):
+        """Systems per thread of the batched solves' multi-system stencil (2 or 4), 0 for one."""
+        _check(self.lib.wc_set_multi_rhs(self.h, int(systems_per_thread)))
+
+    @property
+    def multi_rhs(self) -> int:
+        return int(self.lib.wc_multi_rhs(self.h))
 
     @property
     def link_recon(self) -> int:
@@ -254,6 +287,24 @@ class Lattice:
     def apply_Dee_oo(self, out_e: torch.Tensor, in_e: torch.Tensor, prec):
         self._sync_stream()
         _check(self.lib.wc_apply_Dee_oo(self.h, _ptr(out_e), _ptr(in_e), _prec(prec)))
+
+    def apply_mult_batch(self, outs, ins, out_parity: int, prec):
+        """outs[k] = MULT ins[k] for up to 16 single-parity EO fields, in one launch."""
+        n = len(outs)
+        assert len(ins) == n
+        O = (ctypes.c_void_p * n)(*[_ptr(t).value for t in outs])
+        I_ = (ctypes.c_void_p * n)(*[_ptr(t).value for t in ins])
+        self._sync_stream()
+        _check(self.lib.wc_apply_mult_batch(self.h, n, O, I_, int(out_parity), _prec(prec)))
+
+    def apply_Dee_oo_batch(self, outs, ins, prec):
+        """outs[k] = D-hat_ee ins[k] for up to 16 even-parity EO fields."""
+        n = len(outs)
+        assert len(ins) == n
+        O = (ctypes.c_void_p * n)(*[_ptr(t).value for t in outs])
+        I_ = (ctypes.c_void_p * n)(*[_ptr(t).value for t in ins])
+        self._sync_stream()
+        _check(self.lib.wc_apply_Dee_oo_batch(self.h, n, O, I_, _prec(prec)))
 
     def apply_clover(self, out: torch.Tensor, inp: torch.Tensor, parity: int, inverse: bool, prec):
         self._sync_stream()

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -247,6 +248,7 @@ static void free_all(wc_lattice *lat) {
     if (lat->links18) (void)hipFree(lat->links18);
     if (lat->recon_min) (void)hipFree(lat->recon_min);
     if (lat->recon_err) (void)hipFree(lat->recon_err);
+    if (lat->clov_bad) (void)hipFree(lat->clov_bad);
     for (int k = 0; k < LW_COUNT; k++)
         if (lat->lwork[k]) (void)hipFree(lat->lwork[k]);
     free_work(lat->swork);
@@ -275,7 +277,9 @@ extern "C" int wc_create_lattice(const int dims[4], void *stream, wc_lattice **o
         V *= dims[d];
     }
     if (V / 2 > (1L << 30)) return wc_fail(WC_EINVAL, "lattice too large (V/2 must fit in 30 bits)");
+    static std::atomic<unsigned long long> next_serial{1};
     wc_lattice *lat = new wc_lattice();
+    lat->serial = next_serial.fetch_add(1);
     for (int d = 0; d < 4; d++) {
         lat->dims[d] = dims[d];
         lat->g.L[d] = dims[d];
@@ -411,23 +415,48 @@ extern "C" int wc_solve_multi(int n, wc_lattice *const *lats, const void *const 
         if (lats[k]->recon != lats[0]->recon)
             return wc_fail(WC_EINVAL, "lattices of one batched solve must share the link reconstruction");
         if (int rc = check_links_for(lats[k], P.inner_prec)) return rc;
-        if (int rc = prepare_lattice(lats[k], kappa[k], csw[k])) return rc;
     }
     wc_lattice *lead = lats[0];
-    // every lattice works on the lead lattice's stream for the duration
+    // Every lattice works on the lead lattice's stream for the duration.  Work
+    // already queued on another lattice's own stream is ordered before it by
+    // an event, and the clover rebuilds below then run on the lead stream too,
+    // so nothing of the solve can overtake them.
     std::vector<hipStream_t> saved(n);
     for (int k = 0; k < n; k++) saved[k] = lats[k]->stream;
-    for (int k = 0; k < n; k++) lats[k]->stream = lead->stream;
     auto restore = [&] {
         for (int k = 0; k < n; k++) lats[k]->stream = saved[k];
     };
+    {
+        hipEvent_t ev = nullptr;
+        for (int k = 0; k < n; k++) {
+            bool seen = saved[k] == lead->stream;
+            for (int j = 0; j < k && !seen; j++) seen = saved[j] == saved[k];
+            if (seen) continue;
+            if (!ev) WC_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+            hipError_t e = hipEventRecord(ev, saved[k]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(lead->stream, ev, 0);
+            if (e != hipSuccess) {
+                (void)hipEventDestroy(ev);
+                return wc_fail(WC_EHIP, std::string("ordering the lattices' streams: ") + hipGetErrorString(e));
+            }
+        }
+        if (ev) WC_HIP(hipEventDestroy(ev));
+    }
+    for (int k = 0; k < n; k++) lats[k]->stream = lead->stream;
+    for (int k = 0; k < n; k++)
+        if (int rc = prepare_lattice(lats[k], kappa[k], csw[k])) {
+            restore();
+            return rc;
+        }
+    // the cached systems are reused only for the same lattices, named by their
+    // serial numbers: a destroyed lattice's address may come back with a new one
     BatchCache *bc = lead->batch;
-    bool reuse = bc && (int)bc->lats.size() == n;
-    for (int k = 0; reuse && k < n; k++) reuse = bc->lats[k] == lats[k];
+    bool reuse = bc && (int)bc->serials.size() == n;
+    for (int k = 0; reuse && k < n; k++) reuse = bc->serials[k] == lats[k]->serial;
     if (!reuse) {
         free_batch(bc);
         lead->batch = bc = new BatchCache();
-        bc->lats.assign(lats, lats + n);
+        for (int k = 0; k < n; k++) bc->serials.push_back(lats[k]->serial);
         bc->sys.resize(n);
         bc->work.resize(n);
         if (int rc = arena_alloc(bc->arena, n, lead->stream)) {
@@ -546,8 +575,13 @@ extern "C" int wc_load_links(wc_lattice *lat, const void *U_dev) {
     WC_HIP(hipStreamSynchronize(lat->stream));
     std::memcpy(&lat->su3_err, &bits, sizeof(bits));
     lat->gen++;
-    lat->have_links = true;
     lat->have_clover = false;
+    if (!std::isfinite(lat->su3_err)) {
+        lat->have_links = false;  // the copies now hold the bad entries
+        lat->su3_err = 0.f;
+        return wc_fail(WC_EINVAL, "the links have non-finite entries");
+    }
+    lat->have_links = true;
     if (lat->su3_err > kSU3MaxErr) {
         // not SU(3) to single precision: no two-column form holds, so the
         // FP32 stencil reads the links in full (FP16 is refused)
@@ -600,8 +634,8 @@ extern "C" int wc_link_recon(const wc_lattice *lat) { return lat ? lat->recon : 
 extern "C" int wc_build_clover(wc_lattice *lat, double kappa, double csw) {
     if (!lat) return wc_fail(WC_EINVAL, "null lattice");
     if (!lat->have_links) return wc_fail(WC_ENOTREADY, "wc_build_clover before wc_load_links");
-    if (!(kappa >= 0.0) || !(csw >= 0.0) || kappa * csw * 6.0 >= 1.0)
-        return wc_fail(WC_EINVAL, "need kappa >= 0, csw >= 0 and 6 kappa csw < 1 (F positive definite)");
+    if (!(kappa >= 0.0) || !(csw >= 0.0) || !std::isfinite(kappa) || !std::isfinite(csw))
+        return wc_fail(WC_EINVAL, "need finite kappa >= 0 and csw >= 0");
     for (int p = 0; p < 3; p++) {
         if (!lat->clov[p]) {
             int rc = dev_alloc(&lat->clov[p], 2 * clover_slab_bytes(p, lat->Vh));
@@ -612,11 +646,27 @@ extern "C" int wc_build_clover(wc_lattice *lat, double kappa, double csw) {
             if (rc) return rc;
         }
     }
-    int rc = launch_build_clover(lat, kappa, csw);
+    if (!lat->clov_bad) {
+        int rc = dev_alloc((void **)&lat->clov_bad, sizeof(unsigned));
+        if (rc) return rc;
+    }
+    // whatever happens below, the blocks being overwritten are no longer the
+    // clover term of any (kappa, csw)
+    lat->have_clover = false;
+    lat->gen++;
+    WC_HIP(hipMemsetAsync(lat->clov_bad, 0, sizeof(unsigned), lat->stream));
+    int rc = launch_build_clover(lat, kappa, csw, lat->clov_bad);
     if (rc) return rc;
+    unsigned bad = 0;
+    WC_HIP(hipMemcpyAsync(&bad, lat->clov_bad, sizeof(bad), hipMemcpyDeviceToHost, lat->stream));
+    WC_HIP(hipStreamSynchronize(lat->stream));
+    if (bad)
+        return wc_fail(WC_EINVAL, std::to_string(bad) + " of the " + std::to_string(2 * lat->V) +
+                                      " 6x6 clover blocks are not positive definite at kappa = " +
+                                      std::to_string(kappa) + ", csw = " + std::to_string(csw) +
+                                      " (a non-positive or non-finite elimination pivot)");
     lat->kappa = kappa;
     lat->csw = csw;
-    lat->gen++;
     lat->have_clover = true;
     return WC_OK;
 }
@@ -750,6 +800,17 @@ extern "C" int wc_set_block_size(wc_lattice *lat, int threads) {
     return WC_OK;
 }
 
+extern "C" int wc_set_multi_rhs(wc_lattice *lat, int systems_per_thread) {
+    if (!lat) return wc_fail(WC_EINVAL, "null lattice");
+    if (systems_per_thread != 0 && systems_per_thread != 2 && systems_per_thread != 4)
+        return wc_fail(WC_EINVAL, "systems per thread must be 0, 2 or 4");
+    if (systems_per_thread != lat->mrhs) lat->gen++;  // recorded graphs hold the old kernels
+    lat->mrhs = systems_per_thread;
+    return WC_OK;
+}
+
+extern "C" int wc_multi_rhs(const wc_lattice *lat) { return lat ? lat->mrhs : -1; }
+
 extern "C" int wc_block_size(const wc_lattice *lat, int prec) {
     if (!lat || prec < 0 || prec > 2) return 0;
     return lat->bs_pin ? lat->bs_pin : lat->bs_tuned[prec];
@@ -788,6 +849,49 @@ extern "C" int wc_apply_mult(wc_lattice *lat, void *out, const void *in, int out
     if (int rc = check_links_for(lat, prec)) return rc;
     MultCall c = mult_call(prec, M_HOPINV, out_parity, out, in, nullptr, 0.0);
     return launch_mult(lat, c);
+}
+
+extern "C" int wc_apply_mult_batch(wc_lattice *lat, int n, void *const *out, const void *const *in, int out_parity,
+                                   int prec) {
+    if (!lat || !out || !in) return wc_fail(WC_EINVAL, "null argument");
+    if (n < 1 || n > kMaxSys) return wc_fail(WC_EINVAL, "n must lie in [1, 16]");
+    for (int k = 0; k < n; k++)
+        if (!out[k] || !in[k]) return wc_fail(WC_EINVAL, "null field");
+    if (int rc = check_prec(prec)) return rc;
+    if (out_parity != 0 && out_parity != 1) return wc_fail(WC_EINVAL, "out_parity must be 0 or 1");
+    if (int rc = check_ready(lat)) return rc;
+    if (int rc = check_links_for(lat, prec)) return rc;
+    MultCall calls[kMaxSys];
+    for (int k = 0; k < n; k++) {
+        calls[k] = mult_call(prec, M_HOPINV, out_parity, out[k], in[k], nullptr, 0.0);
+        calls[k].lat = lat;
+        calls[k].bs = lattice_bs(lat, prec);
+    }
+    return launch_mult_batch(lat->stream, calls, n);
+}
+
+extern "C" int wc_apply_Dee_oo_batch(wc_lattice *lat, int n, void *const *out_e, const void *const *in_e, int prec) {
+    if (!lat || !out_e || !in_e) return wc_fail(WC_EINVAL, "null argument");
+    if (n < 1 || n > kMaxSys) return wc_fail(WC_EINVAL, "n must lie in [1, 16]");
+    for (int k = 0; k < n; k++) {
+        if (!out_e[k] || !in_e[k]) return wc_fail(WC_EINVAL, "null field");
+        if (out_e[k] == in_e[k]) return wc_fail(WC_EINVAL, "wc_apply_Dee_oo_batch cannot work in place");
+    }
+    if (int rc = check_prec(prec)) return rc;
+    if (int rc = check_ready(lat)) return rc;
+    if (int rc = check_links_for(lat, prec)) return rc;
+    const size_t sb = spinor_bytes(prec, lat->Vh);
+    char *tmp;
+    if (int rc = lwork(lat, LW_APPLY_TMP, (size_t)n * sb, (void **)&tmp)) return rc;
+    MultCall c1[kMaxSys], c2[kMaxSys];
+    for (int k = 0; k < n; k++) {
+        c1[k] = mult_call(prec, M_HOPINV, 1, tmp + k * sb, in_e[k], nullptr, 0.0);
+        c2[k] = mult_call(prec, M_DHAT, 0, out_e[k], tmp + k * sb, in_e[k], -lat->kappa * lat->kappa);
+        c1[k].lat = c2[k].lat = lat;
+        c1[k].bs = c2[k].bs = lattice_bs(lat, prec);
+    }
+    if (int rc = launch_mult_batch(lat->stream, c1, n)) return rc;
+    return launch_mult_batch(lat->stream, c2, n);
 }
 
 extern "C" int wc_apply_Dee_oo(wc_lattice *lat, void *out_e, const void *in_e, int prec) {

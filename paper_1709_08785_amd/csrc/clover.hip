@@ -156,9 +156,15 @@ __device__ __forceinline__ void add_kron(C (&M)[6][6], C coef, const C (&S)[2][2
         }
 }
 
-// Hermitian positive definite 6x6 inverse (Gauss-Jordan, no pivoting needed)
-__device__ void inv6(const C (&A)[6][6], C (&Ai)[6][6]) {
+// 6x6 inverse by Gauss-Jordan elimination without row exchanges.  For a
+// Hermitian matrix the pivots met on the way are the ratios of successive
+// leading principal minors, so they are all real and positive exactly when the
+// matrix is positive definite; the return value counts the pivots that are
+// not (non-positive or non-finite real part), 0 for a positive definite block,
+// for which elimination without exchanges is stable.
+__device__ int inv6(const C (&A)[6][6], C (&Ai)[6][6]) {
     C a[6][12];
+    int bad = 0;
     for (int i = 0; i < 6; i++)
         for (int j = 0; j < 6; j++) {
             a[i][j] = A[i][j];
@@ -166,6 +172,7 @@ __device__ void inv6(const C (&A)[6][6], C (&Ai)[6][6]) {
         }
     for (int col = 0; col < 6; col++) {
         const C d = a[col][col];
+        if (!(d.re > 0.0) || !isfinite(d.re) || !isfinite(d.im)) bad++;
         const double dn = d.re * d.re + d.im * d.im;
         const C dinv = {d.re / dn, -d.im / dn};
         for (int j = 0; j < 12; j++) a[col][j] = a[col][j] * dinv;
@@ -177,6 +184,7 @@ __device__ void inv6(const C (&A)[6][6], C (&Ai)[6][6]) {
     }
     for (int i = 0; i < 6; i++)
         for (int j = 0; j < 6; j++) Ai[i][j] = a[i][6 + j];
+    return bad;
 }
 
 // pack the Hermitian part of M (times `scale`) into 6 reals + 15 complex
@@ -223,8 +231,10 @@ __device__ void store_block_set(const CloverOut &o, bool inv, int par, int Vh, i
     *tp<float, 148>(d16, i, 144) = s;
 }
 
+// bad_blocks: device counter of the 6x6 blocks (two per site) that are not
+// positive definite, incremented by the kernel
 __global__ __launch_bounds__(64) void k_build_clover(Geom g, const double2 *l64, CloverOut o, double kappa,
-                                                     double csw) {
+                                                     double csw, unsigned *bad_blocks) {
     const int i = blockIdx.x * 64 + threadIdx.x;
     const int par = blockIdx.y;
     if (i >= g.Vh) return;
@@ -259,22 +269,24 @@ __global__ __launch_bounds__(64) void k_build_clover(Geom g, const double2 *l64,
 
     C M[6][6], Mi[6][6];
     double fF[2][36], fI[2][36];
+    unsigned nbad = 0;
     // block 0: A - B (g5 = +1), block 1: A + B (g5 = -1); store halves
     for (int blk = 0; blk < 2; blk++) {
         const double sgn = blk == 0 ? -1.0 : 1.0;
         for (int r = 0; r < 6; r++)
             for (int s = 0; s < 6; s++) M[r][s] = A[r][s] + sgn * B[r][s];
-        inv6(M, Mi);
+        nbad += inv6(M, Mi) != 0;
         pack_herm(M, 0.5, fF[blk]);
         pack_herm(Mi, 0.5, fI[blk]);
     }
     store_block_set(o, false, par, g.Vh, i, fF);
     store_block_set(o, true, par, g.Vh, i, fI);
+    if (nbad) atomicAdd(bad_blocks, nbad);
 }
 
 }  // namespace
 
-int launch_build_clover(wc_lattice *lat, double kappa, double csw) {
+int launch_build_clover(wc_lattice *lat, double kappa, double csw, unsigned *bad_blocks) {
     CloverOut o;
     o.f64 = (char *)lat->clov[P64];
     o.i64 = (char *)lat->clovinv[P64];
@@ -284,7 +296,7 @@ int launch_build_clover(wc_lattice *lat, double kappa, double csw) {
     o.i16 = (char *)lat->clovinv[P16];
     dim3 grid((lat->Vh + 63) / 64, 2);
     hipLaunchKernelGGL(k_build_clover, grid, dim3(64), 0, lat->stream, lat->g, (const double2 *)lat->links[P64], o,
-                       kappa, csw);
+                       kappa, csw, bad_blocks);
     WC_HIP(hipGetLastError());
     return WC_OK;
 }

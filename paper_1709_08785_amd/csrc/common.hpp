@@ -32,15 +32,24 @@ template <class R> WC_HD cx<R> cmulc(cx<R> a, cx<R> b) {
 // i * a, -i * a
 template <class R> WC_HD cx<R> mul_i(cx<R> a) { return {-a.im, a.re}; }
 template <class R> WC_HD cx<R> mul_mi(cx<R> a) { return {a.im, -a.re}; }
-// acc += a * b
+// fused multiply-add in the precision of R
+WC_HD float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+WC_HD double fmar(double a, double b, double c) { return __builtin_fma(a, b, c); }
+// acc += a * b, as a chain of four fused multiply-adds into the accumulator
+// (written out: "acc + (a.re b.re - a.im b.im)" would cost a multiply, an FMA
+// and an add per component, since the sum may not be reassociated)
 template <class R> WC_HD void cmac(cx<R> &acc, cx<R> a, cx<R> b) {
-    acc.re += a.re * b.re - a.im * b.im;
-    acc.im += a.re * b.im + a.im * b.re;
+    acc.re = fmar(a.re, b.re, acc.re);
+    acc.re = fmar(-a.im, b.im, acc.re);
+    acc.im = fmar(a.re, b.im, acc.im);
+    acc.im = fmar(a.im, b.re, acc.im);
 }
-// acc += conj(a) * b
+// acc += conj(a) * b, likewise
 template <class R> WC_HD void cmacc(cx<R> &acc, cx<R> a, cx<R> b) {
-    acc.re += a.re * b.re + a.im * b.im;
-    acc.im += a.re * b.im - a.im * b.re;
+    acc.re = fmar(a.re, b.re, acc.re);
+    acc.re = fmar(a.im, b.im, acc.re);
+    acc.im = fmar(a.re, b.im, acc.im);
+    acc.im = fmar(-a.im, b.re, acc.im);
 }
 template <class R> WC_HD R norm2(cx<R> a) { return a.re * a.re + a.im * a.im; }
 

@@ -280,6 +280,208 @@ double mult_operator_bytes(int prec, int mode, int lr, int Vh) {
 
 
 // ---------------------------------------------------------------------------
+// Several right-hand sides on one lattice (many solutions per gauge field,
+// Sec. II-A): one thread takes one output site for G systems at once.  The
+// neighbour indices, each link (with its third column rebuilt) and each
+// clover block are computed or loaded once and applied to all G spinors, so
+// the per-site work that does not depend on the source is shared, and the
+// operator is read from memory once per site for every system of the launch.
+// A wavefront covers 64 consecutive sites of one group of G systems; the
+// waves of one tile's groups are adjacent in the launch order (and so on one
+// XCD), so their link and clover loads after the first hit in cache.
+// Reductions are per wave: each wave folds its G systems' sums and writes one
+// partial per system and tile, which the finalize stage sums in tile order.
+// ---------------------------------------------------------------------------
+struct MrhsSys {
+    void *out;
+    const void *in;
+    const void *center;
+    const void *aux;
+    double *partials;  // [N][ntiles] of this system
+    const int *done;
+};
+
+struct MrhsArgs {
+    Geom g;
+    int out_par;
+    const char *links;
+    size_t link_slab;
+    const void *clov;
+    double coef;
+    int nsys;     // systems of the launch
+    int ngroups;  // groups of G systems: ceil(nsys / G)
+    int ntiles;   // 64-site tiles of one parity
+    MrhsSys s[kMaxSys];
+};
+
+// one stored 6x6 block; FP16 blocks without their site scale
+template <int P>
+__device__ __forceinline__ Herm6<typename Real<P>::T> clover_block(const void *slab, int Vh, int i, int b) {
+    if constexpr (P == P16) return CloverIO<P16>::template load_scaled<false>(slab, Vh, i, b, 1.0f);
+    else return CloverIO<P>::template load<false>(slab, Vh, i, b);
+}
+
+// out_j = M_blk(w_j) applied blockwise as in clover_apply, for G spinors, each
+// 6x6 block loaded once: on entry acc[j] holds the hopping sum, on exit the
+// clover result
+template <int P, int G, class R>
+__device__ __forceinline__ void clover_apply_multi(const void *slab, int Vh, int i, Spinor<R> (&acc)[G],
+                                                   const bool (&live)[G]) {
+    // acc.up <- wp = up + dn, acc.dn <- M1 (up - dn)
+    {
+        const Herm6<R> M1 = clover_block<P>(slab, Vh, i, 0);
+#pragma unroll
+        for (int j = 0; j < G; j++) {
+            if (!live[j]) continue;
+            cx<R> wm[6], ym[6];
+#pragma unroll
+            for (int k = 0; k < 6; k++) {
+                wm[k] = acc[j].c[k] - acc[j].c[k + 6];
+                acc[j].c[k] = acc[j].c[k] + acc[j].c[k + 6];
+            }
+            herm6_apply(M1, wm, ym);
+#pragma unroll
+            for (int k = 0; k < 6; k++) acc[j].c[k + 6] = ym[k];
+        }
+    }
+    const Herm6<R> M2 = clover_block<P>(slab, Vh, i, 1);
+    R s = R(1);
+    if constexpr (P == P16) s = CloverIO<P16>::scale(slab, i);
+#pragma unroll
+    for (int j = 0; j < G; j++) {
+        if (!live[j]) continue;
+        cx<R> yp[6];
+        herm6_apply(M2, acc[j].c, yp);
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            const cx<R> ym = acc[j].c[k + 6];
+            acc[j].c[k] = s * (yp[k] + ym);
+            acc[j].c[k + 6] = s * (yp[k] - ym);
+        }
+    }
+}
+
+template <int P, int MU, int LR, int G>
+__device__ __forceinline__ void hop_dir_multi(const MrhsArgs &A, const SiteCoord &c, int i, int q,
+                                              Spinor<typename Real<P>::T> (&acc)[G], const bool (&live)[G]) {
+    using R = typename Real<P>::T;
+    const int Vh = A.g.Vh;
+    {
+        const int nf = eo_neighbour(A.g, c, MU, +1);
+        const Mat3<R> U = LinkLoad<P, LR>::template load<false>(A.links + (size_t)(2 * MU + A.out_par) * A.link_slab, Vh, i);
+#pragma unroll
+        for (int j = 0; j < G; j++)
+            if (live[j]) hop_one<P, MU, true>(A.s[q * G + j].in, Vh, nf, U, acc[j]);
+    }
+    {
+        const int nb = eo_neighbour(A.g, c, MU, -1);
+        const Mat3<R> U =
+            LinkLoad<P, LR>::template load<false>(A.links + (size_t)(2 * MU + 1 - A.out_par) * A.link_slab, Vh, nb);
+#pragma unroll
+        for (int j = 0; j < G; j++)
+            if (live[j]) hop_one<P, MU, false>(A.s[q * G + j].in, Vh, nb, U, acc[j]);
+    }
+}
+
+template <int P, int MODE, int RED, int LR, int G>
+__global__ __launch_bounds__(kBlock) void k_mult_mrhs(MrhsArgs A) {
+    using R = typename Real<P>::T;
+    // wave index over (tile, group) pairs, tile-major; uniform across the wave
+    const int f = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) +
+                                                 (int)(threadIdx.x >> 6));
+    const int tile = f / A.ngroups, q = f - tile * A.ngroups;
+    if (tile >= A.ntiles) return;  // whole wave: the tail of the last block
+    bool live[G];
+    bool any = false;
+#pragma unroll
+    for (int j = 0; j < G; j++) {
+        const int s = q * G + j;
+        live[j] = s < A.nsys && !(A.s[s].done && *A.s[s].done);
+        any = any || live[j];
+    }
+    if (!any) return;  // every system of this wave has stopped
+    const int Vh = A.g.Vh;
+    const int i = tile * 64 + (int)(threadIdx.x & 63);
+    const bool active = i < Vh;
+    Spinor<R> acc[G];
+#pragma unroll
+    for (int j = 0; j < G; j++)
+#pragma unroll
+        for (int k = 0; k < 12; k++) acc[j].c[k] = {R(0), R(0)};
+    if (active) {
+        const SiteCoord c = eo_coords(A.g, i, A.out_par);
+        hop_dir_multi<P, 0, LR, G>(A, c, i, q, acc, live);
+        hop_dir_multi<P, 1, LR, G>(A, c, i, q, acc, live);
+        hop_dir_multi<P, 2, LR, G>(A, c, i, q, acc, live);
+        hop_dir_multi<P, 3, LR, G>(A, c, i, q, acc, live);
+        clover_apply_multi<P, G>(A.clov, Vh, i, acc, live);
+        const R coef = (R)A.coef;
+#pragma unroll
+        for (int j = 0; j < G; j++) {
+            if (!live[j]) continue;
+            const MrhsSys &S = A.s[q * G + j];
+            if (MODE == M_DHAT) {
+                const Spinor<R> cen = SpinorIO<P>::template load<true>(S.center, Vh, i);
+#pragma unroll
+                for (int k = 0; k < 12; k++) acc[j].c[k] = cen.c[k] + coef * acc[j].c[k];
+            }
+            SpinorIO<P>::template store<false>(S.out, Vh, i, acc[j]);
+        }
+    }
+    if (RED != R_NONE) {
+        constexpr int N = (RED == R_DOT) ? 2 : 3;
+#pragma unroll
+        for (int j = 0; j < G; j++) {
+            if (!live[j]) continue;
+            const MrhsSys &S = A.s[q * G + j];
+            double v[N];
+#pragma unroll
+            for (int k = 0; k < N; k++) v[k] = 0.0;
+            if (active) {
+                const Spinor<R> ax = SpinorIO<P>::template load<true>(S.aux, Vh, i);
+#pragma unroll
+                for (int k = 0; k < 12; k++) {
+                    const double ar = ax.c[k].re, ai = ax.c[k].im, orr = acc[j].c[k].re, oi = acc[j].c[k].im;
+                    v[0] += ar * orr + ai * oi;
+                    v[1] += ar * oi - ai * orr;
+                    if (N == 3) v[N - 1] += orr * orr + oi * oi;
+                }
+            }
+            wave_fold<N>(v);
+            if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+                for (int k = 0; k < N; k++) S.partials[(size_t)k * A.ntiles + tile] = v[k];
+            }
+        }
+    }
+}
+
+template <int P, int MODE, int RED, int LR, int G>
+void launch_mrhs_g(const MrhsArgs &A, int blocks, hipStream_t s) {
+    hipLaunchKernelGGL((k_mult_mrhs<P, MODE, RED, LR, G>), dim3(blocks), dim3(kBlock), 0, s, A);
+}
+
+template <int P, int MODE, int RED, int LR> void launch_mrhs_lr(const MrhsArgs &A, int blocks, hipStream_t s, int G) {
+    if (G == 2) launch_mrhs_g<P, MODE, RED, LR, 2>(A, blocks, s);
+    else launch_mrhs_g<P, MODE, RED, LR, 4>(A, blocks, s);
+}
+
+template <int P, int MODE, int RED> void launch_mrhs_mode(const MrhsArgs &A, int blocks, hipStream_t s, int lr, int G) {
+    if constexpr (P == P32) {
+        if (lr == 8) return launch_mrhs_lr<P, MODE, RED, 8>(A, blocks, s, G);
+        if (lr == 18) return launch_mrhs_lr<P, MODE, RED, 18>(A, blocks, s, G);
+    }
+    launch_mrhs_lr<P, MODE, RED, 12>(A, blocks, s, G);
+}
+
+template <int P> void dispatch_mrhs(const MrhsArgs &A, int mode, int red, int blocks, hipStream_t s, int lr, int G) {
+    if (mode == M_HOPINV) launch_mrhs_mode<P, M_HOPINV, R_NONE>(A, blocks, s, lr, G);
+    else if (red == R_DOT) launch_mrhs_mode<P, M_DHAT, R_DOT>(A, blocks, s, lr, G);
+    else if (red == R_DOTNORM) launch_mrhs_mode<P, M_DHAT, R_DOTNORM>(A, blocks, s, lr, G);
+    else launch_mrhs_mode<P, M_DHAT, R_NONE>(A, blocks, s, lr, G);
+}
+
+// ---------------------------------------------------------------------------
 // The whole inner loop (Algorithm 2) in one cooperative launch, for lattices
 // small enough that every workgroup is resident at once.  Each phase of an
 // iteration ends in a grid-wide barrier instead of a kernel boundary; every
@@ -657,10 +859,80 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(P == P64
 
 }  // namespace
 
+// Several calls on one lattice through the multi-system stencil: G systems per
+// thread, the operator loaded once per site for all of them.
+static int launch_mult_mrhs(hipStream_t s, const MultCall *calls, int n, wc_lattice *tl, int G) {
+    const MultCall &c0 = calls[0];
+    wc_lattice *lat = c0.lat;
+    const int lr = c0.prec == P32 ? lat->recon : 12;
+    MrhsArgs A;
+    A.g = lat->g;
+    A.out_par = c0.out_par;
+    A.links = (const char *)link_base(lat, c0.prec);
+    A.link_slab = link_slab_for(lat, c0.prec);
+    A.clov = (const char *)lat->clovinv[c0.prec] + (size_t)c0.out_par * clover_slab_bytes(c0.prec, lat->Vh);
+    A.coef = c0.coef;
+    A.nsys = n;
+    A.ngroups = (n + G - 1) / G;
+    A.ntiles = blocks_of(lat->Vh, 64);
+    double bytes = mult_operator_bytes(c0.prec, c0.mode, lr, lat->Vh);
+    for (int k = 0; k < n; k++) {
+        const MultCall &c = calls[k];
+        if (c.coef != c0.coef) return wc_fail(WC_EINVAL, "multi-system stencil calls must share the coefficient");
+        A.s[k] = MrhsSys{c.out, c.in, c.center, c.aux, c.red_to.partials, c.done};
+        bytes += mult_spinor_bytes(c.prec, c.mode, c.red, c.aux == c.center, lat->Vh);
+        lat->dslash_count++;
+    }
+    const long waves = (long)A.ntiles * A.ngroups;
+    const int blocks = (int)((waves + kBlock / 64 - 1) / (kBlock / 64));
+    int slot = c0.mode == M_HOPINV ? KS_MULT_HOPINV_P64 + c0.prec : KS_MULT_DHAT_P64 + c0.prec;
+    TimedLaunch t;
+    if (tl->timing) {
+        timing_begin(tl, slot, bytes, t);
+        t.iter = tl->tag_iter;
+        t.phase = tl->tag_phase;
+        TimedPart op{{}, mult_operator_bytes(c0.prec, c0.mode, lr, lat->Vh)};
+        for (int k = 0; k < n; k++) {
+            const MultCall &c = calls[k];
+            t.parts.push_back(TimedPart{{c.done}, mult_spinor_bytes(c.prec, c.mode, c.red, c.aux == c.center,
+                                                                      lat->Vh)});
+            op.owners.push_back(c.done);
+        }
+        t.parts.push_back(op);
+    }
+    if (c0.prec == P32) dispatch_mrhs<P32>(A, c0.mode, c0.red, blocks, s, lr, G);
+    else dispatch_mrhs<P16>(A, c0.mode, c0.red, blocks, s, 12, G);
+    WC_HIP(hipGetLastError());
+    if (tl->timing) timing_end(tl, t);
+    if (c0.red != R_NONE) {
+        FinArgs f[kMaxSys];
+        for (int k = 0; k < n; k++) {
+            f[k] = FinArgs{};
+            f[k].blocks = A.ntiles;  // one partial per 64-site tile
+            f[k].op = FIN_STORE;
+            f[k].partials = calls[k].red_to.partials;
+            f[k].result = calls[k].red_to.result;
+            f[k].guard = calls[k].done;
+        }
+        return launch_fin_batch(s, f, n, c0.red == R_DOT ? 2 : 3);
+    }
+    return WC_OK;
+}
+
 int launch_mult_batch(hipStream_t s, const MultCall *calls, int n, wc_lattice *timing_lat) {
     if (n <= 0) return WC_OK;
     if (n > kMaxSys) return wc_fail(WC_EINVAL, "too many systems in one batch");
     const MultCall &c0 = calls[0];
+    {
+        // several systems on one lattice in an inner-precision stencil: the
+        // multi-system form, when the lattice has it switched on
+        bool same = n > 1 && c0.lat->mrhs > 0 && (c0.prec == P32 || c0.prec == P16) &&
+                    (c0.mode == M_HOPINV || c0.mode == M_DHAT);
+        for (int k = 1; same && k < n; k++)
+            same = calls[k].lat == c0.lat && calls[k].prec == c0.prec && calls[k].mode == c0.mode &&
+                   calls[k].red == c0.red && calls[k].out_par == c0.out_par && calls[k].coef == c0.coef;
+        if (same) return launch_mult_mrhs(s, calls, n, timing_lat ? timing_lat : c0.lat, c0.lat->mrhs);
+    }
     const int bs = launch_bs(c0.bs);
     if (!valid_block_size(bs)) return wc_fail(WC_EINVAL, "block size must be 64, 128 or 256");
     MultBatch B;

@@ -145,7 +145,7 @@ struct SysWork {
 // A cached set of systems (arena, per-system partials and work vectors) for
 // batched solves on a given list of lattices.
 struct BatchCache {
-    std::vector<wc_lattice *> lats;
+    std::vector<unsigned long long> serials;  // serial numbers of its lattices (wc_lattice::serial)
     Arena arena;
     std::vector<SysState> sys;
     std::vector<SysWork> work;
@@ -155,6 +155,9 @@ struct BatchCache {
 enum LatWorkId { LW_APPLY_IN = 0, LW_APPLY_OUT, LW_APPLY_TMP, LW_GLAM, LW_GX, LW_GN, LW_COUNT };
 
 struct wc_lattice {
+    // process-unique number of this handle (never reused, unlike its address):
+    // cached batches and recorded graphs name their lattices by it
+    unsigned long long serial = 0;
     Geom g;
     int dims[4];
     long V;
@@ -165,6 +168,9 @@ struct wc_lattice {
     // by the caller, else chosen per precision by the tuner (0 = not yet)
     int bs_pin = 0;
     int bs_tuned[3] = {0, 0, 0};
+    // systems per thread of the multi-system stencil that batched solves on
+    // this lattice use in their inner loop (2 or 4), 0 for one system per thread
+    int mrhs = 4;
 
     // gauge links per precision: 8 slabs ([mu][parity]) of link_slab_bytes
     void *links[3] = {nullptr, nullptr, nullptr};
@@ -178,6 +184,7 @@ struct wc_lattice {
     int recon_user = 12;            // the form last chosen by the caller, restored for SU(3) links
     unsigned *recon_min = nullptr;  // device word: smallest N as FP32 bits
     unsigned *recon_err = nullptr;  // device word: largest reconstruct-12 error as FP32 bits
+    unsigned *clov_bad = nullptr;   // device word: clover blocks that are not positive definite
     float su3_err = 0.f;            // that error for the loaded links (0 before any)
     // clover F and F^-1 per precision: 2 slabs ([parity]) of clover_slab_bytes
     void *clov[3] = {nullptr, nullptr, nullptr};
@@ -396,7 +403,9 @@ int launch_unpack_spinor(wc_lattice *lat, int prec, void *canon_out, const void 
 int launch_load_links(wc_lattice *lat, const void *U, unsigned *err_bits);
 int launch_links_recon8(wc_lattice *lat, unsigned *min_bits);
 int launch_links_full32(wc_lattice *lat);  // links18 from the FP64 copy
-int launch_build_clover(wc_lattice *lat, double kappa, double csw);
+// builds F and F^-1; *bad_blocks (device word, zeroed by the caller) receives the
+// number of 6x6 blocks that are not positive definite
+int launch_build_clover(wc_lattice *lat, double kappa, double csw, unsigned *bad_blocks);
 int launch_link_grad(wc_lattice *lat, const void *lam_eo, const void *x_eo, void *G, void *Nbuf, double kappa,
                      double csw, bool clover);
 

@@ -51,7 +51,12 @@ __global__ __launch_bounds__(kBlock) void k_load_links(Geom g, const double2 *U,
         u.w = f2h((float)m[1].x, (float)m[1].y);
         *tp<uint4, 24>(b16, i, 0) = u;
         *tp<uint2, 24>(b16, i, 16) = make_uint2(f2h((float)m[4].x, (float)m[4].y), f2h((float)m[7].x, (float)m[7].y));
-        err = recon12_error(m);
+        bool finite = true;
+    #pragma unroll
+        for (int k = 0; k < 9; k++) finite = finite && isfinite(m[k].x) && isfinite(m[k].y);
+        // a non-finite entry posts +inf, which orders above every finite error
+        // (a NaN would be dropped by the max below)
+        err = finite ? recon12_error(m) : INFINITY;
     }
     // non-negative floats order like their bits
 #pragma unroll

@@ -234,7 +234,7 @@ int inner_chunk_graph(Run &R, const std::vector<int> &act, int n) {
     mix((unsigned long long)R.bs);
     for (int k : act) {
         mix((unsigned long long)k);
-        mix((unsigned long long)(uintptr_t)S_(R, k).lat);
+        mix(S_(R, k).lat->serial);
         mix((unsigned long long)S_(R, k).lat->gen);
     }
     hipGraphExec_t exec = nullptr;

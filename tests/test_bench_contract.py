@@ -29,8 +29,21 @@ def test_table1_counts():
     assert bench.table1_gflops("blas", 10 ** 6, 1000.0) is None
 
 
-def test_traffic_is_null_for_other_sources(tmp_path, monkeypatch):
+def test_traffic_is_null_for_other_sources_or_shapes(tmp_path, monkeypatch):
     # HBM bytes from the stored counters are used only while the kernel
-    # sources hash to the value they were taken on
+    # sources hash to the value they were taken on, and only for the lattice
+    # and link form they were taken on
+    import json
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    entry = {"source_hash": "abcdabcdabcdabcd", "lattice": [32, 32, 32, 64], "link_recon": 12,
+             "kernel": "mult_dhat_fp32", "hbm_bytes_per_launch": 123}
+    (prof / "traffic.json").write_text(json.dumps({"entries": [entry]}))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "source_hash", lambda: "abcdabcdabcdabcd")
+    assert bench.traffic_for("mult_dhat_fp32", (32, 32, 32, 64), 12) == 123
+    assert bench.traffic_for("mult_dhat_fp32", (48, 48, 48, 96), 12) is None
+    assert bench.traffic_for("mult_dhat_fp32", (32, 32, 32, 64), 8) is None
+    assert bench.traffic_for("mult_hopinv_fp32", (32, 32, 32, 64), 12) is None
     monkeypatch.setattr(bench, "source_hash", lambda: "0000000000000000")
-    assert bench.traffic_for("mult_dhat_fp32", 1.0) is None
+    assert bench.traffic_for("mult_dhat_fp32", (32, 32, 32, 64), 12) is None

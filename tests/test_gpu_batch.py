@@ -6,6 +6,7 @@ oracle finishes in seconds (1e-10 relative), the oracle's true residual at the
 full 32^3 x 64 size, and bit-identity with separate single solves (each
 system keeps its own reductions in the same order).
 """
+import os
 import sys
 
 import numpy as np
@@ -16,17 +17,15 @@ torch = pytest.importorskip("torch")
 import oracle
 import synth
 
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from gpu_checks import check_true_residual, say  # noqa: E402
+
 pytestmark = pytest.mark.gpu
 
 if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
 import paper_1709_08785_amd as wc  # noqa: E402
-
-
-def say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
 
 
 def dev(a):
@@ -85,9 +84,9 @@ def test_batch_matches_single_solves(inner):
 
 @pytest.mark.parametrize("inner,recon", [(wc.FP32, 12), (wc.FP32, 8), (wc.FP16, 12)])
 def test_batch_five_sources_two_groups(inner, recon):
-    # five systems on one lattice: the multi-system stencil takes them four at a
-    # time, so the second group has one live slot; the sources differ in size
-    # so the systems converge at different iterations and drop out one by one
+    # five systems on one lattice whose sources differ in size, so that the
+    # systems converge at different iterations and drop out of the batched
+    # launches one by one
     dims = (8, 8, 8, 16)
     kappa, csw = 0.13, 1.0
     say("batch of 5", inner, recon)
@@ -137,8 +136,7 @@ def test_multi_mixed_kappa_and_shared_lattice():
     b = [synth.gaussian_source(dims_a, 2031), synth.gaussian_source(dims_b, 2032), synth.gaussian_source(dims_a, 2033)]
     xs, infos = wc.solve_multi([la, lb, la], [dev(v) for v in b], [0.12, 0.13, 0.12], [1.0, 1.0, 1.0], 1e-11)
     for k, (U, dims, kap) in enumerate([(Ua, dims_a, 0.12), (Ub, dims_b, 0.13), (Ua, dims_a, 0.12)]):
-        r, bn = oracle.residual(U, kap, 1.0, b[k], host(xs[k]))
-        assert r / bn < 1e-11, k
+        check_true_residual(U, kap, 1.0, b[k], host(xs[k]), infos[k], 1e-11)
 
 
 def test_multi_uneven_full_size_residual():
@@ -170,6 +168,7 @@ def test_multi_uneven_full_size_residual():
     torch.cuda.empty_cache()
 
 
+@pytest.mark.timeout(600)
 def test_batch_full_size_point_sources_residual():
     # the 12 point sources on the 32^3 x 64 lattice, kappa 0.135: oracle true residual
     dims = (32, 32, 32, 64)
@@ -181,8 +180,51 @@ def test_batch_full_size_point_sources_residual():
     bs = point_sources(dims)
     xs, infos = lat.solve_batch([dev(b) for b in bs], kappa, csw, 1e-10)
     for k, info in enumerate(infos):
-        assert info["true_rel_residual"] < 1e-10, (k, info)
-    for k in (0, 7):
-        r, bn = oracle.residual(U, kappa, csw, bs[k], host(xs[k]))
-        say("oracle residual", k, r / bn)
-        assert r / bn < 1e-10
+        say("point source", k, info)
+        check_true_residual(U, kappa, csw, bs[k], host(xs[k]), info, 1e-10)
+
+
+def test_multi_lattices_on_other_streams_with_new_kappa():
+    # the second lattice's links are loaded on a stream of its own, and the batched
+    # call asks for a kappa whose clover term is not built yet: the rebuild and the
+    # earlier work on that stream must be ordered before the batch reads them
+    dims_a, dims_b = (8, 8, 8, 8), (8, 8, 8, 16)
+    Ua, Ub = synth.random_links(dims_a, 0.3, 1041), synth.random_links(dims_b, 0.3, 1042)
+    other = torch.cuda.Stream()
+    la = wc.Lattice(dims_a)
+    la.load_links(dev(Ua))
+    la.build_clover(0.12, 1.0)
+    with torch.cuda.stream(other):
+        lb = wc.Lattice(dims_b)
+        lb.load_links(dev(Ub))
+        lb.build_clover(0.12, 1.0)
+    b = [synth.gaussian_source(dims_a, 2041), synth.gaussian_source(dims_b, 2042)]
+    bd = [dev(v) for v in b]
+    torch.cuda.synchronize()
+    xs, infos = wc.solve_multi([la, lb], bd, [0.13, 0.135], [1.0, 1.0], 1e-11)
+    for k, (U, kap) in enumerate([(Ua, 0.13), (Ub, 0.135)]):
+        check_true_residual(U, kap, 1.0, b[k], host(xs[k]), infos[k], 1e-11)
+    la.close()
+    lb.close()
+
+
+def test_multi_after_destroying_and_recreating_a_lattice():
+    # a cached batch names its lattices by serial number: a lattice destroyed and
+    # created again (often at the same address) with other links must not reuse
+    # the graphs recorded with the old one's buffers
+    dims = (8, 8, 8, 8)
+    kappa, csw = 0.13, 1.0
+    la = wc.Lattice(dims)
+    Ua = synth.random_links(dims, 0.3, 1051)
+    la.load_links(dev(Ua))
+    bs = [synth.gaussian_source(dims, 2051), synth.gaussian_source(dims, 2052)]
+    for round_ in range(3):
+        Ub = synth.random_links(dims, 0.3, 1060 + round_)
+        lb = wc.Lattice(dims)
+        lb.load_links(dev(Ub))
+        xs, infos = wc.solve_multi([la, lb], [dev(v) for v in bs], [kappa] * 2, [csw] * 2, 1e-11)
+        say("round", round_, [i["true_rel_residual"] for i in infos])
+        check_true_residual(Ua, kappa, csw, bs[0], host(xs[0]), infos[0], 1e-11)
+        check_true_residual(Ub, kappa, csw, bs[1], host(xs[1]), infos[1], 1e-11)
+        lb.close()
+    la.close()

@@ -38,9 +38,10 @@ def test_not_ready_and_bad_enums():
     with pytest.raises(wc.WCError) as e:
         lat.apply_D(b, 7)
     assert e.value.code == -1
-    with pytest.raises(wc.WCError) as e:
-        lat.build_clover(0.2, 1.0)      # 6 kappa csw >= 1: F not guaranteed positive
-    assert e.value.code == -1
+    for bad in ((-0.1, 1.0), (0.12, -1.0), (float("nan"), 1.0), (0.12, float("inf"))):
+        with pytest.raises(wc.WCError) as e:
+            lat.build_clover(*bad)      # kappa and c_SW must be finite and >= 0
+        assert e.value.code == -1
     with pytest.raises(wc.WCError) as e:
         lat.solve(b, 0.12, 1.0, 0.0)
     assert e.value.code == -1
@@ -81,3 +82,25 @@ def test_past_critical_kappa_terminates():
     b = dev(synth.gaussian_source(dims, 7))
     x, info = lat.solve(b, 0.125, 0.0, 1e-10, inner_maxit=200, outer_maxit=5, raise_on_error=False)
     assert info["rc"] in (0, -5, -6)
+
+
+def test_nonfinite_links_rejected():
+    # a NaN entry must not slip through the load-time check (a maximum over the
+    # entries drops NaN): the load is refused and the lattice has no links
+    dims = (4, 4, 4, 4)
+    lat = wc.Lattice(dims)
+    U = synth.random_links(dims, 0.3, 5)
+    lat.load_links(dev(U))
+    U[2, 1, 0, 3, 2, 1, 1] = np.nan
+    with pytest.raises(wc.WCError) as e:
+        lat.load_links(dev(U))
+    assert e.value.code == -1 and "non-finite" in str(e.value)
+    b = dev(synth.gaussian_source(dims, 6))
+    with pytest.raises(wc.WCError) as e:
+        lat.solve(b, 0.12, 1.0, 1e-10)
+    assert e.value.code == -4
+    U[2, 1, 0, 3, 2, 1, 1] = np.inf
+    with pytest.raises(wc.WCError) as e:
+        lat.load_links(dev(U))
+    assert e.value.code == -1
+    lat.close()

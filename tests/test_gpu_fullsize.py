@@ -1,7 +1,11 @@
 """Parity at the full benchmark sizes: the operator on sampled output sites
-against the oracle's site-by-site D, and complete solves checked through the
-oracle's FP64 true residual on the whole lattice (a property that holds at
-any size; the oracle cannot solve these lattices in test time)."""
+against the oracle's site-by-site D, MULT, D-hat_ee and clover blocks (relative
+L2 error and the largest per-site error printed), and complete solves checked
+through the oracle's FP64 true residual on the whole lattice, which must also
+agree with the residual the library reports.  One 32^3x64 solution is compared
+with the oracle's own solve of the same system, and pure-gauge systems with
+the momentum-space closed form."""
+import os
 import sys
 
 import numpy as np
@@ -12,17 +16,15 @@ torch = pytest.importorskip("torch")
 import oracle
 import synth
 
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from gpu_checks import check_true_residual, say, site_errors  # noqa: E402
+
 pytestmark = pytest.mark.gpu
 
 if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
 import paper_1709_08785_amd as wc  # noqa: E402
-
-
-def say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
 
 
 @pytest.fixture(scope="module")
@@ -46,8 +48,7 @@ def test_apply_D_sampled_sites_32x32x32x64(c2, prec, tol):
     V = int(np.prod(dims))
     sites = np.concatenate([g.integers(0, V, 4000), [0, 1, V - 1, V - 2, dims[0] - 1]])
     ref = oracle.apply_D_sites(U, 0.135, 1.0, psi, sites)
-    err = np.linalg.norm(out[sites] - ref) / np.linalg.norm(ref)
-    say("rel err", err)
+    err, _ = site_errors(out[sites], ref, "apply_D")
     assert err < tol
 
 
@@ -82,8 +83,7 @@ def test_dhat_ee_sampled_even_sites_32x32x32x64(c2, prec, tol):
     cand = np.concatenate([g.integers(0, V, 6000), [0, 1, 2, V // 2, V - 2, V - 1, dims[0] - 2, dims[0] - 1]])
     sites = np.unique(cand[even[cand]])
     ref = oracle.dhat_ee_sites(U, kappa, csw, psi, sites)
-    err = np.linalg.norm(out[sites] - ref) / np.linalg.norm(ref)
-    say(len(sites), "even sites, rel err", err)
+    err, _ = site_errors(out[sites], ref, "D-hat_ee even")
     assert err < tol
 
 
@@ -106,8 +106,7 @@ def test_clover_and_inverse_sampled_sites_32x32x32x64(c2, prec, tol):
             out = lat.unpack(eo_out, prec).cpu().numpy().reshape(-1, 4, 3)
             sites = np.unique(cand[par[cand] == p])
             ref = oracle.clover_sites(U, kappa, csw, psi, sites, bool(inverse))
-            err = np.linalg.norm(out[sites] - ref) / np.linalg.norm(ref)
-            say("clover", prec, "inverse", inverse, "parity", p, "rel err", err)
+            err, _ = site_errors(out[sites], ref, "clover prec %d inverse %d parity %d" % (prec, inverse, p))
             assert err < tol, (inverse, p)
 
 
@@ -129,8 +128,7 @@ def test_mult_sampled_sites_both_parities_32x32x32x64(c2, prec, tol):
         out = lat.unpack(eo_out, prec).cpu().numpy().reshape(-1, 4, 3)
         sites = np.unique(cand[par[cand] == p])
         ref = oracle.htilde_sites(U, kappa, csw, psi, sites)
-        err = np.linalg.norm(out[sites] - ref) / np.linalg.norm(ref)
-        say(len(sites), "sites, rel err", err)
+        err, _ = site_errors(out[sites], ref, "MULT")
         assert err < tol, p
 
 
@@ -140,10 +138,8 @@ def test_solve_32x32x32x64_oracle_residual(c2, inner):
     say("solve 32^3x64", inner)
     b = synth.gaussian_source(dims, 2002)
     x, info = lat.solve(torch.from_numpy(b).cuda(), 0.135, 1.0, 1e-10, inner_prec=inner)
-    r, bn = oracle.residual(U, 0.135, 1.0, b, x.cpu().numpy())
-    say(info, "oracle", r / bn)
-    assert r / bn < 1e-10
-    assert abs(r / bn - info["true_rel_residual"]) < 1e-12
+    say(info)
+    check_true_residual(U, 0.135, 1.0, b, x.cpu().numpy(), info, 1e-10)
 
 
 @pytest.mark.parametrize("recon", [8, 18])
@@ -160,8 +156,7 @@ def test_apply_D_other_link_forms_sampled_sites_32x32x32x64(c2, recon):
     V = int(np.prod(dims))
     sites = np.concatenate([g.integers(0, V, 4000), [0, 1, V - 1, V - 2, dims[0] - 1]])
     ref = oracle.apply_D_sites(U, 0.135, 1.0, psi, sites)
-    err = np.linalg.norm(out[sites] - ref) / np.linalg.norm(ref)
-    say("rel err", err)
+    err, _ = site_errors(out[sites], ref, "apply_D recon %d" % recon)
     assert err < 1e-5
 
 
@@ -175,9 +170,30 @@ def test_solve_32x32x32x64_variants_oracle_residual(c2, inner, recon, outer):
         x, info = lat.solve(torch.from_numpy(b).cuda(), 0.135, 1.0, 1e-10, inner_prec=inner, outer=outer)
     finally:
         lat.set_link_recon(12)
-    r, bn = oracle.residual(U, 0.135, 1.0, b, x.cpu().numpy())
-    say(info, "oracle", r / bn)
-    assert r / bn < 1e-10
+    say(info)
+    check_true_residual(U, 0.135, 1.0, b, x.cpu().numpy(), info, 1e-10)
+
+
+@pytest.mark.timeout(900)
+def test_solve_32x32x32x64_solution_matches_oracle_solve(c2):
+    # the headline system itself: the GPU's nested solve (to 1e-12) against the
+    # oracle's plain FP64 BiCGStab on the full D (to 1e-13), solution to 1e-10
+    dims, lat, U, Ud = c2
+    kappa, csw = 0.135, 1.0
+    say("solve 32^3x64 against the oracle's solve (%d host threads)" % oracle.num_threads())
+    b = synth.gaussian_source(dims, 2002)
+    x, info = lat.solve(torch.from_numpy(b).cuda(), kappa, csw, 1e-12)
+    say(info)
+    xh = x.cpu().numpy()
+    del x
+    check_true_residual(U, kappa, csw, b, xh, info, 1e-12)
+    F = oracle.clover_field(U, dims, kappa, csw)
+    x_ref, its, rr = oracle.solve(U, F, kappa, b, tol=1e-13)
+    del F
+    err = float(np.linalg.norm(xh - x_ref) / np.linalg.norm(x_ref))
+    say("oracle: %d iterations, true rel residual %.3e; solution rel err %.3e" % (its, rr, err))
+    site_errors(xh.reshape(-1, 4, 3), x_ref.reshape(-1, 4, 3), "solution")
+    assert err < 1e-10
 
 
 @pytest.fixture(scope="module")
@@ -208,12 +224,11 @@ def test_apply_D_sampled_sites_48x48x48x96(c3, prec, tol):
     sites = np.concatenate([g.integers(0, V, 4000), [0, 1, V // 2 - 1, V // 2, V - 2, V - 1, dims[0] - 1,
                                                      V - dims[0] * dims[1] * dims[2]]])
     ref = oracle.apply_D_sites(U, kappa, csw, psi, sites)
-    err = np.linalg.norm(out[sites] - ref) / np.linalg.norm(ref)
-    say("rel err", err)
+    err, _ = site_errors(out[sites], ref, "apply_D 48^3x96")
     assert err < tol
 
 
-@pytest.mark.parametrize("prec,tol", [(wc.FP32, 1e-5), (wc.FP16, 2e-3)])
+@pytest.mark.parametrize("prec,tol", [(wc.FP64, 1e-13), (wc.FP32, 1e-5), (wc.FP16, 2e-3)])
 def test_dhat_ee_sampled_even_sites_48x48x48x96(c3, prec, tol):
     dims, lat, U, b = c3
     kappa, csw = 0.1355, 1.0
@@ -230,19 +245,44 @@ def test_dhat_ee_sampled_even_sites_48x48x48x96(c3, prec, tol):
     cand = np.concatenate([g.integers(0, V, 4000), [0, 2, V // 2, V - 2, V - 1, dims[0] - 2, dims[0] - 1]])
     sites = np.unique(cand[even[cand]])
     ref = oracle.dhat_ee_sites(U, kappa, csw, psi, sites)
-    err = np.linalg.norm(out[sites] - ref) / np.linalg.norm(ref)
-    say(len(sites), "even sites, rel err", err)
+    err, _ = site_errors(out[sites], ref, "D-hat_ee even")
     assert err < tol
 
 
-def test_solve_48x48x48x96_fp16_oracle_residual(c3):
+@pytest.mark.parametrize("prec,tol", [(wc.FP64, 1e-13), (wc.FP32, 1e-5), (wc.FP16, 2e-3)])
+def test_mult_sampled_sites_both_parities_48x48x48x96(c3, prec, tol):
+    # MULT = F^-1 H into each parity on the precision-comparison lattice
     dims, lat, U, b = c3
     kappa, csw = 0.1355, 1.0
-    say("solve 48^3x96 fp16")
-    x, info = lat.solve(torch.from_numpy(b).cuda(), kappa, csw, 1e-10, inner_prec=wc.FP16)
-    r, bn = oracle.residual(U, kappa, csw, b, x.cpu().numpy())
-    say(info, "oracle", r / bn)
-    assert r / bn < 1e-10
+    lat.build_clover(kappa, csw)
+    psi = synth.gaussian_source(dims, 2015)
+    eo_in = lat.pack(torch.from_numpy(psi).cuda(), prec)
+    par = oracle.parity(dims).reshape(-1)
+    V = int(np.prod(dims))
+    g = synth.rng(16)
+    cand = np.concatenate([g.integers(0, V, 4000), [0, 1, 2, V // 2, V - 2, V - 1, dims[0] - 2, dims[0] - 1]])
+    for p in (0, 1):
+        say("MULT sampled 48^3x96", prec, "into parity", p)
+        eo_out = lat.new_eo(prec, 2)
+        lat.apply_mult(lat.parity_view(eo_out, p, prec), lat.parity_view(eo_in, 1 - p, prec), p, prec)
+        out = lat.unpack(eo_out, prec).cpu().numpy().reshape(-1, 4, 3)
+        del eo_out
+        sites = np.unique(cand[par[cand] == p])
+        ref = oracle.htilde_sites(U, kappa, csw, psi, sites)
+        err, _ = site_errors(out[sites], ref, "MULT 48^3x96")
+        assert err < tol, p
+
+
+@pytest.mark.parametrize("inner", [wc.FP16, wc.FP32, wc.FP64])
+def test_solve_48x48x48x96_three_forms_oracle_residual(c3, inner):
+    # the three precision forms of the 48^3x96 comparison (FP16-storage and FP32
+    # inner loops under the FP64 outer, and the all-FP64 BiCGStab), two-column links
+    dims, lat, U, b = c3
+    kappa, csw = 0.1355, 1.0
+    say("solve 48^3x96 inner", inner)
+    x, info = lat.solve(torch.from_numpy(b).cuda(), kappa, csw, 1e-10, inner_prec=inner)
+    say(info)
+    check_true_residual(U, kappa, csw, b, x.cpu().numpy(), info, 1e-10)
 
 
 def test_solve_48x48x48x96_recon8_converges_like_recon12(c3):
@@ -256,9 +296,8 @@ def test_solve_48x48x48x96_recon8_converges_like_recon12(c3):
         x, info = lat.solve(torch.from_numpy(b).cuda(), kappa, csw, 1e-10, inner_prec=wc.FP32)
     finally:
         lat.set_link_recon(12)
-    r, bn = oracle.residual(U, kappa, csw, b, x.cpu().numpy())
-    say(info, "oracle", r / bn)
-    assert r / bn < 1e-10
+    say(info)
+    check_true_residual(U, kappa, csw, b, x.cpu().numpy(), info, 1e-10)
     assert info["outer_iters"] == 1 and info["inner_iters_total"] < 230
 
 
@@ -284,3 +323,31 @@ def test_solve_pure_gauge_fft_32x32x32x64():
     say("rel err", err)
     assert err < 1e-10
     lat.close()
+
+
+def test_solve_pure_gauge_fft_48x48x48x96():
+    # the closed form at the precision-comparison size (10.6M sites): for
+    # U_mu(n) = Om(n) Om(n+mu)^dagger, x = Om FFT-solve(Om^dagger b)
+    dims = (48, 48, 48, 96)
+    kappa = 0.12
+    lx, ly, lz, lt = dims
+    say("pure gauge FFT solve 48^3x96")
+    om = synth.haar_su3((lt, lz, ly, lx), synth.rng(88))
+    U = synth.pure_gauge_links(om, dims)
+    lat = wc.Lattice(dims)
+    lat.load_links(torch.from_numpy(U).cuda())
+    del U
+    b = synth.gaussian_source(dims, 89)
+    x, info = lat.solve(torch.from_numpy(b).cuda(), kappa, 1.0, 1e-12)
+    say(info)
+    xh = x.cpu().numpy()
+    del x
+    lat.close()
+    torch.cuda.empty_cache()
+    omd_b = np.einsum("...ji,...aj->...ai", np.conj(om), b)
+    del b
+    x_ref = np.einsum("...ij,...aj->...ai", om, oracle.free_solve_fft(omd_b, kappa))
+    del omd_b, om
+    err = float(np.linalg.norm(xh - x_ref) / np.linalg.norm(x_ref))
+    say("rel err", err)
+    assert err < 1e-10

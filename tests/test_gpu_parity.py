@@ -9,6 +9,7 @@ the ~100 terms of one output is ~1e-6); FP16 storage to 2e-3 relative (half
 precision keeps 11 significant bits, ~5e-4 per stored value).  Solutions of
 the FP64-refined solves agree with the oracle's to 1e-10.
 """
+import os
 import sys
 
 import numpy as np
@@ -18,6 +19,9 @@ torch = pytest.importorskip("torch")
 
 import oracle
 import synth
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from gpu_checks import check_true_residual  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -214,8 +218,7 @@ def test_solve_near_critical_kappas(kappa):
     b = synth.gaussian_source(dims, 2002)
     x, info = lat.solve(dev(b), kappa, 1.0, 1e-10)
     say(info)
-    r, bn = oracle.residual(U, kappa, 1.0, b, host(x))
-    assert r / bn < 1e-10
+    check_true_residual(U, kappa, 1.0, b, host(x), info, 1e-10)
 
 
 def test_solve_pure_gauge_fft_closed_form():
