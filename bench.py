@@ -153,6 +153,22 @@ def small_config():
             "solution_rel_diff": float(np.linalg.norm(xh - x_ref) / np.linalg.norm(x_ref))}
 
 
+def collect(lat, res, suffix, fields=1):
+    """Event-timed kernel statistics of lat into res (keys kernel + suffix); resets them."""
+    st = lat.kernel_stats()
+    for kname, v in st.items():
+        if v["launches"]:
+            avg_us = v["ms"] / v["launches"] * 1e3
+            g = table1_gflops(kname, lat.volume // 2, avg_us)
+            res[kname + suffix] = {
+                "launches": v["launches"], "avg_us": round(avg_us, 2),
+                "algorithmic_GBs": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1),
+                "frac_hbm": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "GFLOPS_table1": None if g is None else round(g * fields, 1),
+                "bytes_per_launch": v["bytes"] / v["launches"]}
+    lat.reset_kernel_stats()
+
+
 def dslash_mode(args, dims):
     """Operator micro-benchmark: MULT and D-hat_ee in each precision, K launches each,
     timed with HIP events on the library stream; plus a device copy of known size
@@ -175,6 +191,8 @@ def dslash_mode(args, dims):
     lat.build_clover(args.kappa, args.csw)
     psid = torch.from_numpy(psi).to(dev)
     res = {}
+    default_chunk = -1  # the lattice's own (tuned, else the default) chunk
+    sweep = [int(v) for v in args.sweep_chunks.split(",")] if args.sweep_chunks else []
     for name, prec, recon in [("fp32", wc.FP32, 12), ("fp16", wc.FP16, 12), ("fp64", wc.FP64, 12),
                               ("fp32", wc.FP32, 8), ("fp32", wc.FP32, 18)]:
         lat.set_link_recon(recon)
@@ -182,29 +200,73 @@ def dslash_mode(args, dims):
         out = lat.new_eo(prec, 1)
         e_in = lat.parity_view(eo, 0, prec)
         o_in = lat.parity_view(eo, 1, prec)
-        for w in range(3):
-            lat.apply_mult(out, o_in, 0, prec)
-            lat.apply_Dee_oo(out, e_in, prec)
-        torch.cuda.synchronize()
-        lat.reset_kernel_stats()
-        lat.set_timing(True)
-        for k in range(args.steps):
-            lat.apply_mult(out, o_in, 0, prec)
-        for k in range(args.steps):
-            lat.apply_Dee_oo(out, e_in, prec)
-        lat.set_timing(False)
-        st = lat.kernel_stats()
-        for kname, v in st.items():
-            if v["launches"]:
-                avg_us = v["ms"] / v["launches"] * 1e3
-                res[kname + ("" if recon == 12 else "_recon%d" % recon)] = {
-                              "launches": v["launches"], "avg_us": round(avg_us, 2),
-                              "algorithmic_GBs": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1),
-                              "frac_hbm": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                              "GFLOPS_table1": table1_gflops(kname, lat.volume // 2, avg_us),
-                              "bytes_per_launch": v["bytes"] / v["launches"]}
-        lat.reset_kernel_stats()
+        for chunk in [default_chunk] + [c for c in sweep if c != default_chunk]:
+            lat.set_xcd_chunk(chunk)
+            for w in range(3):
+                lat.apply_mult(out, o_in, 0, prec)
+                lat.apply_Dee_oo(out, e_in, prec)
+            torch.cuda.synchronize()
+            lat.reset_kernel_stats()
+            lat.set_timing(True)
+            for k in range(args.steps):
+                lat.apply_mult(out, o_in, 0, prec)
+            for k in range(args.steps):
+                lat.apply_Dee_oo(out, e_in, prec)
+            lat.set_timing(False)
+            collect(lat, res, ("" if recon == 12 else "_recon%d" % recon) +
+                    ("" if chunk == default_chunk else "_chunk%d" % chunk))
+        lat.set_xcd_chunk(default_chunk)
         del eo, out
+    # the multi-system stencil: the 12 fields of the point-source batch on one
+    # lattice, with 4 or 2 fields per thread and with one field per thread (the
+    # fields' workgroups interleaved); algorithmic bytes per launch count the
+    # links and clover once and every field's spinors (24S + 8L + C per site
+    # for the MULT)
+    nb = 12
+    lat.set_link_recon(12)
+    chunks = [default_chunk] + [c for c in sweep if c != default_chunk]
+    for name, prec in (("fp32", wc.FP32), ("fp16", wc.FP16)):
+        ins = [lat.pack(psid * (1.0 + 0.1 * k), prec) for k in range(nb)]
+        outs = [lat.new_eo(prec, 1) for k in range(nb)]
+        o_in = [lat.parity_view(e, 1, prec) for e in ins]
+        e_in = [lat.parity_view(e, 0, prec) for e in ins]
+        for chunk in chunks:
+            lat.set_xcd_chunk(chunk)
+            tag = "" if chunk == default_chunk else "_chunk%d" % chunk
+            for gsz in (4, 2, 0):
+                lat.set_multi_rhs(gsz)
+                for w in range(2):
+                    lat.apply_mult_batch(outs, o_in, 0, prec)
+                    lat.apply_Dee_oo_batch(outs, e_in, prec)
+                torch.cuda.synchronize()
+                lat.reset_kernel_stats()
+                lat.set_timing(True)
+                for k in range(args.steps):
+                    lat.apply_mult_batch(outs, o_in, 0, prec)
+                for k in range(args.steps):
+                    lat.apply_Dee_oo_batch(outs, e_in, prec)
+                lat.set_timing(False)
+                collect(lat, res, "_x%d_g%d%s" % (nb, gsz, tag), fields=nb)
+        if sweep:
+            # the 12 fields as sub-batches of 4 and 6 (the operator read once per
+            # sub-batch), two and four fields per thread
+            lat.set_xcd_chunk(default_chunk)
+            for sub in (4, 6):
+                for gsz in (4, 2):
+                    lat.set_multi_rhs(gsz)
+                    for w in range(2):
+                        lat.apply_mult_batch(outs[:sub], o_in[:sub], 0, prec)
+                    torch.cuda.synchronize()
+                    lat.reset_kernel_stats()
+                    lat.set_timing(True)
+                    for k in range(args.steps):
+                        for j in range(0, nb, sub):
+                            lat.apply_mult_batch(outs[j:j + sub], o_in[j:j + sub], 0, prec)
+                    lat.set_timing(False)
+                    collect(lat, res, "_x%d_in%d_g%d" % (nb, sub, gsz), fields=sub)
+        del ins, outs, o_in, e_in
+    lat.set_xcd_chunk(default_chunk)
+    lat.set_multi_rhs(-1)
     # calibration copy: 1 GiB read + 1 GiB written
     n = 1 << 28
     a = torch.ones(n, dtype=torch.float32, device=dev)
@@ -274,8 +336,17 @@ def batch_mode(args):
     lat.load_links(torch.from_numpy(synth.random_links(dims, 0.3, 1004)).to(dev))
     lat.build_clover(kappa, csw)
     bs = [torch.from_numpy(synth.point_source(dims, al, a)).to(dev) for al in range(4) for a in range(3)]
-    lat.solve_batch(bs, kappa, csw, args.tol)  # warm-up (allocation, graph recording)
-    (xs, infos), t_batch = timed(lambda: lat.solve_batch(bs, kappa, csw, args.tol))
+    # the batch with the multi-system stencil at 2 fields per thread, and with
+    # one field per thread (interleaved workgroups), before the default 4
+    by_g = {}
+    for gsz in (0, 4, 2):
+        lat.set_multi_rhs(gsz)
+        lat.solve_batch(bs, kappa, csw, args.tol)  # warm-up (allocation, graph recording)
+        (xs, infos), t_batch = timed(lambda: lat.solve_batch(bs, kappa, csw, args.tol))
+        by_g[gsz] = {"batched_s": round(t_batch, 4), "max_true_rel_residual": max(i["true_rel_residual"] for i in infos),
+                     "inner_iters": [i["inner_iters_total"] for i in infos]}
+        log("point sources, %d fields per thread: %s" % (gsz, json.dumps(by_g[gsz])))
+    lat.set_multi_rhs(-1)  # the precision's default (2 in FP32): the last timing above
     lat.solve(bs[0], kappa, csw, args.tol)
     singles, t_seq = timed(lambda: [lat.solve(b, kappa, csw, args.tol) for b in bs])
     # per-kernel accounting of one batched solve (eager, HIP events)
@@ -289,6 +360,7 @@ def batch_mode(args):
     out["point_sources_32x32x32x64"] = {
         "systems": len(bs), "batched_s": round(t_batch, 4), "sequential_s": round(t_seq, 4),
         "speedup": round(t_seq / t_batch, 3), "s_per_system_batched": round(t_batch / len(bs), 4),
+        "fields_per_thread": lat.multi_rhs(wc.FP32), "by_fields_per_thread": {str(k): v for k, v in by_g.items()},
         "max_true_rel_residual": max(i["true_rel_residual"] for i in infos),
         "inner_iters": [i["inner_iters_total"] for i in infos],
         "algorithmic_GBs_batched_kernels": round(tot_bytes / (tot_ms * 1e-3) / 1e9, 1),
@@ -584,6 +656,9 @@ def main():
     ap.add_argument("--no-fp64-arm", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=1002)
+    ap.add_argument("--sweep-chunks", type=str, default="",
+                    help="dslash mode: also time the stencils at these XCD chunks (tiles, comma-separated; "
+                         "0 = one slab per XCD) and the batched ones at sub-batch sizes")
     args = ap.parse_args()
 
     if args.gpus != 1:

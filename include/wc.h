@@ -142,9 +142,13 @@ void wc_solve_params_default(wc_solve_params *p);
    (pinned, else tuned), or 0 when it is not yet tuned.
    wc_tune_block_size: times the inner loop's stencil pair (F^-1 H into the
    odd parity, then the D-hat half with its fused dot; Sec. II-B eq. 8) on
-   zero vectors at 64, 128 and 256 threads and keeps the fastest, a smaller
-   size only if at least 3% faster.  us_per_pair[3] (may be NULL) receives
-   microseconds per pair for 64, 128, 256; *threads (may be NULL) the choice.
+   zero vectors at 64, 128 and 256 threads and at XCD chunks of 8, 16, 32 and
+   64 tiles (wc_set_xcd_chunk; only the pinned one when pinned) and keeps the
+   fastest shape; 256 threads at chunk 32 are displaced only by a shape at
+   least 3% faster.  us_per_pair[3] (may be NULL) receives microseconds per
+   pair for 64, 128, 256 at the chosen chunk; *threads (may be NULL) the
+   chosen block size.  With a tuning cache (wc_set_tune_cache) holding this
+   case, the stored shape is taken without timing.
    Needs links and clover (WC_ENOTREADY).  Allocates three vectors of the
    precision for the duration of the call and synchronises the stream. */
 int wc_set_block_size(wc_lattice *lat, int threads);
@@ -158,13 +162,36 @@ int wc_tune_block_size(wc_lattice *lat, int prec, double us_per_pair[3], int *th
    launch in which each thread takes one site for systems_per_thread systems:
    it computes the neighbour indices and rebuilds each link once, loads each
    clover block once, and applies them to every system's spinors.
-   wc_set_multi_rhs: systems_per_thread = 2 or 4 (default 4), or 0 for one
-   system per thread (each system's sites in workgroups of their own, the
-   operator shared through the cache).  WC_EINVAL for other values.  Results
-   agree with single solves to rounding.  wc_multi_rhs: the setting, or -1 for
-   a null lattice. */
+   wc_set_multi_rhs: systems_per_thread = 2 or 4, 0 for one system per thread
+   (each system's sites in workgroups of their own, the operator shared through
+   the cache), or -1 (default) for 2 in FP32 and 4 in FP16, the faster setting
+   of each precision on the 12-source batch.  WC_EINVAL for other values.
+   Results agree with single solves to rounding.  wc_multi_rhs: systems per
+   thread a batch in precision prec uses now (0 for FP64, which has no
+   multi-system form), or -1 for a null lattice or bad precision. */
 int wc_set_multi_rhs(wc_lattice *lat, int systems_per_thread);
-int wc_multi_rhs(const wc_lattice *lat);
+int wc_multi_rhs(const wc_lattice *lat, int prec);
+
+/* Order in which the stencils' workgroups visit the lattice.  Workgroups are
+   handed to the device's 8 XCDs (each with its own L2) round-robin; the
+   library remaps them so that each XCD takes chunks of `tiles` consecutive
+   64-site tiles, the XCDs sweeping the lattice side by side (neighbours in y
+   and z then fall in the XCD's own chunk).  tiles = 0 gives each XCD one
+   contiguous slab instead.  Unless pinned, the chunk is tuned with the block
+   size (wc_tune_block_size); before tuning it is 32.  Results do not depend
+   on it.  wc_set_xcd_chunk: tiles in [0, 2^20] pins it for every precision,
+   -1 returns to tuning; WC_EINVAL otherwise.  wc_xcd_chunk: the chunk a
+   launch in precision prec uses now (-2 for a null lattice or bad prec). */
+int wc_set_xcd_chunk(wc_lattice *lat, int tiles);
+int wc_xcd_chunk(const wc_lattice *lat, int prec);
+
+/* Process-wide file in which the launch-shape tuner keeps its results, one
+   line per device (architecture and compute units), lattice extents,
+   precision and FP32 link form; a later tuning of the same case, in this
+   process or another, takes the stored shape instead of timing.  path NULL or
+   "" (the default) keeps no file.  A file that cannot be read or written only
+   costs a new timing.  The path is copied. */
+int wc_set_tune_cache(const char *path);
 
 /* Longest time (seconds, > 0 finite, or 0 for "no waiting allowed") a
    workgroup of the one-launch inner loop (wc_solve_params.persistent) waits

@@ -107,9 +107,12 @@ def load_library():
         "wc_block_size": (I, [P, I]),
         "wc_tune_block_size": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(I)]),
         "wc_set_multi_rhs": (I, [P, I]),
+        "wc_set_xcd_chunk": (I, [P, I]),
+        "wc_xcd_chunk": (I, [P, I]),
+        "wc_set_tune_cache": (I, [ctypes.c_char_p]),
         "wc_apply_mult_batch": (I, [P, I, ctypes.POINTER(P), ctypes.POINTER(P), I, I]),
         "wc_apply_Dee_oo_batch": (I, [P, I, ctypes.POINTER(P), ctypes.POINTER(P), I]),
-        "wc_multi_rhs": (I, [P]),
+        "wc_multi_rhs": (I, [P, I]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -229,15 +232,25 @@ class Lattice:
         us = (ctypes.c_double * 3)()
         th = ctypes.c_int()
         _check(self.lib.wc_tune_block_size(self.h, _prec(prec), us, ctypes.byref(th)))
-        return {"us_per_pair": {64: us[0], 128: us[1], 256: us[2]}, "threads": th.value}
+        return {"us_per_pair": {64: us[0], 128: us[1], 256: us[2]}, "threads": th.value,
+                "chunk": self.xcd_chunk(prec)}
 
     def set_multi_rhs(self, systems_per_thread: int):
         """Systems per thread of the batched solves' multi-system stencil (2 or 4), 0 for one."""
         _check(self.lib.wc_set_multi_rhs(self.h, int(systems_per_thread)))
 
-    @property
-    def multi_rhs(self) -> int:
-        return int(self.lib.wc_multi_rhs(self.h))
+    def set_xcd_chunk(self, tiles: int):
+        """64-site tiles per XCD chunk of the stencils' workgroup order (0: one slab per XCD,
+        -1: tuned with the block size)."""
+        _check(self.lib.wc_set_xcd_chunk(self.h, int(tiles)))
+
+    def xcd_chunk(self, prec=FP32) -> int:
+        """The XCD chunk a launch in this precision uses now."""
+        return int(self.lib.wc_xcd_chunk(self.h, _prec(prec)))
+
+    def multi_rhs(self, prec=FP32) -> int:
+        """Systems per thread of a batched solve's stencil in this precision."""
+        return int(self.lib.wc_multi_rhs(self.h, _prec(prec)))
 
     @property
     def link_recon(self) -> int:
@@ -390,6 +403,12 @@ class Lattice:
                                             ctypes.byref(by)))
             out[name.value.decode()] = {"launches": n.value, "ms": ms.value, "bytes": by.value}
         return out
+
+
+def set_tune_cache(path):
+    """File in which the launch-shape tuner keeps its results across processes (None: none)."""
+    load_library()
+    _check(_lib.wc_set_tune_cache(None if path is None else os.fsencode(path)))
 
 
 def set_barrier_timeout(seconds: float):

@@ -569,6 +569,7 @@ int launch_vec_batch(hipStream_t s, wc_lattice *tlat, int op, int prec, const Ve
     VecBatch B;
     B.h.S = n;
     B.h.interleave = 0;
+    B.h.chunk = 0;
     B.h.off[0] = 0;
     const int xprec = prec == P64 ? P64 : P32;
     const int bs = launch_bs(calls[0].bs);

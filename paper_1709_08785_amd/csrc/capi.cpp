@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <mutex>
 #include <atomic>
 #include <cmath>
 #include <cstring>
@@ -550,6 +552,7 @@ static void set_recon(wc_lattice *lat, int recon, bool automatic) {
     if (recon != lat->recon) {
         lat->recon = recon;
         lat->bs_tuned[P32] = 0;  // the FP32 stencil changed: tune again
+        lat->chunk_tuned[P32] = -1;
         lat->gen++;
     }
     lat->recon_auto = automatic;
@@ -720,13 +723,95 @@ static MultCall mult_call(int prec, int mode, int out_par, void *out, const void
     return c;
 }
 
+// ---------------------------------------------------------------------------
+// launch-shape tuner and its persistent cache
+// ---------------------------------------------------------------------------
+static std::mutex g_tune_mu;
+static std::string g_tune_cache;  // file of tuned shapes ("" = none)
+
+extern "C" int wc_set_tune_cache(const char *path) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune_cache = path ? path : "";
+    return WC_OK;
+}
+
+// the cache key of (device, lattice, precision, link form)
+static std::string tune_key(const wc_lattice *lat, int prec) {
+    int dev = 0;
+    hipDeviceProp_t p;
+    std::string arch = "unknown";
+    int cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess) {
+        arch = p.gcnArchName;
+        cus = p.multiProcessorCount;
+    }
+    for (auto &ch : arch)
+        if (ch == ' ') ch = '_';
+    char buf[256];
+    std::snprintf(buf, sizeof(buf), "%s %d %d %d %d %d %d %d", arch.c_str(), cus, lat->dims[0], lat->dims[1],
+                  lat->dims[2], lat->dims[3], prec, prec == P32 ? lat->recon : 12);
+    return buf;
+}
+
+// the last entry for key in the cache file: block size, chunk, microseconds
+// per pair at the block sizes 64, 128, 256
+static bool tune_lookup(const std::string &key, int *bs, int *chunk, double us[3]) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    if (g_tune_cache.empty()) return false;
+    std::FILE *f = std::fopen(g_tune_cache.c_str(), "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    const std::string head = "wc-tune-v1 " + key + " ";
+    while (std::fgets(line, sizeof(line), f)) {
+        if (std::strncmp(line, head.c_str(), head.size()) != 0) continue;
+        int b = 0, c = -1;
+        double u[3] = {0, 0, 0};
+        if (std::sscanf(line + head.size(), "%d %d %lf %lf %lf", &b, &c, &u[0], &u[1], &u[2]) == 5 &&
+            valid_block_size(b) && c >= 0) {
+            *bs = b;
+            *chunk = c;
+            for (int k = 0; k < 3; k++) us[k] = u[k];
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+static void tune_store(const std::string &key, int bs, int chunk, const double us[3]) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    if (g_tune_cache.empty()) return;
+    std::FILE *f = std::fopen(g_tune_cache.c_str(), "a");
+    if (!f) return;  // a cache that cannot be written only costs a later tuning
+    std::fprintf(f, "wc-tune-v1 %s %d %d %.3f %.3f %.3f\n", key.c_str(), bs, chunk, us[0], us[1], us[2]);
+    std::fclose(f);
+}
+
 // Time the inner loop's stencil pair (F_oo^-1 H_oe into the odd parity, then
-// the D-hat half with its fused dot) at each block size on zero vectors, and
-// keep the fastest; a smaller block must win by 3% to displace a larger one,
-// so that timing noise does not flip the choice on large lattices.
+// the D-hat half with its fused dot) on zero vectors at each block size and
+// XCD chunk, and keep the fastest.  The default shape (256 threads, chunk
+// kDefaultChunk) is displaced only by a shape at least 3% faster, so that
+// timing noise does not flip the choice on large lattices.  A pinned chunk
+// is the only one timed.  With a cache file set, a stored result for the same
+// device, lattice, precision and link form is taken instead of timing.
 int tune_block_size(wc_lattice *lat, int prec, double us[3], int *chosen) {
     if (!lat->have_links || !lat->have_clover)
         return wc_fail(WC_ENOTREADY, "block-size tuning needs links and clover");
+    const std::string key = tune_key(lat, prec);
+    {
+        int b = 0, c = -1;
+        double u[3];
+        if (tune_lookup(key, &b, &c, u)) {
+            lat->bs_tuned[prec] = b;
+            lat->chunk_tuned[prec] = c;
+            lat->gen++;
+            if (us)
+                for (int k = 0; k < 3; k++) us[k] = u[k];
+            if (chosen) *chosen = b;
+            return WC_OK;
+        }
+    }
     const size_t sb = spinor_bytes(prec, lat->Vh);
     char *buf = nullptr;
     const size_t bytes = 3 * sb + 256;
@@ -737,7 +822,10 @@ int tune_block_size(wc_lattice *lat, int prec, double us[3], int *chosen) {
     const long dcount = lat->dslash_count;
     lat->timing = false;
     const int cand[3] = {64, 128, 256};
-    double t[3] = {0, 0, 0};
+    std::vector<int> chunks;
+    if (lat->chunk_pin >= 0) chunks.push_back(lat->chunk_pin);
+    else chunks = {kDefaultChunk, 8, 16, 64};
+    std::vector<double> t(3 * chunks.size(), 0.0);
     auto pair = [&](int bs) -> int {
         MultCall c1 = mult_call(prec, M_HOPINV, 1, buf + sb, buf, nullptr, 0.0);
         c1.bs = bs;
@@ -770,10 +858,15 @@ int tune_block_size(wc_lattice *lat, int prec, double us[3], int *chosen) {
         }
         // about 2 ms of pairs per candidate, between 4 and 64
         double ms = 0;
+        lat->chunk_force = chunks[0];
         if ((rc = timed(256, 2, &ms))) break;
         const int reps = std::max(4, std::min(64, (int)(2.0 / std::max(ms, 1e-3))));
-        for (int c = 0; c < 3 && !rc; c++) rc = timed(cand[c], reps, &t[c]);
+        for (size_t h = 0; h < chunks.size() && !rc; h++) {
+            lat->chunk_force = chunks[h];
+            for (int c = 0; c < 3 && !rc; c++) rc = timed(cand[c], reps, &t[3 * h + c]);
+        }
     } while (false);
+    lat->chunk_force = -1;
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     (void)hipStreamSynchronize(lat->stream);
@@ -781,14 +874,20 @@ int tune_block_size(wc_lattice *lat, int prec, double us[3], int *chosen) {
     lat->timing = timing;
     lat->dslash_count = dcount;
     if (rc) return rc;
-    int best = 2;
-    for (int c = 1; c >= 0; c--)
-        if (t[c] < 0.97 * t[best]) best = c;
-    lat->bs_tuned[prec] = cand[best];
+    // start from 256 threads at the first chunk; another shape must win by 3%
+    size_t best = 2;
+    for (size_t k = 0; k < t.size(); k++)
+        if (t[k] < 0.97 * t[best]) best = k;
+    const size_t h = best / 3;
+    lat->bs_tuned[prec] = cand[best % 3];
+    lat->chunk_tuned[prec] = chunks[h];
     lat->gen++;  // captured graphs hold the old launch shape
+    double u[3];
+    for (int c = 0; c < 3; c++) u[c] = t[3 * h + c] * 1e3;
     if (us)
-        for (int c = 0; c < 3; c++) us[c] = t[c] * 1e3;
-    if (chosen) *chosen = cand[best];
+        for (int c = 0; c < 3; c++) us[c] = u[c];
+    if (chosen) *chosen = cand[best % 3];
+    if (lat->chunk_pin < 0) tune_store(key, cand[best % 3], chunks[h], u);
     return WC_OK;
 }
 
@@ -802,14 +901,30 @@ extern "C" int wc_set_block_size(wc_lattice *lat, int threads) {
 
 extern "C" int wc_set_multi_rhs(wc_lattice *lat, int systems_per_thread) {
     if (!lat) return wc_fail(WC_EINVAL, "null lattice");
-    if (systems_per_thread != 0 && systems_per_thread != 2 && systems_per_thread != 4)
-        return wc_fail(WC_EINVAL, "systems per thread must be 0, 2 or 4");
+    if (systems_per_thread != -1 && systems_per_thread != 0 && systems_per_thread != 2 && systems_per_thread != 4)
+        return wc_fail(WC_EINVAL, "systems per thread must be -1, 0, 2 or 4");
     if (systems_per_thread != lat->mrhs) lat->gen++;  // recorded graphs hold the old kernels
     lat->mrhs = systems_per_thread;
     return WC_OK;
 }
 
-extern "C" int wc_multi_rhs(const wc_lattice *lat) { return lat ? lat->mrhs : -1; }
+extern "C" int wc_multi_rhs(const wc_lattice *lat, int prec) {
+    if (!lat || prec < 0 || prec > 2) return -1;
+    return prec == P64 ? 0 : mrhs_for(lat, prec);
+}
+
+extern "C" int wc_set_xcd_chunk(wc_lattice *lat, int tiles) {
+    if (!lat) return wc_fail(WC_EINVAL, "null lattice");
+    if (tiles < -1 || tiles > (1 << 20)) return wc_fail(WC_EINVAL, "XCD chunk must be -1 or lie in [0, 2^20] tiles");
+    if (tiles != lat->chunk_pin) lat->gen++;  // recorded graphs hold the old launch arguments
+    lat->chunk_pin = tiles;
+    return WC_OK;
+}
+
+extern "C" int wc_xcd_chunk(const wc_lattice *lat, int prec) {
+    if (!lat || prec < 0 || prec > 2) return -2;
+    return lattice_chunk(lat, prec);
+}
 
 extern "C" int wc_block_size(const wc_lattice *lat, int prec) {
     if (!lat || prec < 0 || prec > 2) return 0;

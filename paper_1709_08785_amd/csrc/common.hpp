@@ -152,13 +152,18 @@ WC_HD int pad_sites(int Vh) { return (Vh + kTile - 1) / kTile * kTile; }
 // neighbour that is read again two t-slices later is still in the
 // memory-side cache.  Blocks past the last whole window are split into one
 // slab per XCD; a ragged tail keeps its own index.
+// chunk: blocks per chunk (kXcdChunk for 256-site blocks; launches whose
+// blocks cover fewer sites take more blocks per chunk, so that a chunk keeps
+// covering the same stretch of the lattice).  chunk <= 0 gives one
+// contiguous slab of blocks per XCD.
 constexpr int kXcdChunk = 16;
-WC_HD int xcd_block(int b, int nb) {
-    const int win = 8 * kXcdChunk;
+WC_HD int xcd_block(int b, int nb, int chunk = kXcdChunk) {
+    if (chunk <= 0) chunk = nb;  // a window larger than the launch: slabs only
+    const int win = 8 * chunk;
     const int full = nb / win * win;
     if (b < full) {
         const int k = b >> 3;
-        return ((k / kXcdChunk) * 8 + (b & 7)) * kXcdChunk + k % kXcdChunk;
+        return ((k / chunk) * 8 + (b & 7)) * chunk + k % chunk;
     }
     const int rb = b - full, per = (nb - full) >> 3;
     return full + ((rb < (per << 3)) ? (rb & 7) * per + (rb >> 3) : rb);

@@ -19,6 +19,8 @@
 // blocks of the same XCD shortly before, and hit in that XCD's L2.
 #include <hip/hip_cooperative_groups.h>
 
+#include <algorithm>
+
 #include "reduce.hpp"
 
 namespace {
@@ -157,13 +159,16 @@ template <int P, int MODE, int RED, bool NT, int LR>
 __global__ __launch_bounds__(kBlock) void k_mult(MultBatch B) {
     using R = typename Real<P>::T;
     int s, lb;
-    batch_locate(B.h, xcd_block(blockIdx.x, gridDim.x), s, lb);
+    batch_locate(B.h, xcd_block(blockIdx.x, gridDim.x, B.h.chunk), s, lb);
     const MultKArgs &a = B.d[s];
     if (a.done && *a.done) return;
     const int i = lb * (int)blockDim.x + threadIdx.x;  // 64, 128 or 256 sites per block
     const bool active = i < a.g.Vh;
     const int Vh = a.g.Vh;
     Spinor<R> out;
+    // the fused reduction's operand: the centre vector itself when aux is the
+    // centre (read once), else loaded after the output is stored
+    Spinor<R> ax;
     if (active) {
         Spinor<R> acc;
 #pragma unroll
@@ -182,6 +187,7 @@ __global__ __launch_bounds__(kBlock) void k_mult(MultBatch B) {
             Spinor<R> t;
             clover_apply<P, R, NT>(a.clov, Vh, i, acc, t);
             const Spinor<R> cen = SpinorIO<P>::template load<true>(a.center, Vh, i);
+            if (RED != R_NONE && a.aux == a.center) ax = cen;
 #pragma unroll
             for (int k = 0; k < 12; k++) out.c[k] = cen.c[k] + coef * t.c[k];
         } else if (MODE == M_DFULL) {
@@ -208,7 +214,7 @@ __global__ __launch_bounds__(kBlock) void k_mult(MultBatch B) {
 #pragma unroll
         for (int k = 0; k < N; k++) v[k] = 0.0;
         if (active) {
-            const Spinor<R> ax = SpinorIO<P>::template load<true>(a.aux, Vh, i);
+            if (!(MODE == M_DHAT && a.aux == a.center)) ax = SpinorIO<P>::template load<true>(a.aux, Vh, i);
 #pragma unroll
             for (int k = 0; k < 12; k++) {
                 const double ar = ax.c[k].re, ai = ax.c[k].im, orr = out.c[k].re, oi = out.c[k].im;
@@ -311,6 +317,7 @@ struct MrhsArgs {
     int nsys;     // systems of the launch
     int ngroups;  // groups of G systems: ceil(nsys / G)
     int ntiles;   // 64-site tiles of one parity
+    int chunk;    // tiles per XCD chunk of the block remap (0: one slab per XCD)
     MrhsSys s[kMaxSys];
 };
 
@@ -383,14 +390,16 @@ __device__ __forceinline__ void hop_dir_multi(const MrhsArgs &A, const SiteCoord
     }
 }
 
+// One workgroup per 64-site tile, one wavefront per group of G systems, so the
+// waves that share a tile's links and clover blocks run on one compute unit;
+// chunks of 64 tiles (4096 sites, as for the one-system stencil) per XCD.
+constexpr int kMrhsMaxGroups = 8;  // 16 systems at 2 per thread
 template <int P, int MODE, int RED, int LR, int G>
-__global__ __launch_bounds__(kBlock) void k_mult_mrhs(MrhsArgs A) {
+__global__ __launch_bounds__(64 * kMrhsMaxGroups) void k_mult_mrhs(MrhsArgs A) {
     using R = typename Real<P>::T;
-    // wave index over (tile, group) pairs, tile-major; uniform across the wave
-    const int f = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) +
-                                                 (int)(threadIdx.x >> 6));
-    const int tile = f / A.ngroups, q = f - tile * A.ngroups;
-    if (tile >= A.ntiles) return;  // whole wave: the tail of the last block
+    const int tile = xcd_block(blockIdx.x, gridDim.x, A.chunk);
+    const int q = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // uniform across the wave
+    if (tile >= A.ntiles || q >= A.ngroups) return;  // whole waves only
     bool live[G];
     bool any = false;
 #pragma unroll
@@ -403,6 +412,12 @@ __global__ __launch_bounds__(kBlock) void k_mult_mrhs(MrhsArgs A) {
     const int Vh = A.g.Vh;
     const int i = tile * 64 + (int)(threadIdx.x & 63);
     const bool active = i < Vh;
+    constexpr int NR = (RED == R_DOTNORM) ? 3 : 2;  // values of the fused reduction
+    double red[G][NR];
+#pragma unroll
+    for (int j = 0; j < G; j++)
+#pragma unroll
+        for (int k = 0; k < NR; k++) red[j][k] = 0.0;
     Spinor<R> acc[G];
 #pragma unroll
     for (int j = 0; j < G; j++)
@@ -421,36 +436,37 @@ __global__ __launch_bounds__(kBlock) void k_mult_mrhs(MrhsArgs A) {
             if (!live[j]) continue;
             const MrhsSys &S = A.s[q * G + j];
             if (MODE == M_DHAT) {
+                // the centre, and the reduction's operand beside it (the centre
+                // itself when aux is the centre)
                 const Spinor<R> cen = SpinorIO<P>::template load<true>(S.center, Vh, i);
+                Spinor<R> ax;
+                if (RED != R_NONE) ax = (S.aux == S.center) ? cen : SpinorIO<P>::template load<true>(S.aux, Vh, i);
 #pragma unroll
                 for (int k = 0; k < 12; k++) acc[j].c[k] = cen.c[k] + coef * acc[j].c[k];
+                SpinorIO<P>::template store<false>(S.out, Vh, i, acc[j]);
+                if (RED != R_NONE) {
+#pragma unroll
+                    for (int k = 0; k < 12; k++) {
+                        const double ar = ax.c[k].re, ai = ax.c[k].im, orr = acc[j].c[k].re, oi = acc[j].c[k].im;
+                        red[j][0] += ar * orr + ai * oi;
+                        red[j][1] += ar * oi - ai * orr;
+                        if (NR == 3) red[j][NR - 1] += orr * orr + oi * oi;
+                    }
+                }
+            } else {
+                SpinorIO<P>::template store<false>(S.out, Vh, i, acc[j]);
             }
-            SpinorIO<P>::template store<false>(S.out, Vh, i, acc[j]);
         }
     }
     if (RED != R_NONE) {
-        constexpr int N = (RED == R_DOT) ? 2 : 3;
 #pragma unroll
         for (int j = 0; j < G; j++) {
             if (!live[j]) continue;
-            const MrhsSys &S = A.s[q * G + j];
-            double v[N];
-#pragma unroll
-            for (int k = 0; k < N; k++) v[k] = 0.0;
-            if (active) {
-                const Spinor<R> ax = SpinorIO<P>::template load<true>(S.aux, Vh, i);
-#pragma unroll
-                for (int k = 0; k < 12; k++) {
-                    const double ar = ax.c[k].re, ai = ax.c[k].im, orr = acc[j].c[k].re, oi = acc[j].c[k].im;
-                    v[0] += ar * orr + ai * oi;
-                    v[1] += ar * oi - ai * orr;
-                    if (N == 3) v[N - 1] += orr * orr + oi * oi;
-                }
-            }
-            wave_fold<N>(v);
+            wave_fold<NR>(red[j]);
             if ((threadIdx.x & 63) == 0) {
+                double *part = A.s[q * G + j].partials;
 #pragma unroll
-                for (int k = 0; k < N; k++) S.partials[(size_t)k * A.ntiles + tile] = v[k];
+                for (int k = 0; k < NR; k++) part[(size_t)k * A.ntiles + tile] = red[j][k];
             }
         }
     }
@@ -458,7 +474,7 @@ __global__ __launch_bounds__(kBlock) void k_mult_mrhs(MrhsArgs A) {
 
 template <int P, int MODE, int RED, int LR, int G>
 void launch_mrhs_g(const MrhsArgs &A, int blocks, hipStream_t s) {
-    hipLaunchKernelGGL((k_mult_mrhs<P, MODE, RED, LR, G>), dim3(blocks), dim3(kBlock), 0, s, A);
+    hipLaunchKernelGGL((k_mult_mrhs<P, MODE, RED, LR, G>), dim3(blocks), dim3(64 * A.ngroups), 0, s, A);
 }
 
 template <int P, int MODE, int RED, int LR> void launch_mrhs_lr(const MrhsArgs &A, int blocks, hipStream_t s, int G) {
@@ -875,6 +891,7 @@ static int launch_mult_mrhs(hipStream_t s, const MultCall *calls, int n, wc_latt
     A.nsys = n;
     A.ngroups = (n + G - 1) / G;
     A.ntiles = blocks_of(lat->Vh, 64);
+    A.chunk = lattice_chunk(lat, c0.prec);
     double bytes = mult_operator_bytes(c0.prec, c0.mode, lr, lat->Vh);
     for (int k = 0; k < n; k++) {
         const MultCall &c = calls[k];
@@ -883,8 +900,8 @@ static int launch_mult_mrhs(hipStream_t s, const MultCall *calls, int n, wc_latt
         bytes += mult_spinor_bytes(c.prec, c.mode, c.red, c.aux == c.center, lat->Vh);
         lat->dslash_count++;
     }
-    const long waves = (long)A.ntiles * A.ngroups;
-    const int blocks = (int)((waves + kBlock / 64 - 1) / (kBlock / 64));
+    if (A.ngroups > kMrhsMaxGroups) return wc_fail(WC_EINVAL, "too many systems per multi-system launch");
+    const int blocks = A.ntiles;
     int slot = c0.mode == M_HOPINV ? KS_MULT_HOPINV_P64 + c0.prec : KS_MULT_DHAT_P64 + c0.prec;
     TimedLaunch t;
     if (tl->timing) {
@@ -926,12 +943,12 @@ int launch_mult_batch(hipStream_t s, const MultCall *calls, int n, wc_lattice *t
     {
         // several systems on one lattice in an inner-precision stencil: the
         // multi-system form, when the lattice has it switched on
-        bool same = n > 1 && c0.lat->mrhs > 0 && (c0.prec == P32 || c0.prec == P16) &&
+        bool same = n > 1 && mrhs_for(c0.lat, c0.prec) > 0 && (c0.prec == P32 || c0.prec == P16) &&
                     (c0.mode == M_HOPINV || c0.mode == M_DHAT);
         for (int k = 1; same && k < n; k++)
             same = calls[k].lat == c0.lat && calls[k].prec == c0.prec && calls[k].mode == c0.mode &&
                    calls[k].red == c0.red && calls[k].out_par == c0.out_par && calls[k].coef == c0.coef;
-        if (same) return launch_mult_mrhs(s, calls, n, timing_lat ? timing_lat : c0.lat, c0.lat->mrhs);
+        if (same) return launch_mult_mrhs(s, calls, n, timing_lat ? timing_lat : c0.lat, mrhs_for(c0.lat, c0.prec));
     }
     const int bs = launch_bs(c0.bs);
     if (!valid_block_size(bs)) return wc_fail(WC_EINVAL, "block size must be 64, 128 or 256");
@@ -975,6 +992,12 @@ int launch_mult_batch(hipStream_t s, const MultCall *calls, int n, wc_lattice *t
         if (c.mode != M_CLOV) lat->dslash_count++;
     }
     B.h.interleave = (same && n > 1) ? 1 : 0;
+    // the lattice's chunk of sites per XCD, in blocks of this launch (with the
+    // systems of one lattice interleaved block by block, every system's blocks)
+    {
+        const int tiles = lattice_chunk(c0.lat, c0.prec);
+        B.h.chunk = tiles <= 0 ? 0 : std::max(1, tiles / (bs / 64)) * (B.h.interleave ? n : 1);
+    }
     const int blocks = B.h.off[n];
     wc_lattice *tl = timing_lat ? timing_lat : c0.lat;
     int slot = KS_MULT_OTHER;

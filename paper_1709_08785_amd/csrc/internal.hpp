@@ -169,8 +169,15 @@ struct wc_lattice {
     int bs_pin = 0;
     int bs_tuned[3] = {0, 0, 0};
     // systems per thread of the multi-system stencil that batched solves on
-    // this lattice use in their inner loop (2 or 4), 0 for one system per thread
-    int mrhs = 4;
+    // this lattice use in their inner loop (2 or 4), 0 for one system per
+    // thread, -1 for the default of the precision (mrhs_for)
+    int mrhs = -1;
+    // stretch of sites, in 64-site tiles, that the stencils' block remap hands
+    // to one XCD at a time (0: one contiguous slab per XCD): pinned by the
+    // caller (>= 0), else tuned per precision with the block size (-1 = not yet)
+    int chunk_pin = -1;
+    int chunk_tuned[3] = {-1, -1, -1};
+    int chunk_force = -1;  // set by the tuner while it times a candidate
 
     // gauge links per precision: 8 slabs ([mu][parity]) of link_slab_bytes
     void *links[3] = {nullptr, nullptr, nullptr};
@@ -210,6 +217,14 @@ struct wc_lattice {
     long dslash_count = 0;
 };
 
+// systems per thread of the multi-system stencil in precision prec: the
+// setting, else 2 for FP32 and 4 for FP16 (the faster of the two in each
+// precision on the 12-source batch)
+inline int mrhs_for(const wc_lattice *lat, int prec) {
+    if (lat->mrhs >= 0) return lat->mrhs;
+    return prec == P16 ? 4 : 2;
+}
+
 // the link copy a stencil in precision prec reads, and its slab size
 inline const void *link_base(const wc_lattice *lat, int prec) {
     if (prec == P32 && lat->recon == 8) return lat->links8;
@@ -220,6 +235,14 @@ inline size_t link_slab_for(const wc_lattice *lat, int prec) {
     if (prec == P32 && lat->recon == 8) return link8_slab_bytes(lat->Vh);
     if (prec == P32 && lat->recon == 18) return link18_slab_bytes(lat->Vh);
     return link_slab_bytes(prec, lat->Vh);
+}
+
+constexpr int kDefaultChunk = 32;  // tiles per XCD chunk before tuning
+inline int lattice_chunk(const wc_lattice *lat, int prec) {
+    if (lat->chunk_force >= 0) return lat->chunk_force;
+    if (lat->chunk_pin >= 0) return lat->chunk_pin;
+    const int t = lat->chunk_tuned[prec];
+    return t >= 0 ? t : kDefaultChunk;
 }
 
 inline int lattice_bs(const wc_lattice *lat, int prec) {

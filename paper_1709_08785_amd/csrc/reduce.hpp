@@ -63,6 +63,7 @@ __device__ __forceinline__ void block_partials(double (&v)[N], double *partials,
 struct BatchHdr {
     int S;
     int interleave;
+    int chunk;  // blocks per XCD chunk of the stencil's block remap (xcd_block)
     int off[kMaxSys + 1];
 };
 

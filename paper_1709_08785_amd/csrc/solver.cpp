@@ -659,9 +659,13 @@ int solve_systems(std::vector<SolveSys> &sys, Arena &arena, double tol, const wc
     {
         wc_lattice *big = sys[0].lat;
         for (auto &s : sys) {
-            if (!s.lat->bs_pin && !s.lat->bs_tuned[P.inner_prec]) {
+            if ((!s.lat->bs_pin && !s.lat->bs_tuned[P.inner_prec]) ||
+                (s.lat->chunk_pin < 0 && s.lat->chunk_tuned[P.inner_prec] < 0)) {
                 const int rc = tune_block_size(s.lat, P.inner_prec, nullptr, nullptr);
-                if (rc == WC_ENOMEM) s.lat->bs_tuned[P.inner_prec] = 256;  // no room to time: the default
+                if (rc == WC_ENOMEM) {  // no room to time: the defaults
+                    s.lat->bs_tuned[P.inner_prec] = 256;
+                    s.lat->chunk_tuned[P.inner_prec] = kDefaultChunk;
+                }
                 else if (rc) return rc;
             }
             if (s.lat->Vh > big->Vh) big = s.lat;

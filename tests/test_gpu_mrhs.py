@@ -87,7 +87,7 @@ def test_mult_batch_against_oracle_and_single(dims, g, prec, recon):
                     assert rel(out, host(lat.unpack(one, prec))) < (1e-6 if prec == wc.FP32 else 2e-3), (k, out_par)
     finally:
         lat.set_link_recon(12)
-        lat.set_multi_rhs(4)
+        lat.set_multi_rhs(-1)
 
 
 @pytest.mark.parametrize("prec", [wc.FP32, wc.FP16])
@@ -109,7 +109,7 @@ def test_dhat_batch_against_oracle(g, prec):
             ref = oracle.dhat_ee(U, Finv, kappa, psis[k])
             assert rel(out, ref) < TOL[prec], k
     finally:
-        lat.set_multi_rhs(4)
+        lat.set_multi_rhs(-1)
 
 
 @pytest.mark.parametrize("g", [2, 4, 0])
@@ -133,15 +133,24 @@ def test_batched_solves_against_oracle(g):
             x_ref, _, _ = oracle.solve(U, F, kappa, bs[0], tol=1e-13)
             assert rel(host(xs[0]), x_ref) < 1e-9
     finally:
-        lat.set_multi_rhs(4)
+        lat.set_multi_rhs(-1)
 
 
 def test_settings_are_checked():
     lat, _, _ = setup((6, 6, 6, 10))
-    for bad in (1, 3, 8, -1):
+    for bad in (1, 3, 8, -2):
         with pytest.raises(wc.WCError):
             lat.set_multi_rhs(bad)
-    assert lat.multi_rhs == 4
+    assert lat.multi_rhs(wc.FP32) == 2 and lat.multi_rhs(wc.FP16) == 4 and lat.multi_rhs(wc.FP64) == 0
+    lat.set_multi_rhs(4)
+    assert lat.multi_rhs(wc.FP32) == 4
+    lat.set_multi_rhs(-1)
+    for bad in (-2, 1 << 21):
+        with pytest.raises(wc.WCError):
+            lat.set_xcd_chunk(bad)
+    lat.set_xcd_chunk(0)
+    assert lat.xcd_chunk(wc.FP32) == 0 and lat.xcd_chunk(wc.FP16) == 0
+    lat.set_xcd_chunk(-1)
 
 
 @pytest.mark.timeout(600)
