@@ -297,6 +297,21 @@ int wc_apply_Dee_oo(wc_lattice *lat, void *out_e, const void *in_e, int prec);
 int wc_apply_mult_batch(wc_lattice *lat, int n, void *const *out, const void *const *in, int out_parity, int prec);
 int wc_apply_Dee_oo_batch(wc_lattice *lat, int n, void *const *out_e, const void *const *in_e, int prec);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+   tight serving loops, harnesses that forbid hipMalloc): wc_apply_Dee_oo with
+   the same arguments, result and errors, whose odd-parity intermediate
+   F_oo^-1 H_oe in_e lives in a fixed array of wc_noalloc_scratch_bytes()
+   (128 MiB) that the library holds on each GPU it runs on until the process
+   ends, instead of a buffer allocated on first use.  The call allocates
+   nothing.  Returns WC_EINVAL, touching nothing, when one parity of a spinor
+   field in precision prec (wc_spinor_bytes) is larger than the array.  Every
+   call on one GPU shares that GPU's array: calls that overlap in time on one
+   GPU (other streams, other host threads) race and must be ordered by the
+   caller; each call overwrites the whole part of the array it reads.
+   Asynchronous on the lattice's stream. */
+int wc_apply_Dee_oo_noalloc(wc_lattice *lat, void *out_e, const void *in_e, int prec);
+size_t wc_noalloc_scratch_bytes(void);
+
 /* Site-diagonal clover term of parity p: out_p = F_pp in_p (inverse = 0) or
    F_pp^-1 in_p (inverse = 1), F being the site-diagonal term of eq. 3 (Sec. II-A)
    and F_ee, F_oo its even and odd blocks in the even-odd form of Sec. II-B

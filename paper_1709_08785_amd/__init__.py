@@ -110,6 +110,8 @@ def load_library():
         "wc_set_xcd_chunk": (I, [P, I]),
         "wc_xcd_chunk": (I, [P, I]),
         "wc_set_tune_cache": (I, [ctypes.c_char_p]),
+        "wc_apply_Dee_oo_noalloc": (I, [P, P, P, I]),
+        "wc_noalloc_scratch_bytes": (ctypes.c_size_t, []),
         "wc_apply_mult_batch": (I, [P, I, ctypes.POINTER(P), ctypes.POINTER(P), I, I]),
         "wc_apply_Dee_oo_batch": (I, [P, I, ctypes.POINTER(P), ctypes.POINTER(P), I]),
         "wc_multi_rhs": (I, [P, I]),
@@ -300,6 +302,11 @@ class Lattice:
     def apply_Dee_oo(self, out_e: torch.Tensor, in_e: torch.Tensor, prec):
         self._sync_stream()
         _check(self.lib.wc_apply_Dee_oo(self.h, _ptr(out_e), _ptr(in_e), _prec(prec)))
+
+    def apply_Dee_oo_noalloc(self, out_e: torch.Tensor, in_e: torch.Tensor, prec):
+        """D-hat_ee with its intermediate in the library's fixed scratch array (no allocation)."""
+        self._sync_stream()
+        _check(self.lib.wc_apply_Dee_oo_noalloc(self.h, _ptr(out_e), _ptr(in_e), _prec(prec)))
 
     def apply_mult_batch(self, outs, ins, out_parity: int, prec):
         """outs[k] = MULT ins[k] for up to 16 single-parity EO fields, in one launch."""
