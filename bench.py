@@ -527,11 +527,12 @@ def tune_mode(args):
         for pname, prec in (("fp32", wc.FP32), ("fp16", wc.FP16), ("fp64", wc.FP64)):
             r = lat.tune_block_size(prec)
             row["tuner"][pname] = {"us_per_pair": {str(k): round(v, 2) for k, v in r["us_per_pair"].items()},
-                                   "threads": r["threads"]}
+                                   "threads": r["threads"], "xcd_chunk_tiles": r["chunk"]}
         b = torch.from_numpy(synth.gaussian_source(dims, 2070)).cuda()
         reps = 20 if dims[0] <= 16 else 3
-        for label, pin in (("pinned_256", 256), ("tuned", 0)):
+        for label, pin, chunk in (("pinned_256_chunk32", 256, 32), ("tuned", 0, -1)):
             lat.set_block_size(pin)
+            lat.set_xcd_chunk(chunk)
             lat.solve(b, kappa, csw, args.tol)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -539,8 +540,9 @@ def tune_mode(args):
                 x, info = lat.solve(b, kappa, csw, args.tol)
             torch.cuda.synchronize()
             row[label] = {"ms": round((time.perf_counter() - t0) / reps * 1e3, 3), "threads": info["block_size"],
+                          "xcd_chunk_tiles": lat.xcd_chunk(wc.FP32),
                           "inner_iters": info["inner_iters_total"], "true_rel_residual": info["true_rel_residual"]}
-        row["speedup_tuned"] = round(row["pinned_256"]["ms"] / row["tuned"]["ms"], 3)
+        row["speedup_tuned"] = round(row["pinned_256_chunk32"]["ms"] / row["tuned"]["ms"], 3)
         log("tune %s %s" % (name, json.dumps(row)))
         out["lattices"][name] = row
         lat.close()
@@ -841,7 +843,7 @@ def main():
                                   args.inner_tol, args.tol),
                    "lattice": list(dims), "kappa": args.kappa, "csw": args.csw, "tol": args.tol,
                    "inner": args.inner, "inner_tol": args.inner_tol, "link_recon": args.recon,
-                   "threads_per_block": infos[-1]["block_size"]},
+                   "threads_per_block": infos[-1]["block_size"], "xcd_chunk_tiles": lat.xcd_chunk(inner)},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "small_config_8x8x8x8": small,
