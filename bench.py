@@ -193,6 +193,7 @@ def dslash_mode(args, dims):
     res = {}
     default_chunk = -1  # the lattice's own (tuned, else the default) chunk
     sweep = [int(v) for v in args.sweep_chunks.split(",")] if args.sweep_chunks else []
+    wave_caps = [int(v) for v in args.sweep_wave_caps.split(",")] if args.sweep_wave_caps else []
     for name, prec, recon in [("fp32", wc.FP32, 12), ("fp16", wc.FP16, 12), ("fp64", wc.FP64, 12),
                               ("fp32", wc.FP32, 8), ("fp32", wc.FP32, 18)]:
         lat.set_link_recon(recon)
@@ -216,6 +217,25 @@ def dslash_mode(args, dims):
             collect(lat, res, ("" if recon == 12 else "_recon%d" % recon) +
                     ("" if chunk == default_chunk else "_chunk%d" % chunk))
         lat.set_xcd_chunk(default_chunk)
+        # the waves-per-CU cap: the FP64 stencil against no cap (it runs at 8 by
+        # default), other caps on request
+        caps = [0] if (prec == wc.FP64 and recon == 12) else []
+        caps += [c for c in wave_caps if c not in caps]
+        for cap in caps:
+            lat.set_wave_cap(prec, cap)
+            for w in range(3):
+                lat.apply_mult(out, o_in, 0, prec)
+                lat.apply_Dee_oo(out, e_in, prec)
+            torch.cuda.synchronize()
+            lat.reset_kernel_stats()
+            lat.set_timing(True)
+            for k in range(args.steps):
+                lat.apply_mult(out, o_in, 0, prec)
+            for k in range(args.steps):
+                lat.apply_Dee_oo(out, e_in, prec)
+            lat.set_timing(False)
+            collect(lat, res, ("" if recon == 12 else "_recon%d" % recon) + "_cap%d" % cap)
+        lat.set_wave_cap(prec, -1)
         del eo, out
     # the multi-system stencil: the 12 fields of the point-source batch on one
     # lattice, with 4 or 2 fields per thread and with one field per thread (the
@@ -661,6 +681,12 @@ def main():
     ap.add_argument("--sweep-chunks", type=str, default="",
                     help="dslash mode: also time the stencils at these XCD chunks (tiles, comma-separated; "
                          "0 = one slab per XCD) and the batched ones at sub-batch sizes")
+    ap.add_argument("--wave-cap", type=int, default=None,
+                    help="waves-per-CU cap of the inner precision's one-system stencils in the timed solve "
+                         "(0 = none; default: the library's)")
+    ap.add_argument("--sweep-wave-caps", type=str, default="",
+                    help="dslash mode: also time the one-system stencils of every precision at these "
+                         "waves-per-CU caps (comma-separated; 0 = no cap)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -708,6 +734,8 @@ def main():
     del Ud
     torch.cuda.synchronize()
     inner = wc._prec(args.inner)
+    if args.wave_cap is not None:
+        lat.set_wave_cap(inner, args.wave_cap)
     solve_kw = dict(inner_prec=inner, inner_tol=args.inner_tol)
 
     for w in range(args.warmup):
@@ -843,7 +871,8 @@ def main():
                                   args.inner_tol, args.tol),
                    "lattice": list(dims), "kappa": args.kappa, "csw": args.csw, "tol": args.tol,
                    "inner": args.inner, "inner_tol": args.inner_tol, "link_recon": args.recon,
-                   "threads_per_block": infos[-1]["block_size"], "xcd_chunk_tiles": lat.xcd_chunk(inner)},
+                   "threads_per_block": infos[-1]["block_size"], "xcd_chunk_tiles": lat.xcd_chunk(inner),
+                   "waves_per_cu_cap": lat.wave_cap(inner)},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "small_config_8x8x8x8": small,

@@ -185,9 +185,25 @@ int wc_multi_rhs(const wc_lattice *lat, int prec);
 int wc_set_xcd_chunk(wc_lattice *lat, int tiles);
 int wc_xcd_chunk(const wc_lattice *lat, int prec);
 
+/* Occupancy cap of the one-system stencils (MULT, F^-1 H of Sec. II-B eq. 9,
+   and the D-hat_ee halves of eq. 8, plus D of eqs. 3-4): at most waves_per_cu
+   wavefronts of such a launch in precision prec share a compute unit.  The
+   library applies it by reserving LDS that the kernels do not use, so results
+   do not depend on it.  A cap that keeps fewer waves resident lets the L2
+   keep more of the neighbour spinors those waves share: the FP64 stencil runs
+   10-11% faster at 8 waves per CU than at the 12 its registers allow.
+   wc_set_wave_cap: 4, 8, 12 or 16 waves, 0 for no cap, -1 (default) for the
+   precision's default: 8 for FP64, none for FP32 and FP16.  Changing it drops
+   the tuned launch shape of that precision.  WC_EINVAL for other values or a
+   bad precision.  Batches of several systems on one lattice take no cap.
+   wc_wave_cap: the cap launches in prec use now (0 = none, also when the
+   device does not report its LDS size; -2 for a null lattice or bad prec). */
+int wc_set_wave_cap(wc_lattice *lat, int prec, int waves_per_cu);
+int wc_wave_cap(const wc_lattice *lat, int prec);
+
 /* Process-wide file in which the launch-shape tuner keeps its results, one
    line per device (architecture and compute units), lattice extents,
-   precision and FP32 link form; a later tuning of the same case, in this
+   precision, FP32 link form and wave cap (wc_set_wave_cap); a later tuning of the same case, in this
    process or another, takes the stored shape instead of timing.  path NULL or
    "" (the default) keeps no file.  A file that cannot be read or written only
    costs a new timing.  The path is copied. */

@@ -109,6 +109,8 @@ def load_library():
         "wc_set_multi_rhs": (I, [P, I]),
         "wc_set_xcd_chunk": (I, [P, I]),
         "wc_xcd_chunk": (I, [P, I]),
+        "wc_set_wave_cap": (I, [P, I, I]),
+        "wc_wave_cap": (I, [P, I]),
         "wc_set_tune_cache": (I, [ctypes.c_char_p]),
         "wc_apply_Dee_oo_noalloc": (I, [P, P, P, I]),
         "wc_noalloc_scratch_bytes": (ctypes.c_size_t, []),
@@ -249,6 +251,15 @@ class Lattice:
     def xcd_chunk(self, prec=FP32) -> int:
         """The XCD chunk a launch in this precision uses now."""
         return int(self.lib.wc_xcd_chunk(self.h, _prec(prec)))
+
+    def set_wave_cap(self, prec, waves_per_cu: int):
+        """Hold the one-system stencils in this precision to waves_per_cu waves per CU
+        (4, 8, 12, 16; 0: no cap; -1: the default, 8 for FP64 and none otherwise)."""
+        _check(self.lib.wc_set_wave_cap(self.h, _prec(prec), int(waves_per_cu)))
+
+    def wave_cap(self, prec=FP64) -> int:
+        """The waves-per-CU cap launches in this precision use now (0 = none)."""
+        return int(self.lib.wc_wave_cap(self.h, _prec(prec)))
 
     def multi_rhs(self, prec=FP32) -> int:
         """Systems per thread of a batched solve's stencil in this precision."""

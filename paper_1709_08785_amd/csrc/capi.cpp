@@ -292,6 +292,12 @@ extern "C" int wc_create_lattice(const int dims[4], void *stream, wc_lattice **o
     lat->g.Vh = lat->Vh;
     lat->stream = (hipStream_t)stream;
     lat->nblocks = (lat->Vh + 255) / 256;
+    {
+        int dev = 0, lds = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) == hipSuccess)
+            lat->lds_per_cu = lds;  // left 0 (no wave cap) if the device does not say
+    }
     int rc = arena_alloc(lat->arena, 1, lat->stream);
     if (!rc) {
         arena_bind(lat->arena, 0, lat->sys);
@@ -735,7 +741,7 @@ extern "C" int wc_set_tune_cache(const char *path) {
     return WC_OK;
 }
 
-// the cache key of (device, lattice, precision, link form)
+// the cache key of (device, lattice, precision, link form, waves per CU)
 static std::string tune_key(const wc_lattice *lat, int prec) {
     int dev = 0;
     hipDeviceProp_t p;
@@ -748,8 +754,8 @@ static std::string tune_key(const wc_lattice *lat, int prec) {
     for (auto &ch : arch)
         if (ch == ' ') ch = '_';
     char buf[256];
-    std::snprintf(buf, sizeof(buf), "%s %d %d %d %d %d %d %d", arch.c_str(), cus, lat->dims[0], lat->dims[1],
-                  lat->dims[2], lat->dims[3], prec, prec == P32 ? lat->recon : 12);
+    std::snprintf(buf, sizeof(buf), "%s %d %d %d %d %d %d %d %d", arch.c_str(), cus, lat->dims[0], lat->dims[1],
+                  lat->dims[2], lat->dims[3], prec, prec == P32 ? lat->recon : 12, wc_wave_cap(lat, prec));
     return buf;
 }
 
@@ -762,7 +768,7 @@ static bool tune_lookup(const std::string &key, int *bs, int *chunk, double us[3
     if (!f) return false;
     char line[512];
     bool found = false;
-    const std::string head = "wc-tune-v1 " + key + " ";
+    const std::string head = "wc-tune-v2 " + key + " ";
     while (std::fgets(line, sizeof(line), f)) {
         if (std::strncmp(line, head.c_str(), head.size()) != 0) continue;
         int b = 0, c = -1;
@@ -784,7 +790,7 @@ static void tune_store(const std::string &key, int bs, int chunk, const double u
     if (g_tune_cache.empty()) return;
     std::FILE *f = std::fopen(g_tune_cache.c_str(), "a");
     if (!f) return;  // a cache that cannot be written only costs a later tuning
-    std::fprintf(f, "wc-tune-v1 %s %d %d %.3f %.3f %.3f\n", key.c_str(), bs, chunk, us[0], us[1], us[2]);
+    std::fprintf(f, "wc-tune-v2 %s %d %d %.3f %.3f %.3f\n", key.c_str(), bs, chunk, us[0], us[1], us[2]);
     std::fclose(f);
 }
 
@@ -924,6 +930,26 @@ extern "C" int wc_set_xcd_chunk(wc_lattice *lat, int tiles) {
 extern "C" int wc_xcd_chunk(const wc_lattice *lat, int prec) {
     if (!lat || prec < 0 || prec > 2) return -2;
     return lattice_chunk(lat, prec);
+}
+
+extern "C" int wc_set_wave_cap(wc_lattice *lat, int prec, int waves_per_cu) {
+    if (!lat) return wc_fail(WC_EINVAL, "null lattice");
+    if (int rc = check_prec(prec)) return rc;
+    if (!(waves_per_cu == -1 || waves_per_cu == 0 ||
+          (waves_per_cu >= 4 && waves_per_cu <= 16 && waves_per_cu % 4 == 0)))
+        return wc_fail(WC_EINVAL, "waves per CU must be -1 (default), 0 (no cap), 4, 8, 12 or 16");
+    if (waves_per_cu != lat->wave_cap[prec]) {
+        lat->gen++;  // recorded graphs hold the old launch shape
+        lat->bs_tuned[prec] = 0;  // the tuned shape was timed under the old cap
+        lat->chunk_tuned[prec] = -1;
+    }
+    lat->wave_cap[prec] = waves_per_cu;
+    return WC_OK;
+}
+
+extern "C" int wc_wave_cap(const wc_lattice *lat, int prec) {
+    if (!lat || prec < 0 || prec > 2) return -2;
+    return lat->lds_per_cu > 0 ? wave_cap_for(lat, prec) : 0;
 }
 
 extern "C" int wc_block_size(const wc_lattice *lat, int prec) {

@@ -237,41 +237,45 @@ void k_mult(MultBatch B) {
     }
 }
 
-template <int P, int MODE, int RED, int LR> void launch_nt(const MultBatch &B, int blocks, int bs, hipStream_t s) {
+// lds: dynamic LDS bytes that cap the workgroups per CU of the one-system
+// (non-temporal) instance; the kernels use none of it
+template <int P, int MODE, int RED, int LR>
+void launch_nt(const MultBatch &B, int blocks, int bs, unsigned lds, hipStream_t s) {
     if (B.h.interleave)
         hipLaunchKernelGGL((k_mult<P, MODE, RED, false, LR>), dim3(blocks), dim3(bs), 0, s, B);
     else
-        hipLaunchKernelGGL((k_mult<P, MODE, RED, true, LR>), dim3(blocks), dim3(bs), 0, s, B);
+        hipLaunchKernelGGL((k_mult<P, MODE, RED, true, LR>), dim3(blocks), dim3(bs), lds, s, B);
 }
 
 // reconstruct-8 and full-link instances exist for the FP32 stencil only
-template <int P, int MODE, int RED> void launch_one(const MultBatch &B, int blocks, int bs, hipStream_t s, int lr) {
+template <int P, int MODE, int RED>
+void launch_one(const MultBatch &B, int blocks, int bs, unsigned lds, hipStream_t s, int lr) {
     if constexpr (P == P32) {
         if (lr == 8) {
-            launch_nt<P, MODE, RED, 8>(B, blocks, bs, s);
+            launch_nt<P, MODE, RED, 8>(B, blocks, bs, lds, s);
             return;
         }
         if (lr == 18) {
-            launch_nt<P, MODE, RED, 18>(B, blocks, bs, s);
+            launch_nt<P, MODE, RED, 18>(B, blocks, bs, lds, s);
             return;
         }
     }
-    launch_nt<P, MODE, RED, 12>(B, blocks, bs, s);
+    launch_nt<P, MODE, RED, 12>(B, blocks, bs, lds, s);
 }
 
 template <int P>
-void dispatch_mode(const MultBatch &B, int mode, int red, int blocks, int bs, hipStream_t s, int lr) {
+void dispatch_mode(const MultBatch &B, int mode, int red, int blocks, int bs, unsigned lds, hipStream_t s, int lr) {
     switch (mode) {
-    case M_HOPINV: launch_one<P, M_HOPINV, R_NONE>(B, blocks, bs, s, lr); break;
+    case M_HOPINV: launch_one<P, M_HOPINV, R_NONE>(B, blocks, bs, lds, s, lr); break;
     case M_DHAT:
-        if (red == R_DOT) launch_one<P, M_DHAT, R_DOT>(B, blocks, bs, s, lr);
-        else if (red == R_DOTNORM) launch_one<P, M_DHAT, R_DOTNORM>(B, blocks, bs, s, lr);
-        else launch_one<P, M_DHAT, R_NONE>(B, blocks, bs, s, lr);
+        if (red == R_DOT) launch_one<P, M_DHAT, R_DOT>(B, blocks, bs, lds, s, lr);
+        else if (red == R_DOTNORM) launch_one<P, M_DHAT, R_DOTNORM>(B, blocks, bs, lds, s, lr);
+        else launch_one<P, M_DHAT, R_NONE>(B, blocks, bs, lds, s, lr);
         break;
-    case M_DFULL: launch_one<P, M_DFULL, R_NONE>(B, blocks, bs, s, lr); break;
-    case M_INVSRC: launch_one<P, M_INVSRC, R_NONE>(B, blocks, bs, s, lr); break;
-    case M_HOP: launch_one<P, M_HOP, R_NONE>(B, blocks, bs, s, lr); break;
-    case M_CLOV: launch_one<P, M_CLOV, R_NONE>(B, blocks, bs, s, lr); break;
+    case M_DFULL: launch_one<P, M_DFULL, R_NONE>(B, blocks, bs, lds, s, lr); break;
+    case M_INVSRC: launch_one<P, M_INVSRC, R_NONE>(B, blocks, bs, lds, s, lr); break;
+    case M_HOP: launch_one<P, M_HOP, R_NONE>(B, blocks, bs, lds, s, lr); break;
+    case M_CLOV: launch_one<P, M_CLOV, R_NONE>(B, blocks, bs, lds, s, lr); break;
     }
 }
 
@@ -1032,9 +1036,10 @@ int launch_mult_batch(hipStream_t s, const MultCall *calls, int n, wc_lattice *t
             t.parts.push_back(op);
         }
     }
-    if (c0.prec == P64) dispatch_mode<P64>(B, c0.mode, c0.red, blocks, bs, s, 12);
-    else if (c0.prec == P32) dispatch_mode<P32>(B, c0.mode, c0.red, blocks, bs, s, lr);
-    else dispatch_mode<P16>(B, c0.mode, c0.red, blocks, bs, s, 12);
+    const unsigned lds = B.h.interleave ? 0u : cap_lds_bytes(c0.lat, c0.prec, bs);
+    if (c0.prec == P64) dispatch_mode<P64>(B, c0.mode, c0.red, blocks, bs, lds, s, 12);
+    else if (c0.prec == P32) dispatch_mode<P32>(B, c0.mode, c0.red, blocks, bs, lds, s, lr);
+    else dispatch_mode<P16>(B, c0.mode, c0.red, blocks, bs, lds, s, 12);
     WC_HIP(hipGetLastError());
     if (tl->timing) timing_end(tl, t);
     if (c0.red != R_NONE && c0.mode == M_DHAT) {

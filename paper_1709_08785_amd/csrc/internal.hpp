@@ -178,6 +178,11 @@ struct wc_lattice {
     int chunk_pin = -1;
     int chunk_tuned[3] = {-1, -1, -1};
     int chunk_force = -1;  // set by the tuner while it times a candidate
+    // waves per CU that the one-system stencils are held to, per precision
+    // (0: no cap, -1: the precision's default, wave_cap_for), and the LDS
+    // bytes per CU of the device, through which the cap is applied
+    int wave_cap[3] = {-1, -1, -1};
+    int lds_per_cu = 0;
 
     // gauge links per precision: 8 slabs ([mu][parity]) of link_slab_bytes
     void *links[3] = {nullptr, nullptr, nullptr};
@@ -243,6 +248,30 @@ inline int lattice_chunk(const wc_lattice *lat, int prec) {
     if (lat->chunk_pin >= 0) return lat->chunk_pin;
     const int t = lat->chunk_tuned[prec];
     return t >= 0 ? t : kDefaultChunk;
+}
+
+// The FP64 stencil (140-196 VGPRs) runs 3 workgroups of 256 threads per CU
+// when left alone; held to 2 (8 waves per CU) its L2 keeps more of the
+// neighbours that the resident waves share, and MULT and D-hat run 10-11%
+// faster at 32^3x64 and 48^3x96.  The FP32 and FP16 stencils lose time under
+// any cap, so they have none by default.
+constexpr int kDefaultWaveCap64 = 8;
+inline int wave_cap_for(const wc_lattice *lat, int prec) {
+    const int c = lat->wave_cap[prec];
+    return c >= 0 ? c : (prec == P64 ? kDefaultWaveCap64 : 0);
+}
+// Dynamic LDS bytes per workgroup that leave room for exactly cap / (bs / 64)
+// workgroups of bs threads on a CU (0 = no cap).  The bytes are a multiple of
+// 512 (the allocation granule) less 512 for the kernel's own few bytes of
+// LDS, so floor(lds_per_cu / allocation) is the wanted count for up to 16
+// workgroups per CU.
+inline unsigned cap_lds_bytes(const wc_lattice *lat, int prec, int bs) {
+    const int cap = wave_cap_for(lat, prec);
+    if (cap <= 0 || lat->lds_per_cu <= 0) return 0;
+    int blocks = cap / (bs / 64);
+    if (blocks < 1) blocks = 1;
+    const int per = (lat->lds_per_cu / blocks) / 512 * 512 - 512;
+    return per > 0 ? (unsigned)per : 0u;
 }
 
 inline int lattice_bs(const wc_lattice *lat, int prec) {
