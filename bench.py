@@ -530,7 +530,8 @@ def tune_mode(args):
     (F^-1 H, then the D-hat half with its fused dot) at 64, 128 and 256 threads
     per block in each precision, its choice, and the nested solve (FP32 inner,
     Algorithm 1 outer, kappa 0.13, c_SW 1, Gaussian source, tol) at the tuned
-    size against 256 pinned."""
+    size against 256 pinned, and at 2 to 32 inner iterations between host
+    convergence reads."""
     import torch
 
     import paper_1709_08785_amd as wc
@@ -563,6 +564,17 @@ def tune_mode(args):
                           "xcd_chunk_tiles": lat.xcd_chunk(wc.FP32),
                           "inner_iters": info["inner_iters_total"], "true_rel_residual": info["true_rel_residual"]}
         row["speedup_tuned"] = round(row["pinned_256_chunk32"]["ms"] / row["tuned"]["ms"], 3)
+        # inner iterations queued between host convergence reads: fewer reads
+        # against more launches queued after convergence (they return at once)
+        row["check_every_ms"] = {}
+        for ce in (2, 4, 8, 16, 32):
+            lat.solve(b, kappa, csw, args.tol, check_every=ce)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for r in range(reps):
+                x, info = lat.solve(b, kappa, csw, args.tol, check_every=ce)
+            torch.cuda.synchronize()
+            row["check_every_ms"][str(ce)] = round((time.perf_counter() - t0) / reps * 1e3, 3)
         log("tune %s %s" % (name, json.dumps(row)))
         out["lattices"][name] = row
         lat.close()
