@@ -260,17 +260,18 @@ inline int wave_cap_for(const wc_lattice *lat, int prec) {
     const int c = lat->wave_cap[prec];
     return c >= 0 ? c : (prec == P64 ? kDefaultWaveCap64 : 0);
 }
-// Dynamic LDS bytes per workgroup that leave room for exactly cap / (bs / 64)
-// workgroups of bs threads on a CU (0 = no cap).  The bytes are a multiple of
-// 512 (the allocation granule) less 512 for the kernel's own few bytes of
-// LDS, so floor(lds_per_cu / allocation) is the wanted count for up to 16
-// workgroups per CU.
+// Dynamic LDS bytes per workgroup that leave room for exactly b = cap / (bs / 64)
+// workgroups of bs threads on a CU (0 = no cap).  A workgroup's allocation
+// must lie in (L / (b + 1), L / b] for L bytes of LDS per CU; the bytes are
+// taken from the middle of that window, less the kernel's own few bytes of
+// LDS, so that rounding up to the allocation granule keeps them inside it.
 inline unsigned cap_lds_bytes(const wc_lattice *lat, int prec, int bs) {
     const int cap = wave_cap_for(lat, prec);
-    if (cap <= 0 || lat->lds_per_cu <= 0) return 0;
+    const int L = lat->lds_per_cu;
+    if (cap <= 0 || L <= 0) return 0;
     int blocks = cap / (bs / 64);
     if (blocks < 1) blocks = 1;
-    const int per = (lat->lds_per_cu / blocks) / 512 * 512 - 512;
+    const int per = (L / blocks + L / (blocks + 1)) / 2 / 128 * 128 - 128;
     return per > 0 ? (unsigned)per : 0u;
 }
 

@@ -3,7 +3,10 @@
 //   - xcd_block maps the hardware blocks of a launch one-to-one onto its
 //     logical blocks, for any block count;
 //   - the tiled EO addressing (tile_off) covers every padded slab exactly once
-//     for each field's plane list, and blocks_of covers every site.
+//     for each field's plane list, and blocks_of covers every site;
+//   - the LDS reservation of the wave cap leaves room for exactly the wanted
+//     number of workgroups per CU on a 160 KiB-LDS CU, whatever the kernel's
+//     own LDS (up to 256 B) and for allocation granules of 64 to 1024 bytes.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -36,6 +39,55 @@ int main() {
                 return 1;
             }
         }
+    }
+    for (int chunk : {-1, 0, 1, 2, 8, 16, 32, 64, 1000}) {
+        for (int nb : nbs) {
+            std::vector<int> seen(nb, 0);
+            for (int b = 0; b < nb; b++) {
+                const int l = xcd_block(b, nb, chunk);
+                if (l < 0 || l >= nb || seen[l]++) {
+                    printf("xcd_block not one-to-one: nb %d chunk %d b %d -> %d\n", nb, chunk, b, l);
+                    return 1;
+                }
+            }
+        }
+    }
+    {
+        wc_lattice *lat = new wc_lattice();
+        if (wave_cap_for(lat, P64) != 8 || wave_cap_for(lat, P32) != 0 || wave_cap_for(lat, P16) != 0) {
+            printf("wave cap defaults wrong\n");
+            return 1;
+        }
+        for (int lds : {163840}) {
+            lat->lds_per_cu = lds;
+            for (int cap : {4, 8, 12, 16})
+                for (int bs : {64, 128, 256}) {
+                    lat->wave_cap[P32] = cap;
+                    int want = cap / (bs / 64);
+                    if (want < 1) want = 1;
+                    const unsigned dyn = cap_lds_bytes(lat, P32, bs);
+                    for (unsigned own : {0u, 96u, 256u})
+                        for (unsigned gran : {64u, 128u, 256u, 512u, 1024u}) {
+                            const unsigned alloc = (dyn + own + gran - 1) / gran * gran;
+                            if (dyn == 0 || alloc > (unsigned)lds || (int)(lds / alloc) != want) {
+                                printf("wave cap LDS wrong: lds %d cap %d bs %d own %u gran %u: %u bytes -> %u blocks\n",
+                                       lds, cap, bs, own, gran, dyn, alloc ? lds / alloc : 0);
+                                return 1;
+                            }
+                        }
+                }
+            lat->wave_cap[P32] = 0;
+            if (cap_lds_bytes(lat, P32, 256) != 0) {
+                printf("no cap must reserve nothing\n");
+                return 1;
+            }
+        }
+        lat->lds_per_cu = 0;
+        if (cap_lds_bytes(lat, P64, 256) != 0) {
+            printf("an unknown LDS size must reserve nothing\n");
+            return 1;
+        }
+        delete lat;
     }
     for (int Vh : {1, 63, 64, 65, 1080, 2048, 4097}) {
         for (int bs : {64, 128, 256})
