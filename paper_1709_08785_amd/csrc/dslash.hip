@@ -306,9 +306,9 @@ double mult_operator_bytes(int prec, int mode, int lr, int Vh) {
 // clover block are computed or loaded once and applied to all G spinors, so
 // the per-site work that does not depend on the source is shared, and the
 // operator is read from memory once per site for every system of the launch.
-// A wavefront covers 64 consecutive sites of one group of G systems; the
-// waves of one tile's groups are adjacent in the launch order (and so on one
-// XCD), so their link and clover loads after the first hit in cache.
+// A wavefront covers the 64 sites of one tile for one group of G systems, and
+// the waves of all groups of a tile form one workgroup (so they run on one
+// compute unit), so their link and clover loads after the first hit in cache.
 // Reductions are per wave: each wave folds its G systems' sums and writes one
 // partial per system and tile, which the finalize stage sums in tile order.
 // ---------------------------------------------------------------------------
@@ -406,7 +406,8 @@ __device__ __forceinline__ void hop_dir_multi(const MrhsArgs &A, const SiteCoord
 
 // One workgroup per 64-site tile, one wavefront per group of G systems, so the
 // waves that share a tile's links and clover blocks run on one compute unit;
-// chunks of 64 tiles (4096 sites, as for the one-system stencil) per XCD.
+// the tiles are handed to the XCDs in the lattice's chunks, as for the
+// one-system stencil.
 constexpr int kMrhsMaxGroups = 8;  // 16 systems at 2 per thread
 template <int P, int MODE, int RED, int LR, int G>
 __global__ __launch_bounds__(64 * kMrhsMaxGroups) void k_mult_mrhs(MrhsArgs A) {

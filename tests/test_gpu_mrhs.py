@@ -29,7 +29,9 @@ if not torch.cuda.is_available():
 
 import paper_1709_08785_amd as wc  # noqa: E402
 
-TOL = {wc.FP32: 1e-5, wc.FP16: 2e-3}
+TOL = {wc.FP64: 1e-13, wc.FP32: 1e-5, wc.FP16: 2e-3}
+# batched against one-field results: equal up to the rounding of the stored output
+SAME = {wc.FP64: 1e-14, wc.FP32: 1e-6, wc.FP16: 2e-3}
 
 
 def dev(a):
@@ -59,7 +61,8 @@ def setup(dims, kappa=0.13, csw=1.0, seed=1300):
     return _cache[key]
 
 
-@pytest.mark.parametrize("prec,recon", [(wc.FP32, 12), (wc.FP32, 8), (wc.FP32, 18), (wc.FP16, 12)])
+# FP64 batches take the one-system-per-thread path (fields' workgroups interleaved)
+@pytest.mark.parametrize("prec,recon", [(wc.FP32, 12), (wc.FP32, 8), (wc.FP32, 18), (wc.FP16, 12), (wc.FP64, 12)])
 @pytest.mark.parametrize("g", [2, 4, 0])
 @pytest.mark.parametrize("dims", [(6, 6, 6, 10), (4, 6, 8, 10)])
 def test_mult_batch_against_oracle_and_single(dims, g, prec, recon):
@@ -84,13 +87,13 @@ def test_mult_batch_against_oracle_and_single(dims, g, prec, recon):
                     # the rounding of the stored output
                     lat.apply_mult(lat.parity_view(one, out_par, prec), lat.parity_view(eo_in[k], 1 - out_par, prec),
                                    out_par, prec)
-                    assert rel(out, host(lat.unpack(one, prec))) < (1e-6 if prec == wc.FP32 else 2e-3), (k, out_par)
+                    assert rel(out, host(lat.unpack(one, prec))) < SAME[prec], (k, out_par)
     finally:
         lat.set_link_recon(12)
         lat.set_multi_rhs(-1)
 
 
-@pytest.mark.parametrize("prec", [wc.FP32, wc.FP16])
+@pytest.mark.parametrize("prec", [wc.FP32, wc.FP16, wc.FP64])
 @pytest.mark.parametrize("g", [2, 4])
 def test_dhat_batch_against_oracle(g, prec):
     dims = (6, 6, 6, 10)
