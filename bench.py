@@ -548,7 +548,8 @@ def tune_mode(args):
         for pname, prec in (("fp32", wc.FP32), ("fp16", wc.FP16), ("fp64", wc.FP64)):
             r = lat.tune_block_size(prec)
             row["tuner"][pname] = {"us_per_pair": {str(k): round(v, 2) for k, v in r["us_per_pair"].items()},
-                                   "threads": r["threads"], "xcd_chunk_tiles": r["chunk"]}
+                                   "threads": r["threads"], "xcd_chunk_tiles": r["chunk"],
+                                   "waves_per_cu_cap": r["wave_cap"]}
         b = torch.from_numpy(synth.gaussian_source(dims, 2070)).cuda()
         reps = 20 if dims[0] <= 16 else 3
         for label, pin, chunk in (("pinned_256_chunk32", 256, 32), ("tuned", 0, -1)):
@@ -884,7 +885,7 @@ def main():
                    "lattice": list(dims), "kappa": args.kappa, "csw": args.csw, "tol": args.tol,
                    "inner": args.inner, "inner_tol": args.inner_tol, "link_recon": args.recon,
                    "threads_per_block": infos[-1]["block_size"], "xcd_chunk_tiles": lat.xcd_chunk(inner),
-                   "waves_per_cu_cap": lat.wave_cap(inner)},
+                   "waves_per_cu_cap": {"mult": lat.wave_cap(inner), "dhat": lat.wave_cap(inner, dhat=True)}},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "small_config_8x8x8x8": small,

@@ -145,10 +145,14 @@ void wc_solve_params_default(wc_solve_params *p);
    zero vectors at 64, 128 and 256 threads and at XCD chunks of 8, 16, 32 and
    64 tiles (wc_set_xcd_chunk; only the pinned one when pinned) and keeps the
    fastest shape; 256 threads at chunk 32 are displaced only by a shape at
-   least 3% faster.  us_per_pair[3] (may be NULL) receives microseconds per
-   pair for 64, 128, 256 at the chosen chunk; *threads (may be NULL) the
-   chosen block size.  With a tuning cache (wc_set_tune_cache) holding this
-   case, the stored shape is taken without timing.
+   least 3% faster.  At that shape it then times the two kernels on their
+   own under no cap and caps of 8 and 12 waves per CU (wc_set_wave_cap;
+   skipped when pinned), and each kernel class keeps a cap only if it beats
+   the precision's default by 3%.  us_per_pair[3] (may be NULL) receives
+   microseconds per pair for 64, 128, 256 at the chosen chunk under the
+   default cap; *threads (may be NULL) the chosen block size.  With a tuning
+   cache (wc_set_tune_cache) holding this case, the stored shape and caps are
+   taken without timing.
    Needs links and clover (WC_ENOTREADY).  Allocates three vectors of the
    precision for the duration of the call and synchronises the stream. */
 int wc_set_block_size(wc_lattice *lat, int threads);
@@ -192,18 +196,23 @@ int wc_xcd_chunk(const wc_lattice *lat, int prec);
    do not depend on it.  A cap that keeps fewer waves resident lets the L2
    keep more of the neighbour spinors those waves share: the FP64 stencil runs
    10-11% faster at 8 waves per CU than at the 12 its registers allow.
-   wc_set_wave_cap: 4, 8, 12 or 16 waves, 0 for no cap, -1 (default) for the
-   precision's default: 8 for FP64, none for FP32 and FP16.  Changing it drops
-   the tuned launch shape of that precision.  WC_EINVAL for other values or a
-   bad precision.  Batches of several systems on one lattice take no cap.
-   wc_wave_cap: the cap launches in prec use now (0 = none, also when the
-   device does not report its LDS size; -2 for a null lattice or bad prec). */
+   Unless pinned, the cap is chosen per precision and per kernel class (the
+   D-hat half, and every other stencil) by the launch-shape tuner
+   (wc_tune_block_size) among no cap, 8 and 12 waves; before tuning it is 8
+   for FP64 and none for FP32 and FP16.
+   wc_set_wave_cap: 4, 8, 12 or 16 waves pins the cap of both classes, 0 pins
+   no cap, -1 returns to tuning.  Changing it drops the tuned launch shape of
+   that precision.  WC_EINVAL for other values or a bad precision.  Batches of
+   several systems on one lattice take no cap.
+   wc_wave_cap: the cap that launches in prec use now, for the D-hat half
+   (dhat != 0) or the other stencils (dhat = 0); 0 = none, also when the
+   device does not report its LDS size; -2 for a null lattice or bad prec. */
 int wc_set_wave_cap(wc_lattice *lat, int prec, int waves_per_cu);
-int wc_wave_cap(const wc_lattice *lat, int prec);
+int wc_wave_cap(const wc_lattice *lat, int prec, int dhat);
 
 /* Process-wide file in which the launch-shape tuner keeps its results, one
    line per device (architecture and compute units), lattice extents,
-   precision, FP32 link form and wave cap (wc_set_wave_cap); a later tuning of the same case, in this
+   precision, FP32 link form and pinned wave cap (wc_set_wave_cap); a later tuning of the same case, in this
    process or another, takes the stored shape instead of timing.  path NULL or
    "" (the default) keeps no file.  A file that cannot be read or written only
    costs a new timing.  The path is copied. */

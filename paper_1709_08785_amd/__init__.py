@@ -110,7 +110,7 @@ def load_library():
         "wc_set_xcd_chunk": (I, [P, I]),
         "wc_xcd_chunk": (I, [P, I]),
         "wc_set_wave_cap": (I, [P, I, I]),
-        "wc_wave_cap": (I, [P, I]),
+        "wc_wave_cap": (I, [P, I, I]),
         "wc_set_tune_cache": (I, [ctypes.c_char_p]),
         "wc_apply_Dee_oo_noalloc": (I, [P, P, P, I]),
         "wc_noalloc_scratch_bytes": (ctypes.c_size_t, []),
@@ -231,13 +231,15 @@ class Lattice:
         return int(self.lib.wc_block_size(self.h, _prec(prec)))
 
     def tune_block_size(self, prec=FP32) -> dict:
-        """Time the inner loop's stencil pair at 64, 128, 256 threads per block and keep
-        the fastest; returns the microseconds per pair and the choice."""
+        """Time the inner loop's stencil pair at 64, 128, 256 threads per block and the
+        XCD chunks, then the wave caps, and keep the fastest; returns the microseconds per
+        pair and the choices."""
         us = (ctypes.c_double * 3)()
         th = ctypes.c_int()
         _check(self.lib.wc_tune_block_size(self.h, _prec(prec), us, ctypes.byref(th)))
         return {"us_per_pair": {64: us[0], 128: us[1], 256: us[2]}, "threads": th.value,
-                "chunk": self.xcd_chunk(prec)}
+                "chunk": self.xcd_chunk(prec),
+                "wave_cap": {"mult": self.wave_cap(prec), "dhat": self.wave_cap(prec, dhat=True)}}
 
     def set_multi_rhs(self, systems_per_thread: int):
         """Systems per thread of the batched solves' multi-system stencil (2 or 4), 0 for one."""
@@ -253,13 +255,15 @@ class Lattice:
         return int(self.lib.wc_xcd_chunk(self.h, _prec(prec)))
 
     def set_wave_cap(self, prec, waves_per_cu: int):
-        """Hold the one-system stencils in this precision to waves_per_cu waves per CU
-        (4, 8, 12, 16; 0: no cap; -1: the default, 8 for FP64 and none otherwise)."""
+        """Pin the one-system stencils in this precision to waves_per_cu waves per CU
+        (4, 8, 12, 16; 0: no cap), or -1 to let the tuner choose (default: 8 for FP64,
+        none otherwise, before tuning)."""
         _check(self.lib.wc_set_wave_cap(self.h, _prec(prec), int(waves_per_cu)))
 
-    def wave_cap(self, prec=FP64) -> int:
-        """The waves-per-CU cap launches in this precision use now (0 = none)."""
-        return int(self.lib.wc_wave_cap(self.h, _prec(prec)))
+    def wave_cap(self, prec=FP64, dhat: bool = False) -> int:
+        """The waves-per-CU cap launches in this precision use now, for the D-hat half
+        (dhat) or the other stencils (0 = none)."""
+        return int(self.lib.wc_wave_cap(self.h, _prec(prec), 1 if dhat else 0))
 
     def multi_rhs(self, prec=FP32) -> int:
         """Systems per thread of a batched solve's stencil in this precision."""

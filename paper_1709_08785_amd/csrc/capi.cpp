@@ -559,6 +559,7 @@ static void set_recon(wc_lattice *lat, int recon, bool automatic) {
         lat->recon = recon;
         lat->bs_tuned[P32] = 0;  // the FP32 stencil changed: tune again
         lat->chunk_tuned[P32] = -1;
+        lat->cap_tuned[P32][0] = lat->cap_tuned[P32][1] = -1;
         lat->gen++;
     }
     lat->recon_auto = automatic;
@@ -741,7 +742,7 @@ extern "C" int wc_set_tune_cache(const char *path) {
     return WC_OK;
 }
 
-// the cache key of (device, lattice, precision, link form, waves per CU)
+// the cache key of (device, lattice, precision, link form, pinned waves per CU or -1)
 static std::string tune_key(const wc_lattice *lat, int prec) {
     int dev = 0;
     hipDeviceProp_t p;
@@ -755,28 +756,30 @@ static std::string tune_key(const wc_lattice *lat, int prec) {
         if (ch == ' ') ch = '_';
     char buf[256];
     std::snprintf(buf, sizeof(buf), "%s %d %d %d %d %d %d %d %d", arch.c_str(), cus, lat->dims[0], lat->dims[1],
-                  lat->dims[2], lat->dims[3], prec, prec == P32 ? lat->recon : 12, wc_wave_cap(lat, prec));
+                  lat->dims[2], lat->dims[3], prec, prec == P32 ? lat->recon : 12, lat->wave_cap[prec]);
     return buf;
 }
 
-// the last entry for key in the cache file: block size, chunk, microseconds
-// per pair at the block sizes 64, 128, 256
-static bool tune_lookup(const std::string &key, int *bs, int *chunk, double us[3]) {
+// the last entry for key in the cache file: block size, chunk, wave caps of
+// the two kernel classes, microseconds per pair at the block sizes 64, 128, 256
+static bool tune_lookup(const std::string &key, int *bs, int *chunk, int caps[2], double us[3]) {
     std::lock_guard<std::mutex> g(g_tune_mu);
     if (g_tune_cache.empty()) return false;
     std::FILE *f = std::fopen(g_tune_cache.c_str(), "r");
     if (!f) return false;
     char line[512];
     bool found = false;
-    const std::string head = "wc-tune-v2 " + key + " ";
+    const std::string head = "wc-tune-v3 " + key + " ";
     while (std::fgets(line, sizeof(line), f)) {
         if (std::strncmp(line, head.c_str(), head.size()) != 0) continue;
-        int b = 0, c = -1;
+        int b = 0, c = -1, w0 = -1, w1 = -1;
         double u[3] = {0, 0, 0};
-        if (std::sscanf(line + head.size(), "%d %d %lf %lf %lf", &b, &c, &u[0], &u[1], &u[2]) == 5 &&
-            valid_block_size(b) && c >= 0) {
+        if (std::sscanf(line + head.size(), "%d %d %d %d %lf %lf %lf", &b, &c, &w0, &w1, &u[0], &u[1], &u[2]) == 7 &&
+            valid_block_size(b) && c >= 0 && valid_wave_cap(w0) && valid_wave_cap(w1)) {
             *bs = b;
             *chunk = c;
+            caps[0] = w0;
+            caps[1] = w1;
             for (int k = 0; k < 3; k++) us[k] = u[k];
             found = true;
         }
@@ -785,12 +788,13 @@ static bool tune_lookup(const std::string &key, int *bs, int *chunk, double us[3
     return found;
 }
 
-static void tune_store(const std::string &key, int bs, int chunk, const double us[3]) {
+static void tune_store(const std::string &key, int bs, int chunk, const int caps[2], const double us[3]) {
     std::lock_guard<std::mutex> g(g_tune_mu);
     if (g_tune_cache.empty()) return;
     std::FILE *f = std::fopen(g_tune_cache.c_str(), "a");
     if (!f) return;  // a cache that cannot be written only costs a later tuning
-    std::fprintf(f, "wc-tune-v2 %s %d %d %.3f %.3f %.3f\n", key.c_str(), bs, chunk, us[0], us[1], us[2]);
+    std::fprintf(f, "wc-tune-v3 %s %d %d %d %d %.3f %.3f %.3f\n", key.c_str(), bs, chunk, caps[0], caps[1], us[0], us[1],
+                 us[2]);
     std::fclose(f);
 }
 
@@ -799,18 +803,23 @@ static void tune_store(const std::string &key, int bs, int chunk, const double u
 // XCD chunk, and keep the fastest.  The default shape (256 threads, chunk
 // kDefaultChunk) is displaced only by a shape at least 3% faster, so that
 // timing noise does not flip the choice on large lattices.  A pinned chunk
-// is the only one timed.  With a cache file set, a stored result for the same
-// device, lattice, precision and link form is taken instead of timing.
+// is the only one timed.  Then, unless the caller pinned a wave cap, the two
+// kernels are timed on their own at the chosen shape under caps of 0, 8 and
+// 12 waves per CU, and each keeps the cap that beats the precision's default
+// by 3%.  With a cache file set, a stored result for the same device,
+// lattice, precision, link form and pinned cap is taken instead of timing.
 int tune_block_size(wc_lattice *lat, int prec, double us[3], int *chosen) {
     if (!lat->have_links || !lat->have_clover)
         return wc_fail(WC_ENOTREADY, "block-size tuning needs links and clover");
     const std::string key = tune_key(lat, prec);
     {
-        int b = 0, c = -1;
+        int b = 0, c = -1, w[2] = {-1, -1};
         double u[3];
-        if (tune_lookup(key, &b, &c, u)) {
+        if (tune_lookup(key, &b, &c, w, u)) {
             lat->bs_tuned[prec] = b;
             lat->chunk_tuned[prec] = c;
+            lat->cap_tuned[prec][0] = w[0];
+            lat->cap_tuned[prec][1] = w[1];
             lat->gen++;
             if (us)
                 for (int k = 0; k < 3; k++) us[k] = u[k];
@@ -827,28 +836,38 @@ int tune_block_size(wc_lattice *lat, int prec, double us[3], int *chosen) {
     const bool timing = lat->timing;
     const long dcount = lat->dslash_count;
     lat->timing = false;
+    // the block size and chunk are timed under the precision's default cap
+    lat->cap_tuned[prec][0] = lat->cap_tuned[prec][1] = -1;
     const int cand[3] = {64, 128, 256};
     std::vector<int> chunks;
     if (lat->chunk_pin >= 0) chunks.push_back(lat->chunk_pin);
     else chunks = {kDefaultChunk, 8, 16, 64};
     std::vector<double> t(3 * chunks.size(), 0.0);
-    auto pair = [&](int bs) -> int {
-        MultCall c1 = mult_call(prec, M_HOPINV, 1, buf + sb, buf, nullptr, 0.0);
-        c1.bs = bs;
-        if (int r = launch_mult(lat, c1)) return r;
-        MultCall c2 = mult_call(prec, M_DHAT, 0, buf + 2 * sb, buf + sb, buf, -lat->kappa * lat->kappa);
-        c2.bs = bs;
-        c2.red = R_DOT;
-        c2.aux = buf;
-        c2.red_to = RedTarget{lat->sys.partials, (double *)(buf + 3 * sb)};
-        return launch_mult(lat, c2);
+    size_t best = 2;
+    int caps[2] = {default_wave_cap(prec), default_wave_cap(prec)};
+    // which: 3 = the pair, 1 = the MULT alone, 2 = the D-hat half alone
+    auto pair = [&](int bs, int which) -> int {
+        if (which & 1) {
+            MultCall c1 = mult_call(prec, M_HOPINV, 1, buf + sb, buf, nullptr, 0.0);
+            c1.bs = bs;
+            if (int r = launch_mult(lat, c1)) return r;
+        }
+        if (which & 2) {
+            MultCall c2 = mult_call(prec, M_DHAT, 0, buf + 2 * sb, buf + sb, buf, -lat->kappa * lat->kappa);
+            c2.bs = bs;
+            c2.red = R_DOT;
+            c2.aux = buf;
+            c2.red_to = RedTarget{lat->sys.partials, (double *)(buf + 3 * sb)};
+            if (int r = launch_mult(lat, c2)) return r;
+        }
+        return WC_OK;
     };
-    auto timed = [&](int bs, int reps, double *ms) -> int {
+    auto timed = [&](int bs, int reps, double *ms, int which = 3) -> int {
         for (int w = 0; w < 2; w++)
-            if (int r = pair(bs)) return r;
+            if (int r = pair(bs, which)) return r;
         WC_HIP(hipEventRecord(e0, lat->stream));
         for (int r = 0; r < reps; r++)
-            if (int q = pair(bs)) return q;
+            if (int q = pair(bs, which)) return q;
         WC_HIP(hipEventRecord(e1, lat->stream));
         WC_HIP(hipEventSynchronize(e1));
         float f = 0.f;
@@ -871,8 +890,33 @@ int tune_block_size(wc_lattice *lat, int prec, double us[3], int *chosen) {
             lat->chunk_force = chunks[h];
             for (int c = 0; c < 3 && !rc; c++) rc = timed(cand[c], reps, &t[3 * h + c]);
         }
+        if (rc) break;
+        // start from 256 threads at the first chunk; another shape must win by 3%
+        for (size_t k = 0; k < t.size(); k++)
+            if (t[k] < 0.97 * t[best]) best = k;
+        // the wave cap of each kernel class at that shape
+        if (lat->wave_cap[prec] >= 0 || lat->lds_per_cu <= 0) break;
+        lat->chunk_force = chunks[best / 3];
+        const int bsb = cand[best % 3];
+        const int def = default_wave_cap(prec);
+        double tk[2];
+        lat->cap_force = def;
+        for (int j = 0; j < 2 && !rc; j++) rc = timed(bsb, reps, &tk[j], j + 1);
+        for (int cap : {0, 8, 12}) {
+            if (cap == def || rc) continue;
+            lat->cap_force = cap;
+            for (int j = 0; j < 2 && !rc; j++) {
+                double tc = 0;
+                rc = timed(bsb, reps, &tc, j + 1);
+                if (!rc && tc < 0.97 * tk[j]) {
+                    tk[j] = tc;
+                    caps[j] = cap;
+                }
+            }
+        }
     } while (false);
     lat->chunk_force = -1;
+    lat->cap_force = -1;
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     (void)hipStreamSynchronize(lat->stream);
@@ -880,20 +924,20 @@ int tune_block_size(wc_lattice *lat, int prec, double us[3], int *chosen) {
     lat->timing = timing;
     lat->dslash_count = dcount;
     if (rc) return rc;
-    // start from 256 threads at the first chunk; another shape must win by 3%
-    size_t best = 2;
-    for (size_t k = 0; k < t.size(); k++)
-        if (t[k] < 0.97 * t[best]) best = k;
     const size_t h = best / 3;
     lat->bs_tuned[prec] = cand[best % 3];
     lat->chunk_tuned[prec] = chunks[h];
+    if (lat->wave_cap[prec] < 0) {
+        lat->cap_tuned[prec][0] = caps[0];
+        lat->cap_tuned[prec][1] = caps[1];
+    }
     lat->gen++;  // captured graphs hold the old launch shape
     double u[3];
     for (int c = 0; c < 3; c++) u[c] = t[3 * h + c] * 1e3;
     if (us)
         for (int c = 0; c < 3; c++) us[c] = u[c];
     if (chosen) *chosen = cand[best % 3];
-    if (lat->chunk_pin < 0) tune_store(key, cand[best % 3], chunks[h], u);
+    if (lat->chunk_pin < 0) tune_store(key, cand[best % 3], chunks[h], caps, u);
     return WC_OK;
 }
 
@@ -935,21 +979,21 @@ extern "C" int wc_xcd_chunk(const wc_lattice *lat, int prec) {
 extern "C" int wc_set_wave_cap(wc_lattice *lat, int prec, int waves_per_cu) {
     if (!lat) return wc_fail(WC_EINVAL, "null lattice");
     if (int rc = check_prec(prec)) return rc;
-    if (!(waves_per_cu == -1 || waves_per_cu == 0 ||
-          (waves_per_cu >= 4 && waves_per_cu <= 16 && waves_per_cu % 4 == 0)))
+    if (waves_per_cu != -1 && !valid_wave_cap(waves_per_cu))
         return wc_fail(WC_EINVAL, "waves per CU must be -1 (default), 0 (no cap), 4, 8, 12 or 16");
     if (waves_per_cu != lat->wave_cap[prec]) {
         lat->gen++;  // recorded graphs hold the old launch shape
         lat->bs_tuned[prec] = 0;  // the tuned shape was timed under the old cap
         lat->chunk_tuned[prec] = -1;
+        lat->cap_tuned[prec][0] = lat->cap_tuned[prec][1] = -1;
     }
     lat->wave_cap[prec] = waves_per_cu;
     return WC_OK;
 }
 
-extern "C" int wc_wave_cap(const wc_lattice *lat, int prec) {
+extern "C" int wc_wave_cap(const wc_lattice *lat, int prec, int dhat) {
     if (!lat || prec < 0 || prec > 2) return -2;
-    return lat->lds_per_cu > 0 ? wave_cap_for(lat, prec) : 0;
+    return lat->lds_per_cu > 0 ? wave_cap_for(lat, prec, dhat ? M_DHAT : M_HOPINV) : 0;
 }
 
 extern "C" int wc_block_size(const wc_lattice *lat, int prec) {

@@ -1037,7 +1037,7 @@ int launch_mult_batch(hipStream_t s, const MultCall *calls, int n, wc_lattice *t
             t.parts.push_back(op);
         }
     }
-    const unsigned lds = B.h.interleave ? 0u : cap_lds_bytes(c0.lat, c0.prec, bs);
+    const unsigned lds = B.h.interleave ? 0u : cap_lds_bytes(c0.lat, c0.prec, bs, c0.mode);
     if (c0.prec == P64) dispatch_mode<P64>(B, c0.mode, c0.red, blocks, bs, lds, s, 12);
     else if (c0.prec == P32) dispatch_mode<P32>(B, c0.mode, c0.red, blocks, bs, lds, s, lr);
     else dispatch_mode<P16>(B, c0.mode, c0.red, blocks, bs, lds, s, 12);

@@ -178,10 +178,14 @@ struct wc_lattice {
     int chunk_pin = -1;
     int chunk_tuned[3] = {-1, -1, -1};
     int chunk_force = -1;  // set by the tuner while it times a candidate
-    // waves per CU that the one-system stencils are held to, per precision
-    // (0: no cap, -1: the precision's default, wave_cap_for), and the LDS
-    // bytes per CU of the device, through which the cap is applied
+    // waves per CU that the one-system stencils are held to, per precision:
+    // pinned by the caller (>= 0; 0 = no cap), else tuned per kernel class
+    // ([0]: MULT and the other stencils, [1]: the D-hat half) with the block
+    // size, else the precision's default (wave_cap_for); the LDS bytes per CU
+    // of the device, through which the cap is applied
     int wave_cap[3] = {-1, -1, -1};
+    int cap_tuned[3][2] = {{-1, -1}, {-1, -1}, {-1, -1}};
+    int cap_force = -1;  // set by the tuner while it times a candidate
     int lds_per_cu = 0;
 
     // gauge links per precision: 8 slabs ([mu][parity]) of link_slab_bytes
@@ -248,31 +252,6 @@ inline int lattice_chunk(const wc_lattice *lat, int prec) {
     if (lat->chunk_pin >= 0) return lat->chunk_pin;
     const int t = lat->chunk_tuned[prec];
     return t >= 0 ? t : kDefaultChunk;
-}
-
-// The FP64 stencil (140-196 VGPRs) runs 3 workgroups of 256 threads per CU
-// when left alone; held to 2 (8 waves per CU) its L2 keeps more of the
-// neighbours that the resident waves share, and MULT and D-hat run 10-11%
-// faster at 32^3x64 and 48^3x96.  The FP32 and FP16 stencils lose time under
-// any cap, so they have none by default.
-constexpr int kDefaultWaveCap64 = 8;
-inline int wave_cap_for(const wc_lattice *lat, int prec) {
-    const int c = lat->wave_cap[prec];
-    return c >= 0 ? c : (prec == P64 ? kDefaultWaveCap64 : 0);
-}
-// Dynamic LDS bytes per workgroup that leave room for exactly b = cap / (bs / 64)
-// workgroups of bs threads on a CU (0 = no cap).  A workgroup's allocation
-// must lie in (L / (b + 1), L / b] for L bytes of LDS per CU; the bytes are
-// taken from the middle of that window, less the kernel's own few bytes of
-// LDS, so that rounding up to the allocation granule keeps them inside it.
-inline unsigned cap_lds_bytes(const wc_lattice *lat, int prec, int bs) {
-    const int cap = wave_cap_for(lat, prec);
-    const int L = lat->lds_per_cu;
-    if (cap <= 0 || L <= 0) return 0;
-    int blocks = cap / (bs / 64);
-    if (blocks < 1) blocks = 1;
-    const int per = (L / blocks + L / (blocks + 1)) / 2 / 128 * 128 - 128;
-    return per > 0 ? (unsigned)per : 0u;
 }
 
 inline int lattice_bs(const wc_lattice *lat, int prec) {
@@ -356,6 +335,36 @@ int launch_fin_batch(hipStream_t s, const FinArgs *f, int n, int nvals);
 // ---------------------------------------------------------------------------
 enum MultMode { M_HOPINV = 0, M_DHAT = 1, M_DFULL = 2, M_INVSRC = 3, M_HOP = 4, M_CLOV = 5 };
 enum MultRed { R_NONE = 0, R_DOT = 1, R_DOTNORM = 2 };
+
+// The FP64 stencil (140-196 VGPRs) runs 3 workgroups of 256 threads per CU
+// when left alone; held to 2 (8 waves per CU) its L2 keeps more of the
+// neighbours that the resident waves share, and MULT and D-hat run 10-11%
+// faster at 32^3x64 and 48^3x96.  The FP32 and FP16 stencils have no cap
+// unless the tuner finds one that pays on the lattice at hand.
+constexpr int kDefaultWaveCap64 = 8;
+inline int cap_class(int mode) { return mode == M_DHAT ? 1 : 0; }
+inline bool valid_wave_cap(int w) { return w == 0 || (w >= 4 && w <= 16 && w % 4 == 0); }
+inline int default_wave_cap(int prec) { return prec == P64 ? kDefaultWaveCap64 : 0; }
+inline int wave_cap_for(const wc_lattice *lat, int prec, int mode = M_HOPINV) {
+    if (lat->cap_force >= 0) return lat->cap_force;
+    if (lat->wave_cap[prec] >= 0) return lat->wave_cap[prec];
+    const int t = lat->cap_tuned[prec][cap_class(mode)];
+    return t >= 0 ? t : default_wave_cap(prec);
+}
+// Dynamic LDS bytes per workgroup that leave room for exactly b = cap / (bs / 64)
+// workgroups of bs threads on a CU (0 = no cap).  A workgroup's allocation
+// must lie in (L / (b + 1), L / b] for L bytes of LDS per CU; the bytes are
+// taken from the middle of that window, less the kernel's own few bytes of
+// LDS, so that rounding up to the allocation granule keeps them inside it.
+inline unsigned cap_lds_bytes(const wc_lattice *lat, int prec, int bs, int mode = M_HOPINV) {
+    const int cap = wave_cap_for(lat, prec, mode);
+    const int L = lat->lds_per_cu;
+    if (cap <= 0 || L <= 0) return 0;
+    int blocks = cap / (bs / 64);
+    if (blocks < 1) blocks = 1;
+    const int per = (L / blocks + L / (blocks + 1)) / 2 / 128 * 128 - 128;
+    return per > 0 ? (unsigned)per : 0u;
+}
 
 struct MultCall {
     wc_lattice *lat;

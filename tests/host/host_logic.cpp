@@ -58,6 +58,28 @@ int main() {
             printf("wave cap defaults wrong\n");
             return 1;
         }
+        // tuned per kernel class; a pinned cap and the tuner's forced one take precedence
+        lat->cap_tuned[P32][1] = 12;
+        lat->cap_tuned[P64][0] = 0;
+        if (wave_cap_for(lat, P32, M_DHAT) != 12 || wave_cap_for(lat, P32, M_HOPINV) != 0 ||
+            wave_cap_for(lat, P32, M_DFULL) != 0 || wave_cap_for(lat, P64, M_HOPINV) != 0 ||
+            wave_cap_for(lat, P64, M_DHAT) != 8) {
+            printf("tuned wave caps wrong\n");
+            return 1;
+        }
+        lat->wave_cap[P32] = 4;
+        if (wave_cap_for(lat, P32, M_DHAT) != 4) {
+            printf("a pinned cap must win over the tuned one\n");
+            return 1;
+        }
+        lat->cap_force = 16;
+        if (wave_cap_for(lat, P32, M_DHAT) != 16 || wave_cap_for(lat, P64, M_HOPINV) != 16) {
+            printf("the tuner's forced cap must win\n");
+            return 1;
+        }
+        lat->cap_force = -1;
+        lat->wave_cap[P32] = -1;
+        lat->cap_tuned[P32][1] = lat->cap_tuned[P64][0] = -1;
         for (int lds : {163840}) {
             lat->lds_per_cu = lds;
             for (int cap : {4, 8, 12, 16})

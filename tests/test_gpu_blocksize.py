@@ -221,15 +221,16 @@ def test_tuner_cache_file(tmp_path):
         r1 = lat.tune_block_size(wc.FP16)
         lines = path.read_text().splitlines()
         say(lines)
-        assert len(lines) == 1 and lines[0].startswith("wc-tune-v2 ")
+        assert len(lines) == 1 and lines[0].startswith("wc-tune-v3 ")
         f = lines[0].split()
-        # wc-tune-v2 arch CUs Lx Ly Lz Lt prec recon wave-cap threads chunk us64 us128 us256
+        # wc-tune-v3 arch CUs Lx Ly Lz Lt prec recon pinned-cap threads chunk cap-mult cap-dhat us64 us128 us256
         assert [int(v) for v in f[3:7]] == list(dims) and int(f[7]) == wc.FP16 and int(f[8]) == 12
-        assert int(f[9]) == lat.wave_cap(wc.FP16) == 0
+        assert int(f[9]) == -1
         assert int(f[10]) == r1["threads"] and int(f[11]) == r1["chunk"]
+        assert int(f[12]) == r1["wave_cap"]["mult"] and int(f[13]) == r1["wave_cap"]["dhat"]
         lat2, _ = lattice(dims, 1070, kappa)
         r2 = lat2.tune_block_size(wc.FP16)
-        assert r2["threads"] == r1["threads"] and r2["chunk"] == r1["chunk"]
+        assert r2["threads"] == r1["threads"] and r2["chunk"] == r1["chunk"] and r2["wave_cap"] == r1["wave_cap"]
         assert all(abs(r2["us_per_pair"][k] - round(r1["us_per_pair"][k], 3)) < 1e-9 for k in (64, 128, 256))
         assert len(path.read_text().splitlines()) == 1
         lat.close()

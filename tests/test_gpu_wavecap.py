@@ -63,13 +63,14 @@ def test_defaults_and_settings():
     caps = (lat.wave_cap(wc.FP64), lat.wave_cap(wc.FP32), lat.wave_cap(wc.FP16))
     say("default caps", caps)
     assert caps == (8, 0, 0)
+    assert lat.wave_cap(wc.FP64, dhat=True) == 8 and lat.wave_cap(wc.FP32, dhat=True) == 0
     for bad in (-2, 1, 2, 3, 5, 20, 32, 64):
         with pytest.raises(wc.WCError):
             lat.set_wave_cap(wc.FP64, bad)
     with pytest.raises(wc.WCError):
         lat.set_wave_cap(3, 8)
     lat.set_wave_cap(wc.FP32, 12)
-    assert lat.wave_cap(wc.FP32) == 12 and lat.wave_cap(wc.FP64) == 8
+    assert lat.wave_cap(wc.FP32) == 12 and lat.wave_cap(wc.FP32, dhat=True) == 12 and lat.wave_cap(wc.FP64) == 8
     lat.set_wave_cap(wc.FP64, 0)
     assert lat.wave_cap(wc.FP64) == 0
     lat.set_wave_cap(wc.FP32, -1)
@@ -112,19 +113,44 @@ def test_results_identical_under_every_cap_and_block_size(prec):
         lat.set_wave_cap(prec, -1)
 
 
-def test_fp64_solve_under_no_cap_and_default_cap_agree():
+def test_fp64_solve_under_no_cap_and_tuned_cap_agree():
+    # the launch shape pinned, so that only the cap differs between the solves
     dims, kappa, csw = (6, 6, 6, 10), 0.13, 1.0
     lat, U, _ = setup(dims, kappa, csw)
     b = synth.gaussian_source(dims, 1820)
     xs = []
     try:
-        for cap in (0, -1):
+        lat.set_block_size(128)
+        lat.set_xcd_chunk(16)
+        for cap in (0, 12, -1):
             lat.set_wave_cap(wc.FP64, cap)
             x, info = lat.solve(dev(b), kappa, csw, 1e-12, inner_prec=wc.FP64)
-            say("cap", cap, "iterations", info["inner_iters_total"])
+            say("cap", cap, "->", lat.wave_cap(wc.FP64), lat.wave_cap(wc.FP64, dhat=True),
+                "iterations", info["inner_iters_total"])
             r, bn = oracle.residual(U, kappa, csw, b, host(x))
             assert r / bn < 1e-12
             xs.append(host(x))
-        assert np.array_equal(xs[0], xs[1])
+        assert np.array_equal(xs[0], xs[1]) and np.array_equal(xs[0], xs[2])
     finally:
         lat.set_wave_cap(wc.FP64, -1)
+        lat.set_block_size(0)
+        lat.set_xcd_chunk(-1)
+
+
+@pytest.mark.parametrize("prec", [wc.FP64, wc.FP32, wc.FP16])
+def test_tuner_picks_valid_caps_per_kernel_class(prec):
+    dims = (8, 8, 8, 16)
+    U = synth.random_links(dims, 0.3, 1830)
+    lat = wc.Lattice(dims)
+    lat.load_links(dev(U))
+    lat.build_clover(0.13, 1.0)
+    r = lat.tune_block_size(prec)
+    say("prec", prec, r)
+    for v in r["wave_cap"].values():
+        assert v in (0, 8, 12)
+    assert r["wave_cap"]["mult"] == lat.wave_cap(prec) and r["wave_cap"]["dhat"] == lat.wave_cap(prec, dhat=True)
+    # a pinned cap is not tuned
+    lat.set_wave_cap(prec, 16)
+    r = lat.tune_block_size(prec)
+    assert r["wave_cap"] == {"mult": 16, "dhat": 16}
+    lat.close()
