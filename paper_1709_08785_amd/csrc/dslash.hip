@@ -155,11 +155,12 @@ __device__ __forceinline__ void hop_dir(const MultKArgs &a, const SiteCoord &c, 
 // NT: links and clover read once per launch (one system) use non-temporal
 // loads; a launch that serves several systems on one lattice reads them
 // through the cache so that the blocks of the other systems hit in L2.
-// The one-system FP16 MULT and D-hat instances are held to at most 102 VGPRs,
-// which keeps five waves per SIMD instead of four: their loads carry half the
-// bytes of the FP32 stencil's, and the extra wave keeps more of them in flight
-// (MULT 88.2 -> 85.5 us at 32^3x64; six waves spill and lose 25%).  The other
-// instances would spill at five.
+// The one-system FP16 MULT and D-hat instances are held to 96 VGPRs (512 / 5,
+// rounded down to the allocation granule), which keeps five waves per SIMD
+// instead of four: their loads carry half the bytes of the FP32 stencil's,
+// and the extra wave keeps more of them in flight (MULT 88.2 -> 85.5 us at
+// 32^3x64; six waves spill and lose 25%).  The other instances would spill
+// at five.
 template <int P, int MODE, int RED, bool NT>
 constexpr int stencil_waves() {
     return (P == P16 && NT && (MODE == M_HOPINV || MODE == M_DHAT)) ? 5 : 1;
