@@ -47,7 +47,16 @@ def host(t):
 
 
 def rel(a, b):
-    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+    """Whole-field relative L2 error; the largest per-site relative error (each
+    site's 12 components against the reference site's norm, sites where the
+    reference is zero left out) is printed beside it."""
+    e = float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+    if a.ndim >= 2 and a.shape[-2:] == (4, 3):
+        d = np.linalg.norm((a - b).reshape(-1, 12), axis=1)
+        r = np.linalg.norm(b.reshape(-1, 12), axis=1)
+        m = r > 0
+        say("rel L2 err %.3e, max per-site rel err %.3e over %d sites" % (e, float(np.max(d[m] / r[m])), int(m.sum())))
+    return e
 
 
 _cache = {}
