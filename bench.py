@@ -34,11 +34,39 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def code_text(src: str) -> str:
+    """C/C++/HIP source without its comments, runs of whitespace made one space;
+    string and character literals are kept as they are."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        ch = src[i]
+        if ch in "\"'":
+            j = i + 1
+            while j < n and src[j] != ch:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        elif src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+            out.append(" ")
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(ch)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def source_hash() -> str:
+    """Hash of the kernel sources' code (comments and layout left out), which keys
+    the stored HBM counters: they stay valid while the compiled code is the same."""
     h = hashlib.sha256()
     for f in sorted(glob.glob(os.path.join(ROOT, "paper_1709_08785_amd", "csrc", "*"))):
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+        with open(f, encoding="utf-8") as fh:
+            h.update(os.path.basename(f).encode() + b"\0" + code_text(fh.read()).encode() + b"\0")
     return h.hexdigest()[:16]
 
 

@@ -152,10 +152,10 @@ WC_HD int pad_sites(int Vh) { return (Vh + kTile - 1) / kTile * kTile; }
 // neighbour that is read again two t-slices later is still in the
 // memory-side cache.  Blocks past the last whole window are split into one
 // slab per XCD; a ragged tail keeps its own index.
-// chunk: blocks per chunk (kXcdChunk for 256-site blocks; launches whose
-// blocks cover fewer sites take more blocks per chunk, so that a chunk keeps
-// covering the same stretch of the lattice).  chunk <= 0 gives one
-// contiguous slab of blocks per XCD.
+// chunk: blocks per chunk.  The stencil launches pass the lattice's chunk
+// (tuned, in 64-site tiles, converted to blocks of the launch); the default
+// kXcdChunk serves the one-launch inner loop, whose 256-site blocks then take
+// 64 tiles per chunk.  chunk <= 0 gives one contiguous slab of blocks per XCD.
 constexpr int kXcdChunk = 16;
 WC_HD int xcd_block(int b, int nb, int chunk = kXcdChunk) {
     if (chunk <= 0) chunk = nb;  // a window larger than the launch: slabs only

@@ -47,3 +47,23 @@ def test_traffic_is_null_for_other_sources_or_shapes(tmp_path, monkeypatch):
     assert bench.traffic_for("mult_hopinv_fp32", (32, 32, 32, 64), 12) is None
     monkeypatch.setattr(bench, "source_hash", lambda: "0000000000000000")
     assert bench.traffic_for("mult_dhat_fp32", (32, 32, 32, 64), 12) is None
+
+
+def test_source_hash_follows_code_not_comments(tmp_path, monkeypatch):
+    # the stored HBM counters are keyed by the kernel sources' code: editing a
+    # comment keeps the key, editing code changes it
+    assert bench.code_text('a // c\nb /* x\n y */ c "//s" \'/\' d') == 'a b c "//s" \'/\' d'
+    src = os.path.join(bench.ROOT, "paper_1709_08785_amd", "csrc")
+    dst = tmp_path / "paper_1709_08785_amd" / "csrc"
+    dst.mkdir(parents=True)
+    for name in sorted(os.listdir(src)):
+        if os.path.isfile(os.path.join(src, name)):
+            (dst / name).write_text(open(os.path.join(src, name), encoding="utf-8").read(), encoding="utf-8")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    h0 = bench.source_hash()
+    f = dst / "reduce.hpp"
+    text = f.read_text(encoding="utf-8")
+    f.write_text("// another comment\n" + text.replace("// ", "//  ") + "\n/* trailing */\n", encoding="utf-8")
+    assert bench.source_hash() == h0
+    f.write_text(text.replace("kBlock = 256", "kBlock = 128"), encoding="utf-8")
+    assert bench.source_hash() != h0
