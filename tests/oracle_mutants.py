@@ -71,6 +71,21 @@ MUTANTS = {
     "residual_zero": ("c", "r += creal(d) * creal(d) + cimag(d) * cimag(d);", "r += 0.0 * creal(d);"),
     "residual_drops_imag": ("c", "r += creal(d) * creal(d) + cimag(d) * cimag(d);", "r += creal(d) * creal(d);"),
     # storage format
+    # more gamma matrices, hops, solver updates and the residual
+    "gamma_x_sign": ("c", "if (k == 0) { s[0][1] = 1; s[1][0] = 1; }", "if (k == 0) { s[0][1] = -1; s[1][0] = -1; }"),
+    "gamma_z_sign": ("c", "if (k == 2) { s[0][0] = 1; s[1][1] = -1; }", "if (k == 2) { s[0][0] = -1; s[1][1] = 1; }"),
+    "gamma_t_sign": ("c", "g[0][0] = 1; g[1][1] = 1; g[2][2] = -1; g[3][3] = -1;",
+                     "g[0][0] = -1; g[1][1] = -1; g[2][2] = 1; g[3][3] = 1;"),
+    "gamma_spatial_i_swapped": ("c", "g[i][2 + j] = -I * s[i][j];\n                g[2 + i][j] = I * s[i][j];",
+                                "g[i][2 + j] = I * s[i][j];\n                g[2 + i][j] = -I * s[i][j];"),
+    "hop_forward_link_daggered": ("c", "memcpy(u, link(U, V, mu, n), sizeof(u));              /* U_mu(n)            */",
+                                  "m3_dag(link(U, V, mu, n), u);"),
+    "hop_directions_swapped": ("c", "long m = shifted(L, c, mu, dir == 0 ? +1 : -1);",
+                               "long m = shifted(L, c, mu, dir == 0 ? -1 : +1);"),
+    "bicgstab_x_update_drops_omega_s": ("c", "x[i] += alpha * p[i] + omega * s[i]; r[i] = s[i] - omega * t[i];",
+                                        "x[i] += alpha * p[i]; r[i] = s[i] - omega * t[i];"),
+    "residual_sign_of_D_x": ("c", "cplx d = b[n * 12 + i] - (a - kappa * h[i]);", "cplx d = b[n * 12 + i] + (a - kappa * h[i]);"),
+    "residual_hop_sign": ("c", "cplx d = b[n * 12 + i] - (a - kappa * h[i]);", "cplx d = b[n * 12 + i] - (a + kappa * h[i]);"),
     "fp16_scale_per_spin": ("py", "sites = re.reshape(re.shape[:-3] + (24,))", "sites = re.reshape(re.shape[:-2] + (6,))"),
 }
 
