@@ -891,9 +891,13 @@ int tune_block_size(wc_lattice *lat, int prec, double us[3], int *chosen) {
             for (int c = 0; c < 3 && !rc; c++) rc = timed(cand[c], reps, &t[3 * h + c]);
         }
         if (rc) break;
-        // start from 256 threads at the first chunk; another shape must win by 3%
+        // start from 256 threads (or the pinned size) at the first chunk;
+        // another shape must win by 3%.  A pinned block size is the only one
+        // the choice of chunk and caps considers.
+        const int pin = lat->bs_pin;
+        if (pin) best = pin == 64 ? 0 : pin == 128 ? 1 : 2;
         for (size_t k = 0; k < t.size(); k++)
-            if (t[k] < 0.97 * t[best]) best = k;
+            if ((!pin || cand[k % 3] == pin) && t[k] < 0.97 * t[best]) best = k;
         // the wave cap of each kernel class at that shape
         if (lat->wave_cap[prec] >= 0 || lat->lds_per_cu <= 0) break;
         lat->chunk_force = chunks[best / 3];

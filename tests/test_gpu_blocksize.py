@@ -237,3 +237,23 @@ def test_tuner_cache_file(tmp_path):
         lat2.close()
     finally:
         wc.set_tune_cache(None)
+
+
+def test_tuner_with_a_pinned_block_size_chooses_for_that_size():
+    dims, kappa = (16, 16, 16, 16), 0.13
+    lat, U = lattice(dims, 1071, kappa)
+    lat.set_block_size(64)
+    try:
+        res = lat.tune_block_size(wc.FP32)
+        say(res)
+        assert res["threads"] == 64 and lat.block_size(wc.FP32) == 64
+        assert res["chunk"] in (8, 16, 32, 64)
+        assert all(v in (0, 8, 12) for v in res["wave_cap"].values())
+        b = synth.gaussian_source(dims, 2071)
+        x, info = lat.solve(dev(b), kappa, 1.0, 1e-10)
+        assert info["block_size"] == 64
+        r, bn = oracle.residual(U, kappa, 1.0, b, host(x))
+        assert r / bn < 1e-10
+    finally:
+        lat.set_block_size(0)
+        lat.close()
