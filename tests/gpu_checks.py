@@ -40,6 +40,22 @@ def site_errors(out_sites, ref_sites, label=""):
     return l2, per_site
 
 
+def rel(a, b):
+    """Whole-field relative L2 error of a against b; for spinor fields (last axes
+    4 x 3) the largest per-site relative error (each site's 12 components against
+    the reference site's norm, sites where the reference is zero left out) is
+    printed beside it."""
+    a = np.asarray(a)
+    b = np.asarray(b)
+    e = float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+    if a.ndim >= 2 and a.shape[-2:] == (4, 3):
+        d = np.linalg.norm((a - b).reshape(-1, 12), axis=1)
+        r = np.linalg.norm(b.reshape(-1, 12), axis=1)
+        m = r > 0
+        say("rel L2 err %.3e, max per-site rel err %.3e over %d sites" % (e, float(np.max(d[m] / r[m])), int(m.sum())))
+    return e
+
+
 def check_true_residual(U, kappa, csw, b, x, info, tol, agree=1e-6):
     """Oracle residual of x below tol, and equal to the library's own to `agree`
     (relative) plus 1e-15.  Returns the oracle's relative residual."""

@@ -21,7 +21,7 @@ import oracle
 import synth
 
 sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
-from gpu_checks import check_true_residual  # noqa: E402
+from gpu_checks import check_true_residual, rel  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -44,19 +44,6 @@ def dev(a):
 
 def host(t):
     return t.detach().cpu().numpy()
-
-
-def rel(a, b):
-    """Whole-field relative L2 error; the largest per-site relative error (each
-    site's 12 components against the reference site's norm, sites where the
-    reference is zero left out) is printed beside it."""
-    e = float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
-    if a.ndim >= 2 and a.shape[-2:] == (4, 3):
-        d = np.linalg.norm((a - b).reshape(-1, 12), axis=1)
-        r = np.linalg.norm(b.reshape(-1, 12), axis=1)
-        m = r > 0
-        say("rel L2 err %.3e, max per-site rel err %.3e over %d sites" % (e, float(np.max(d[m] / r[m])), int(m.sum())))
-    return e
 
 
 _cache = {}

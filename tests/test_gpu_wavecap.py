@@ -19,7 +19,7 @@ import oracle
 import synth
 
 sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
-from gpu_checks import say  # noqa: E402
+from gpu_checks import rel, say  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -37,10 +37,6 @@ def dev(a):
 
 def host(t):
     return t.detach().cpu().numpy()
-
-
-def rel(a, b):
-    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
 
 
 _cache = {}
