@@ -361,7 +361,8 @@ def batch_mode(args):
     """Batched solves: (a) 12 spin-colour point sources on one 32^3x64 lattice,
     (b) one Gaussian source on each of 16^4, 24^3x48 and 32^3x64.  Each set is
     solved together (one launch per phase, chunk graphs) and, for comparison,
-    one system after another; FP32 inner / FP64 outer to true residual tol."""
+    one system after another; FP32 inner / FP64 outer to true residual tol,
+    and the point sources also with the FP16-storage inner solve."""
     import torch
 
     import paper_1709_08785_amd as wc
@@ -417,7 +418,20 @@ def batch_mode(args):
                     for k, v in st.items() if v["launches"]},
     }
     log("point sources:", json.dumps(out["point_sources_32x32x32x64"]))
-    del xs, singles, bs
+    # the same 12 sources with the FP16-storage inner solve (4 fields per thread),
+    # batched and one after another
+    lat.solve_batch(bs, kappa, csw, args.tol, inner_prec=wc.FP16)
+    (xs16, inf16), t_b16 = timed(lambda: lat.solve_batch(bs, kappa, csw, args.tol, inner_prec=wc.FP16))
+    lat.solve(bs[0], kappa, csw, args.tol, inner_prec=wc.FP16)
+    _, t_s16 = timed(lambda: [lat.solve(b, kappa, csw, args.tol, inner_prec=wc.FP16) for b in bs])
+    out["point_sources_32x32x32x64_fp16_inner"] = {
+        "batched_s": round(t_b16, 4), "sequential_s": round(t_s16, 4), "speedup": round(t_s16 / t_b16, 3),
+        "fields_per_thread": lat.multi_rhs(wc.FP16), "vs_fp32_batched": round(t_batch / t_b16, 3),
+        "max_true_rel_residual": max(i["true_rel_residual"] for i in inf16),
+        "inner_iters": [i["inner_iters_total"] for i in inf16],
+    }
+    log("point sources, FP16 inner:", json.dumps(out["point_sources_32x32x32x64_fp16_inner"]))
+    del xs, xs16, singles, bs
     lat.close()
     torch.cuda.empty_cache()
 
