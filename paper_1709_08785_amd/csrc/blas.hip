@@ -394,6 +394,9 @@ template <int N> __global__ __launch_bounds__(kBlock) void k_finalize(FinBatch B
     double a[N];
 #pragma unroll
     for (int k = 0; k < N; k++) a[k] = 0.0;
+    // unrolled so that the loads of several partials are in flight at once;
+    // the sums keep their order, so the result does not change
+#pragma unroll 8
     for (int j = threadIdx.x; j < f.blocks; j += kBlock) {
 #pragma unroll
         for (int k = 0; k < N; k++) a[k] += f.partials[(size_t)k * f.blocks + j];
