@@ -303,6 +303,19 @@ template <> struct SpinorIO<P32> {
 // FP16 storage: planes of uint4 (3 * 16 B) followed by a float scale plane at 48
 template <> struct SpinorIO<P16> {
     using R = float;
+    // stored values without their site scale, from the three stored planes
+    __device__ static Spinor<R> decode(const uint4 (&v)[3]) {
+        Spinor<R> out;
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            const float2 a = h2f(v[k].x), b = h2f(v[k].y), c = h2f(v[k].z), d = h2f(v[k].w);
+            out.c[4 * k + 0] = {a.x, a.y};
+            out.c[4 * k + 1] = {b.x, b.y};
+            out.c[4 * k + 2] = {c.x, c.y};
+            out.c[4 * k + 3] = {d.x, d.y};
+        }
+        return out;
+    }
     // stored values without their site scale, and the scale
     __device__ static Spinor<R> load_raw(const void *base, int Vh, int i, float &s) {
         s = *tp<float, 52>(base, i, 48);
@@ -404,6 +417,10 @@ template <> struct LinkIO<P16> {
     template <bool NT = true> __device__ static Mat3<R> load(const void *slab, int Vh, int i) {
         uint4 a = ld_op<NT>(tp<uint4, 24>(slab, i, 0));
         uint2 b = ld_op<NT>(tp<uint2, 24>(slab, i, 16));
+        return decode(a, b);
+    }
+    // the link from its two stored planes
+    __device__ static Mat3<R> decode(uint4 a, uint2 b) {
         float2 v0 = h2f(a.x), v1 = h2f(a.y), v2 = h2f(a.z), v3 = h2f(a.w), v4 = h2f(b.x), v5 = h2f(b.y);
         // convert each half once: left to itself the compiler folds the
         // conversion into every product as a mixed-precision FMA, which issues

@@ -139,6 +139,31 @@ __device__ __forceinline__ void hop_dir(const MultKArgs &a, const SiteCoord &c, 
                                         Spinor<typename Real<P>::T> &acc) {
     using R = typename Real<P>::T;
     const int Vh = a.g.Vh;
+    if constexpr (P == P16) {
+        // FP16 storage: every load of both hops is issued before the first
+        // conversion.  Its loads are small (half the bytes of FP32), and with
+        // one hop's loads in flight at a time the waves waited on latency;
+        // two hops' loads in flight took the MULT from 86.6-87.9 to 83.9-84.7
+        // us at 32^3x64, with results bit for bit the same.
+        const int nf = eo_neighbour(a.g, c, MU, +1);
+        const int nb = eo_neighbour(a.g, c, MU, -1);
+        const char *lf = a.links + (size_t)(2 * MU + a.out_par) * a.link_slab;
+        const char *lk = a.links + (size_t)(2 * MU + 1 - a.out_par) * a.link_slab;
+        const uint4 fa = ld_op<NT>(tp<uint4, 24>(lf, i, 0));
+        const uint2 fb = ld_op<NT>(tp<uint2, 24>(lf, i, 16));
+        const uint4 ba = ld_op<NT>(tp<uint4, 24>(lk, nb, 0));
+        const uint2 bb = ld_op<NT>(tp<uint2, 24>(lk, nb, 16));
+        uint4 sf[3], sb[3];
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            sf[k] = *tp<uint4, 52>(a.in, nf, 16 * k);
+            sb[k] = *tp<uint4, 52>(a.in, nb, 16 * k);
+        }
+        const float scf = *tp<float, 52>(a.in, nf, 48), scb = *tp<float, 52>(a.in, nb, 48);
+        hop_term<R, MU, true, true>(SpinorIO<P16>::decode(sf), LinkIO<P16>::decode(fa, fb), acc, scf);
+        hop_term<R, MU, false, true>(SpinorIO<P16>::decode(sb), LinkIO<P16>::decode(ba, bb), acc, scb);
+        return;
+    }
     {
         const int nf = eo_neighbour(a.g, c, MU, +1);
         const Mat3<R> U = LinkLoad<P, LR>::template load<NT>(a.links + (size_t)(2 * MU + a.out_par) * a.link_slab, Vh, i);
@@ -155,15 +180,14 @@ __device__ __forceinline__ void hop_dir(const MultKArgs &a, const SiteCoord &c, 
 // NT: links and clover read once per launch (one system) use non-temporal
 // loads; a launch that serves several systems on one lattice reads them
 // through the cache so that the blocks of the other systems hit in L2.
-// The one-system FP16 MULT and D-hat instances are held to 96 VGPRs (512 / 5,
-// rounded down to the allocation granule), which keeps five waves per SIMD
-// instead of four: their loads carry half the bytes of the FP32 stencil's,
-// and the extra wave keeps more of them in flight (MULT 88.2 -> 85.5 us at
-// 32^3x64; six waves spill and lose 25%).  The other instances would spill
-// at five.
+// The one-system FP16 MULT and D-hat instances are held to four waves per
+// SIMD (128 VGPRs; they use about 103 with both hops' loads in flight, hop_dir).
+// Five waves at 96 VGPRs helped the form with one hop's loads in flight
+// (MULT 88.2 -> 85.5 us at 32^3x64), but with two hops' loads it spills and
+// runs at 100.7 us; four waves with two hops' loads run at 83.9-84.7 us.
 template <int P, int MODE, int RED, bool NT>
 constexpr int stencil_waves() {
-    return (P == P16 && NT && (MODE == M_HOPINV || MODE == M_DHAT)) ? 5 : 1;
+    return (P == P16 && NT && (MODE == M_HOPINV || MODE == M_DHAT)) ? 4 : 1;
 }
 template <int P, int MODE, int RED, bool NT, int LR>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(stencil_waves<P, MODE, RED, NT>())))
