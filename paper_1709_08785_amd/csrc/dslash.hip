@@ -164,6 +164,23 @@ __device__ __forceinline__ void hop_dir(const MultKArgs &a, const SiteCoord &c, 
         hop_term<R, MU, false, true>(SpinorIO<P16>::decode(sb), LinkIO<P16>::decode(ba, bb), acc, scb);
         return;
     }
+    if constexpr (P == P32 && LR == 8) {
+        // reconstruct-8 links: both hops' links and spinors are loaded before
+        // either hop is computed, so the loads overlap the rebuild of the
+        // links (MULT 144.2 -> 140.3 us, D-hat half 154.8 -> 147.3 us at
+        // 32^3x64, bit for bit the same).  The two-column and full forms
+        // gain nothing from it and keep the one-hop order.
+        const int nf = eo_neighbour(a.g, c, MU, +1);
+        const int nb = eo_neighbour(a.g, c, MU, -1);
+        const Mat3<R> Uf = LinkLoad<P, LR>::template load<NT>(a.links + (size_t)(2 * MU + a.out_par) * a.link_slab, Vh, i);
+        const Mat3<R> Ub =
+            LinkLoad<P, LR>::template load<NT>(a.links + (size_t)(2 * MU + 1 - a.out_par) * a.link_slab, Vh, nb);
+        const Spinor<R> pf = SpinorIO<P32>::load(a.in, Vh, nf);
+        const Spinor<R> pb = SpinorIO<P32>::load(a.in, Vh, nb);
+        hop_term<R, MU, true, false>(pf, Uf, acc, R(1));
+        hop_term<R, MU, false, false>(pb, Ub, acc, R(1));
+        return;
+    }
     {
         const int nf = eo_neighbour(a.g, c, MU, +1);
         const Mat3<R> U = LinkLoad<P, LR>::template load<NT>(a.links + (size_t)(2 * MU + a.out_par) * a.link_slab, Vh, i);
@@ -185,12 +202,14 @@ __device__ __forceinline__ void hop_dir(const MultKArgs &a, const SiteCoord &c, 
 // Five waves at 96 VGPRs helped the form with one hop's loads in flight
 // (MULT 88.2 -> 85.5 us at 32^3x64), but with two hops' loads it spills and
 // runs at 100.7 us; four waves with two hops' loads run at 83.9-84.7 us.
-template <int P, int MODE, int RED, bool NT>
+// The reconstruct-8 FP32 instances, with both hops' loads in flight, are held
+// to four waves per SIMD in the same way (118-120 VGPRs).
+template <int P, int MODE, int RED, bool NT, int LR>
 constexpr int stencil_waves() {
-    return (P == P16 && NT && (MODE == M_HOPINV || MODE == M_DHAT)) ? 4 : 1;
+    return ((P == P16 || (P == P32 && LR == 8)) && NT && (MODE == M_HOPINV || MODE == M_DHAT)) ? 4 : 1;
 }
 template <int P, int MODE, int RED, bool NT, int LR>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(stencil_waves<P, MODE, RED, NT>())))
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(stencil_waves<P, MODE, RED, NT, LR>())))
 void k_mult(MultBatch B) {
     using R = typename Real<P>::T;
     int s, lb;
