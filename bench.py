@@ -745,8 +745,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the sharded design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(it runs one process's share of a lattice on one GPU); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -1,4 +1,4 @@
-"""Error paths of the C ABI on a GPU machine: every failure is reported through a
+"""Error paths of the C ABI on a GPU: every failure is reported through a
 status code (and wc_last_error), never by a hang or a fault.  Conditions are
 forced from the host (bad arguments, iteration caps, a non-finite source)."""
 import numpy as np
