@@ -153,7 +153,8 @@ void wc_solve_params_default(wc_solve_params *p);
    microseconds per pair for 64, 128, 256 at the chosen chunk under the
    default cap; *threads (may be NULL) the chosen block size.  With a tuning
    cache (wc_set_tune_cache) holding this case, the stored shape and caps are
-   taken without timing.
+   taken without timing; a tuning under a pinned block size or chunk neither
+   reads nor writes the cache.
    Needs links and clover (WC_ENOTREADY).  Allocates three vectors of the
    precision for the duration of the call and synchronises the stream. */
 int wc_set_block_size(wc_lattice *lat, int threads);
@@ -213,8 +214,10 @@ int wc_wave_cap(const wc_lattice *lat, int prec, int dhat);
 
 /* Process-wide file in which the launch-shape tuner keeps its results, one
    line per device (architecture and compute units), lattice extents,
-   precision, FP32 link form and pinned wave cap (wc_set_wave_cap); a later tuning of the same case, in this
-   process or another, takes the stored shape instead of timing.  path NULL or
+   precision, FP32 link form and pinned wave cap (wc_set_wave_cap); a later
+   tuning of the same case, in this process or another, takes the stored
+   shape instead of timing.  Tunings under a pinned block size or XCD chunk
+   do not use the file.  path NULL or
    "" (the default) keeps no file.  A file that cannot be read or written only
    costs a new timing.  The path is copied. */
 int wc_set_tune_cache(const char *path);

@@ -808,11 +808,15 @@ static void tune_store(const std::string &key, int bs, int chunk, const int caps
 // 12 waves per CU, and each keeps the cap that beats the precision's default
 // by 3%.  With a cache file set, a stored result for the same device,
 // lattice, precision, link form and pinned cap is taken instead of timing.
+// A pinned block size or chunk bypasses the file both ways: a stored shape was
+// chosen over every size and chunk, and a constrained choice must not be
+// handed to a later, unconstrained tuning.
 int tune_block_size(wc_lattice *lat, int prec, double us[3], int *chosen) {
     if (!lat->have_links || !lat->have_clover)
         return wc_fail(WC_ENOTREADY, "block-size tuning needs links and clover");
     const std::string key = tune_key(lat, prec);
-    {
+    const bool use_cache = !lat->bs_pin && lat->chunk_pin < 0;
+    if (use_cache) {
         int b = 0, c = -1, w[2] = {-1, -1};
         double u[3];
         if (tune_lookup(key, &b, &c, w, u)) {
@@ -941,7 +945,7 @@ int tune_block_size(wc_lattice *lat, int prec, double us[3], int *chosen) {
     if (us)
         for (int c = 0; c < 3; c++) us[c] = u[c];
     if (chosen) *chosen = cand[best % 3];
-    if (lat->chunk_pin < 0) tune_store(key, cand[best % 3], chunks[h], caps, u);
+    if (use_cache) tune_store(key, cand[best % 3], chunks[h], caps, u);
     return WC_OK;
 }
 

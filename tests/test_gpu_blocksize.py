@@ -239,6 +239,38 @@ def test_tuner_cache_file(tmp_path):
         wc.set_tune_cache(None)
 
 
+def test_tuner_cache_bypassed_under_a_pinned_shape(tmp_path):
+    # a tuning under a pinned block size or chunk neither writes the cache file
+    # nor takes a stored shape from it
+    dims, kappa = (8, 8, 8, 16), 0.13
+    path = tmp_path / "tune.txt"
+    wc.set_tune_cache(str(path))
+    lat, U = lattice(dims, 1072, kappa)
+    try:
+        lat.set_block_size(64)
+        r0 = lat.tune_block_size(wc.FP32)
+        assert r0["threads"] == 64
+        assert not path.exists() or path.read_text() == ""
+        lat.set_block_size(0)
+        r1 = lat.tune_block_size(wc.FP32)
+        assert len(path.read_text().splitlines()) == 1
+        other = 128 if r1["threads"] != 128 else 64
+        lat.set_block_size(other)
+        r2 = lat.tune_block_size(wc.FP32)
+        say(r1, r2)
+        assert r2["threads"] == other and lat.block_size(wc.FP32) == other
+        lat.set_block_size(0)
+        lat.set_xcd_chunk(16)
+        r3 = lat.tune_block_size(wc.FP32)
+        assert r3["chunk"] == 16
+        assert len(path.read_text().splitlines()) == 1
+    finally:
+        lat.set_block_size(0)
+        lat.set_xcd_chunk(-1)
+        lat.close()
+        wc.set_tune_cache(None)
+
+
 def test_tuner_with_a_pinned_block_size_chooses_for_that_size():
     dims, kappa = (16, 16, 16, 16), 0.13
     lat, U = lattice(dims, 1071, kappa)

@@ -74,19 +74,23 @@ def test_defaults_and_settings():
     assert lat.wave_cap(wc.FP64) == 8 and lat.wave_cap(wc.FP32) == 0
 
 
-@pytest.mark.parametrize("prec", [wc.FP64, wc.FP32, wc.FP16])
-def test_results_identical_under_every_cap_and_block_size(prec):
+@pytest.mark.parametrize("prec,recon", [(wc.FP64, 12), (wc.FP32, 12), (wc.FP32, 8), (wc.FP32, 18),
+                                        (wc.FP16, 12)])
+def test_results_identical_under_every_cap_and_block_size(prec, recon):
+    # FP32 in each link form: the reconstruct-8 stencil loads both hops of a
+    # direction before rebuilding either link, at four waves per SIMD
     dims, kappa = (6, 6, 6, 10), 0.13
     lat, U, Finv = setup(dims, kappa)
     psi = synth.gaussian_source(dims, 1810)
-    eo = lat.pack(dev(psi), prec)
     try:
+        lat.set_link_recon(recon)
+        eo = lat.pack(dev(psi), prec)
         for bs in (64, 128, 256):
             lat.set_block_size(bs)
             ref = None
             for cap in (0, 4, 8, 12, 16, -1):
                 lat.set_wave_cap(prec, cap)
-                say("prec", prec, "threads", bs, "cap", cap, "->", lat.wave_cap(prec))
+                say("prec", prec, "links", recon, "threads", bs, "cap", cap, "->", lat.wave_cap(prec))
                 m = lat.new_eo(prec, 2)
                 lat.apply_mult(lat.parity_view(m, 0, prec), lat.parity_view(eo, 1, prec), 0, prec)
                 lat.apply_mult(lat.parity_view(m, 1, prec), lat.parity_view(eo, 0, prec), 1, prec)
@@ -107,6 +111,7 @@ def test_results_identical_under_every_cap_and_block_size(prec):
     finally:
         lat.set_block_size(0)
         lat.set_wave_cap(prec, -1)
+        lat.set_link_recon(12)
 
 
 def test_fp64_solve_under_no_cap_and_tuned_cap_agree():
