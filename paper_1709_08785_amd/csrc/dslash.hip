@@ -203,7 +203,7 @@ __device__ __forceinline__ void hop_dir(const MultKArgs &a, const SiteCoord &c, 
 // (MULT 88.2 -> 85.5 us at 32^3x64), but with two hops' loads it spills and
 // runs at 100.7 us; four waves with two hops' loads run at 83.9-84.7 us.
 // The reconstruct-8 FP32 instances, with both hops' loads in flight, are held
-// to four waves per SIMD in the same way (118-120 VGPRs).
+// to four waves per SIMD in the same way (118-122 VGPRs).
 template <int P, int MODE, int RED, bool NT, int LR>
 constexpr int stencil_waves() {
     return ((P == P16 || (P == P32 && LR == 8)) && NT && (MODE == M_HOPINV || MODE == M_DHAT)) ? 4 : 1;
