@@ -145,11 +145,12 @@ void wc_solve_params_default(wc_solve_params *p);
    zero vectors at 64, 128 and 256 threads and at XCD chunks of 8, 16, 32 and
    64 tiles (wc_set_xcd_chunk; only the pinned one when pinned) and keeps the
    fastest shape; 256 threads at chunk 32 are displaced only by a shape at
-   least 3% faster.  With a pinned block size, the chunk and caps are chosen
+   least 3% faster, in the sweep and again in three alternating timings
+   against it.  With a pinned block size, the chunk and caps are chosen
    for that size.  At that shape it then times the two kernels on their
    own under no cap and caps of 8 and 12 waves per CU (wc_set_wave_cap;
    skipped when pinned), and each kernel class keeps a cap only if it beats
-   the precision's default by 3%.  us_per_pair[3] (may be NULL) receives
+   the precision's default by 3%, confirmed in the same way.  us_per_pair[3] (may be NULL) receives
    microseconds per pair for 64, 128, 256 at the chosen chunk under the
    default cap; *threads (may be NULL) the chosen block size.  With a tuning
    cache (wc_set_tune_cache) holding this case, the stored shape and caps are

@@ -801,12 +801,13 @@ static void tune_store(const std::string &key, int bs, int chunk, const int caps
 // Time the inner loop's stencil pair (F_oo^-1 H_oe into the odd parity, then
 // the D-hat half with its fused dot) on zero vectors at each block size and
 // XCD chunk, and keep the fastest.  The default shape (256 threads, chunk
-// kDefaultChunk) is displaced only by a shape at least 3% faster, so that
-// timing noise does not flip the choice on large lattices.  A pinned chunk
+// kDefaultChunk) is displaced only by a shape at least 3% faster, in the sweep
+// and again in three alternating timings against it, so that timing noise
+// does not flip the choice on large lattices.  A pinned chunk
 // is the only one timed.  Then, unless the caller pinned a wave cap, the two
 // kernels are timed on their own at the chosen shape under caps of 0, 8 and
 // 12 waves per CU, and each keeps the cap that beats the precision's default
-// by 3%.  With a cache file set, a stored result for the same device,
+// by 3%, again confirmed by alternating timings.  With a cache file set, a stored result for the same device,
 // lattice, precision, link form and pinned cap is taken instead of timing.
 // A pinned block size or chunk bypasses the file both ways: a stored shape was
 // chosen over every size and chunk, and a constrained choice must not be
@@ -899,9 +900,40 @@ int tune_block_size(wc_lattice *lat, int prec, double us[3], int *chosen) {
         // another shape must win by 3%.  A pinned block size is the only one
         // the choice of chunk and caps considers.
         const int pin = lat->bs_pin;
-        if (pin) best = pin == 64 ? 0 : pin == 128 ? 1 : 2;
+        const size_t start = pin ? (pin == 64 ? 0 : pin == 128 ? 1 : 2) : 2;
+        best = start;
         for (size_t k = 0; k < t.size(); k++)
             if ((!pin || cand[k % 3] == pin) && t[k] < 0.97 * t[best]) best = k;
+        // One timing of about 2 ms can favour a shape by a few percent by
+        // chance, so a challenger is timed again against the starting shape,
+        // alternately, three times each, and keeps its place only if the
+        // better of its times still wins by 3%.
+        auto confirm = [&](auto run_a, auto run_b, bool *b_wins) -> int {
+            double ta = 1e30, tb = 1e30, m = 0;
+            for (int k = 0; k < 3; k++) {
+                if (int r = run_a(&m)) return r;
+                ta = std::min(ta, m);
+                if (int r = run_b(&m)) return r;
+                tb = std::min(tb, m);
+            }
+            *b_wins = tb < 0.97 * ta;
+            return WC_OK;
+        };
+        if (best != start) {
+            bool wins = false;
+            rc = confirm(
+                [&](double *m) {
+                    lat->chunk_force = chunks[start / 3];
+                    return timed(cand[start % 3], reps, m);
+                },
+                [&](double *m) {
+                    lat->chunk_force = chunks[best / 3];
+                    return timed(cand[best % 3], reps, m);
+                },
+                &wins);
+            if (rc) break;
+            if (!wins) best = start;
+        }
         // the wave cap of each kernel class at that shape
         if (lat->wave_cap[prec] >= 0 || lat->lds_per_cu <= 0) break;
         lat->chunk_force = chunks[best / 3];
@@ -921,6 +953,21 @@ int tune_block_size(wc_lattice *lat, int prec, double us[3], int *chosen) {
                     caps[j] = cap;
                 }
             }
+        }
+        for (int j = 0; j < 2 && !rc; j++) {
+            if (caps[j] == def) continue;
+            bool wins = false;
+            rc = confirm(
+                [&](double *m) {
+                    lat->cap_force = def;
+                    return timed(bsb, reps, m, j + 1);
+                },
+                [&](double *m) {
+                    lat->cap_force = caps[j];
+                    return timed(bsb, reps, m, j + 1);
+                },
+                &wins);
+            if (!rc && !wins) caps[j] = def;
         }
     } while (false);
     lat->chunk_force = -1;
