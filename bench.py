@@ -553,9 +553,12 @@ def precisions_mode(args):
         xh = x.cpu().numpy()
         r, bn = oracle.residual(U, kappa, csw, b, xh)
         xs[name] = xh
+        ip = kw["inner_prec"]
         res[name] = {"seconds": round(el, 4), "inner_iters": info["inner_iters_total"],
                      "outer_iters": info["outer_iters"], "restarts": info["restarts"],
-                     "true_rel_residual_gpu": info["true_rel_residual"], "true_rel_residual_oracle": r / bn}
+                     "true_rel_residual_gpu": info["true_rel_residual"], "true_rel_residual_oracle": r / bn,
+                     "threads_per_block": info["block_size"], "xcd_chunk_tiles": lat.xcd_chunk(ip),
+                     "waves_per_cu_cap": {"mult": lat.wave_cap(ip), "dhat": lat.wave_cap(ip, dhat=True)}}
         log(name, json.dumps(res[name]))
         del x
     lat.set_link_recon(12)
