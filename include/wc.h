@@ -47,6 +47,11 @@
  * the null stream).  wc_apply_* calls are asynchronous on that stream.
  * wc_solve and wc_solve_batch return after the solve has finished.
  *
+ * Devices: a lattice lives on the HIP device that is current when it is
+ * created, and every later call on it must be made with that device
+ * current; the library never switches devices.  Lattices given to one
+ * wc_solve_multi call must live on the same device.
+ *
  * Errors: every int-returning call returns WC_OK (0) or a negative wc_status.
  * Arguments are checked on the host before any GPU work (WC_EINVAL).  The
  * text of the last error of the calling thread is wc_last_error().  A

@@ -801,17 +801,17 @@ static void tune_store(const std::string &key, int bs, int chunk, const int caps
 // Time the inner loop's stencil pair (F_oo^-1 H_oe into the odd parity, then
 // the D-hat half with its fused dot) on zero vectors at each block size and
 // XCD chunk, and keep the fastest.  The default shape (256 threads, chunk
-// kDefaultChunk) is displaced only by a shape at least 3% faster, in the sweep
-// and again in three alternating timings against it, so that timing noise
-// does not flip the choice on large lattices.  A pinned chunk
-// is the only one timed.  Then, unless the caller pinned a wave cap, the two
-// kernels are timed on their own at the chosen shape under caps of 0, 8 and
-// 12 waves per CU, and each keeps the cap that beats the precision's default
-// by 3%, again confirmed by alternating timings.  With a cache file set, a stored result for the same device,
-// lattice, precision, link form and pinned cap is taken instead of timing.
-// A pinned block size or chunk bypasses the file both ways: a stored shape was
-// chosen over every size and chunk, and a constrained choice must not be
-// handed to a later, unconstrained tuning.
+// kDefaultChunk) is displaced only by a shape at least 3% faster, in the
+// sweep and again in three alternating timings against it, so that timing
+// noise does not flip the choice on large lattices.  A pinned chunk is the
+// only one timed.  Then, unless the caller pinned a wave cap, the two kernels
+// are timed on their own at the chosen shape under caps of 0, 8 and 12 waves
+// per CU, and each keeps the cap that beats the precision's default by 3%,
+// again confirmed by alternating timings.  With a cache file set, a stored
+// result for the same device, lattice, precision, link form and pinned cap
+// is taken instead of timing.  A pinned block size or chunk bypasses the file
+// both ways: a stored shape was chosen over every size and chunk, and a
+// constrained choice must not be handed to a later, unconstrained tuning.
 int tune_block_size(wc_lattice *lat, int prec, double us[3], int *chosen) {
     if (!lat->have_links || !lat->have_clover)
         return wc_fail(WC_ENOTREADY, "block-size tuning needs links and clover");
