@@ -87,6 +87,12 @@ MUTANTS = {
     "residual_sign_of_D_x": ("c", "cplx d = b[n * 12 + i] - (a - kappa * h[i]);", "cplx d = b[n * 12 + i] + (a - kappa * h[i]);"),
     "residual_hop_sign": ("c", "cplx d = b[n * 12 + i] - (a - kappa * h[i]);", "cplx d = b[n * 12 + i] - (a + kappa * h[i]);"),
     "fp16_scale_per_spin": ("py", "sites = re.reshape(re.shape[:-3] + (24,))", "sites = re.reshape(re.shape[:-2] + (6,))"),
+    "fp16_decode_without_scale": ("py", "dec = (h.astype(np.float32) * s).astype(np.float32).reshape(re.shape)",
+                                  "dec = h.astype(np.float32).reshape(re.shape)"),
+    "fp16_scale_from_sum": ("py", "s = np.abs(sites).max(axis=-1, keepdims=True).astype(np.float32)",
+                            "s = np.abs(sites).sum(axis=-1, keepdims=True).astype(np.float32)"),
+    "fp32_storage_not_rounded": ("py", "return np.asarray(psi, dtype=np.complex128).astype(np.complex64).astype(np.complex128)",
+                                 "return np.asarray(psi, dtype=np.complex128).astype(np.complex128)"),
 }
 
 
