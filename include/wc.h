@@ -343,7 +343,10 @@ int wc_apply_Dee_oo_batch(wc_lattice *lat, int n, void *const *out_e, const void
    call on one GPU shares that GPU's array: calls that overlap in time on one
    GPU (other streams, other host threads) race and must be ordered by the
    caller; each call overwrites the whole part of the array it reads.
-   Asynchronous on the lattice's stream. */
+   Asynchronous on the lattice's stream.  With event timing on
+   (wc_set_timing) its launches are timed like any other, with HIP events
+   created for them; leave timing off (the default) where no runtime object
+   may be created. */
 int wc_apply_Dee_oo_noalloc(wc_lattice *lat, void *out_e, const void *in_e, int prec);
 size_t wc_noalloc_scratch_bytes(void);
 
