@@ -145,6 +145,17 @@ def _ptr(t: torch.Tensor):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _require(cond: bool, what: str):
+    # argument checks that stay on under python -O (the C ABI takes bare
+    # pointers, so a wrong size here would become an access out of bounds)
+    if not cond:
+        raise ValueError(what)
+
+
+def _nbytes(t: torch.Tensor) -> int:
+    return t.numel() * t.element_size()
+
+
 # every open lattice, so that all of them are destroyed while the HIP runtime
 # is still fully up: interpreter exit runs these atexit hooks before tearing
 # down modules, whereas a lattice left to garbage collection at the very end
@@ -198,9 +209,25 @@ class Lattice:
         except Exception:
             pass
 
+    def _canonical(self, t, name: str, shape=None):
+        """t must be a complex128 tensor of the canonical spinor (or given) shape."""
+        shape = self.spinor_shape if shape is None else shape
+        _require(isinstance(t, torch.Tensor) and t.dtype == torch.complex128 and tuple(t.shape) == shape,
+                 "%s must be a complex128 tensor of shape %s" % (name, shape))
+
+    def _eo(self, t, prec, parities: int, name: str):
+        """t must hold at least `parities` EO parities in precision prec (any dtype:
+        EO fields are raw buffers).  An invalid precision is left to the library,
+        which refuses it."""
+        p = _prec(prec)
+        if p in (FP64, FP32, FP16):
+            need = parities * self.spinor_bytes(p)
+            _require(isinstance(t, torch.Tensor) and _nbytes(t) >= need,
+                     "%s must hold at least %d bytes (%d parity field(s) in precision %d)" % (name, need, parities, p))
+
     # ---- set-up -------------------------------------------------------------
     def load_links(self, U: torch.Tensor):
-        assert U.dtype == torch.complex128 and tuple(U.shape) == self.link_shape
+        self._canonical(U, "U", self.link_shape)
         self._sync_stream()
         _check(self.lib.wc_load_links(self.h, _ptr(U)))
         self._links_key = None
@@ -285,14 +312,14 @@ class Lattice:
         return torch.zeros(parities * self.spinor_bytes(prec), dtype=torch.uint8, device=self.device)
 
     def pack(self, psi: torch.Tensor, prec) -> torch.Tensor:
-        assert psi.dtype == torch.complex128 and tuple(psi.shape) == self.spinor_shape
+        self._canonical(psi, "psi")
         out = self.new_eo(prec, 2)
         self._sync_stream()
         _check(self.lib.wc_pack_spinor(self.h, _ptr(out), _ptr(psi), _prec(prec)))
         return out
 
     def unpack(self, eo: torch.Tensor, prec) -> torch.Tensor:
-        assert eo.numel() == 2 * self.spinor_bytes(prec)
+        self._eo(eo, prec, 2, "eo")
         out = torch.empty(self.spinor_shape, dtype=torch.complex128, device=self.device)
         self._sync_stream()
         _check(self.lib.wc_unpack_spinor(self.h, _ptr(out), _ptr(eo), _prec(prec)))
@@ -304,29 +331,38 @@ class Lattice:
 
     # ---- operators -------------------------------------------------------------
     def apply_D(self, psi: torch.Tensor, prec=FP64) -> torch.Tensor:
-        assert psi.dtype == torch.complex128 and tuple(psi.shape) == self.spinor_shape
+        self._canonical(psi, "psi")
         out = torch.empty_like(psi)
         self._sync_stream()
         _check(self.lib.wc_apply_D(self.h, _ptr(out), _ptr(psi), _prec(prec)))
         return out
 
     def apply_mult(self, out: torch.Tensor, inp: torch.Tensor, out_parity: int, prec):
+        self._eo(out, prec, 1, "out")
+        self._eo(inp, prec, 1, "inp")
         self._sync_stream()
         _check(self.lib.wc_apply_mult(self.h, _ptr(out), _ptr(inp), int(out_parity), _prec(prec)))
 
     def apply_Dee_oo(self, out_e: torch.Tensor, in_e: torch.Tensor, prec):
+        self._eo(out_e, prec, 1, "out_e")
+        self._eo(in_e, prec, 1, "in_e")
         self._sync_stream()
         _check(self.lib.wc_apply_Dee_oo(self.h, _ptr(out_e), _ptr(in_e), _prec(prec)))
 
     def apply_Dee_oo_noalloc(self, out_e: torch.Tensor, in_e: torch.Tensor, prec):
         """D-hat_ee with its intermediate in the library's fixed scratch array (no allocation)."""
+        self._eo(out_e, prec, 1, "out_e")
+        self._eo(in_e, prec, 1, "in_e")
         self._sync_stream()
         _check(self.lib.wc_apply_Dee_oo_noalloc(self.h, _ptr(out_e), _ptr(in_e), _prec(prec)))
 
     def apply_mult_batch(self, outs, ins, out_parity: int, prec):
         """outs[k] = MULT ins[k] for up to 16 single-parity EO fields, in one launch."""
         n = len(outs)
-        assert len(ins) == n
+        _require(len(ins) == n, "outs and ins must have the same length")
+        for k in range(n):
+            self._eo(outs[k], prec, 1, "outs[%d]" % k)
+            self._eo(ins[k], prec, 1, "ins[%d]" % k)
         O = (ctypes.c_void_p * n)(*[_ptr(t).value for t in outs])
         I_ = (ctypes.c_void_p * n)(*[_ptr(t).value for t in ins])
         self._sync_stream()
@@ -335,13 +371,18 @@ class Lattice:
     def apply_Dee_oo_batch(self, outs, ins, prec):
         """outs[k] = D-hat_ee ins[k] for up to 16 even-parity EO fields."""
         n = len(outs)
-        assert len(ins) == n
+        _require(len(ins) == n, "outs and ins must have the same length")
+        for k in range(n):
+            self._eo(outs[k], prec, 1, "outs[%d]" % k)
+            self._eo(ins[k], prec, 1, "ins[%d]" % k)
         O = (ctypes.c_void_p * n)(*[_ptr(t).value for t in outs])
         I_ = (ctypes.c_void_p * n)(*[_ptr(t).value for t in ins])
         self._sync_stream()
         _check(self.lib.wc_apply_Dee_oo_batch(self.h, n, O, I_, _prec(prec)))
 
     def apply_clover(self, out: torch.Tensor, inp: torch.Tensor, parity: int, inverse: bool, prec):
+        self._eo(out, prec, 1, "out")
+        self._eo(inp, prec, 1, "inp")
         self._sync_stream()
         _check(self.lib.wc_apply_clover(self.h, _ptr(out), _ptr(inp), int(parity), int(bool(inverse)),
                                         _prec(prec)))
@@ -367,7 +408,9 @@ class Lattice:
     def solve(self, b: torch.Tensor, kappa: float, csw: float, tol: float, x0: torch.Tensor = None,
               raise_on_error: bool = True, **params):
         """x = D^-1 b; returns (x, info dict).  params go into wc_solve_params."""
-        assert b.dtype == torch.complex128 and tuple(b.shape) == self.spinor_shape
+        self._canonical(b, "b")
+        if x0 is not None:
+            self._canonical(x0, "x0")
         p = self.default_params(**params)
         info = SolveInfo()
         x = torch.empty_like(b) if x0 is None else x0.clone()
@@ -383,8 +426,8 @@ class Lattice:
     def solve_batch(self, bs, kappa: float, csw: float, tol: float, raise_on_error: bool = True, **params):
         """Solve D x_k = b_k for up to 16 sources together; returns ([x_k], [info_k])."""
         n = len(bs)
-        for b in bs:
-            assert b.dtype == torch.complex128 and tuple(b.shape) == self.spinor_shape
+        for k, b in enumerate(bs):
+            self._canonical(b, "bs[%d]" % k)
         xs = [torch.empty_like(b) for b in bs]
         p = self.default_params(**params)
         infos = (SolveInfo * n)()
@@ -399,8 +442,8 @@ class Lattice:
     def link_grad(self, lam: torch.Tensor, x: torch.Tensor, kappa: float, csw: float,
                   include_clover: bool = True) -> torch.Tensor:
         """Gradient of -Re<lam, D[U] x> with respect to the loaded links (torch convention)."""
-        assert lam.dtype == torch.complex128 and tuple(lam.shape) == self.spinor_shape
-        assert x.dtype == torch.complex128 and tuple(x.shape) == self.spinor_shape
+        self._canonical(lam, "lam")
+        self._canonical(x, "x")
         G = torch.empty(self.link_shape, dtype=torch.complex128, device=self.device)
         self._sync_stream()
         _check(self.lib.wc_link_grad(self.h, _ptr(lam), _ptr(x), float(kappa), float(csw),
@@ -444,6 +487,10 @@ def solve_multi(lats, bs, kappas, csws, tol: float, raise_on_error: bool = True,
     """Solve D_k x_k = b_k on lattices lats[k] (sizes may differ) together, on
     lats[0]'s stream; returns ([x_k], [info_k])."""
     n = len(lats)
+    _require(len(bs) == n and len(kappas) == n and len(csws) == n,
+             "lats, bs, kappas and csws must have the same length")
+    for k in range(n):
+        lats[k]._canonical(bs[k], "bs[%d]" % k)
     lib = load_library()
     xs = [torch.empty_like(b) for b in bs]
     p = Lattice.default_params(**params)
